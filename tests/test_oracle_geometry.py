@@ -1,0 +1,142 @@
+"""Pins of the oracle's mesh, RWG, grouping and angular grid (CPU only)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from synth import workloads as W
+from oracle import geometry as geo
+
+
+@pytest.mark.parametrize("f", [1, 2, 3, 8])
+def test_icosphere_counts_and_euler(f):
+    v, t = synth.icosphere(f, 1.0)
+    assert v.shape == (10 * f * f + 2, 3)
+    assert t.shape == (20 * f * f, 3)
+    b = geo.rwg(v, t)
+    ne = b["edge"].shape[0]
+    assert ne == 30 * f * f == 3 * t.shape[0] // 2
+    assert v.shape[0] - ne + t.shape[0] == 2
+    assert np.allclose(np.linalg.norm(v, axis=1), 1.0, atol=1e-15)
+    assert np.unique(t).size == v.shape[0]
+
+
+def test_small_mesh_is_the_1280_triangle_sphere():
+    v, t = synth.icosphere(W.SMALL.freq, W.SMALL.radius)
+    assert (v.shape[0], t.shape[0]) == (642, 1280)
+    assert geo.rwg(v, t)["edge"].shape[0] == 1920
+
+
+def test_orientation_outward_and_volume_converges():
+    prev = None
+    for f in (4, 8, 16):
+        v, t = synth.icosphere(f, 1.0)
+        a, b, c = v[t[:, 0]], v[t[:, 1]], v[t[:, 2]]
+        n = np.cross(b - a, c - a)
+        assert np.all(np.einsum("ij,ij->i", n, a + b + c) > 0)
+        vol = np.sum(np.einsum("ij,ij->i", a, np.cross(b, c))) / 6.0
+        err = abs(vol - 4.0 / 3.0 * math.pi)
+        if prev is not None:
+            assert err < prev / 3.0          # second-order convergence (4x per halving)
+        prev = err
+    area = geo.triangle_areas(*synth.icosphere(64, 1.0)).sum()
+    assert abs(area - 4 * math.pi) / (4 * math.pi) < 1e-3
+
+
+def test_rwg_orientation_rule():
+    v, t = synth.icosphere(3, 1.0)
+    b = geo.rwg(v, t)
+    for n in range(b["edge"].shape[0]):
+        a_, b_ = b["edge"][n]
+        assert a_ < b_
+        tp, tm = t[b["tri_p"][n]], t[b["tri_m"][n]]
+        # T+ traverses a -> b, T- traverses b -> a
+        cyc_p = [(tp[i], tp[(i + 1) % 3]) for i in range(3)]
+        cyc_m = [(tm[i], tm[(i + 1) % 3]) for i in range(3)]
+        assert (a_, b_) in cyc_p and (b_, a_) in cyc_m
+        assert b["free_p"][n] not in (a_, b_) and b["free_p"][n] in tp
+        assert b["free_m"][n] not in (a_, b_) and b["free_m"][n] in tm
+        assert np.isclose(b["length"][n], np.linalg.norm(v[b_] - v[a_]))
+
+
+def test_rwg_rejects_open_or_misoriented_mesh():
+    v, t = synth.icosphere(2, 1.0)
+    with pytest.raises(ValueError):
+        geo.rwg(v, t[:-1])
+    bad = t.copy()
+    bad[0] = bad[0][[0, 2, 1]]
+    with pytest.raises(ValueError):
+        geo.rwg(v, bad)
+
+
+def test_grouping_small_workload():
+    w = W.SMALL
+    v, t = synth.icosphere(w.freq, w.radius)
+    P = geo.Problem(v, t, w.origin, w.box, w.boxes_per_axis, w.n_theta, w.n_phi)
+    assert P.n_groups == 8
+    assert P.n_basis == 1920
+    # every basis midpoint lies in its group's box
+    e = P.rwg["edge"]
+    mid = 0.5 * (P.verts[e[:, 0]] + P.verts[e[:, 1]])
+    c = P.centers[P.group_of_basis()]
+    assert np.all(np.abs(mid - c) <= 0.5 * w.box + 1e-12)
+    # group order is increasing linear box index
+    lin = (P.box_index[:, 0] * 2 + P.box_index[:, 1]) * 2 + P.box_index[:, 2]
+    assert np.all(np.diff(lin) > 0)
+
+
+@pytest.mark.slow
+def test_sphere_average_group_size_matches_paper(golden_dir):
+    """Average basis functions per box on the 30-lambda sphere (Section III.B)."""
+    ref = json.load(open(os.path.join(golden_dir, "paper_sphere_navg.json")))
+    v, t = synth.icosphere(W.SPHERE30.freq, W.SPHERE30.radius)
+    edges = geo.rwg(v, t)["edge"]
+    assert edges.shape[0] == 939870
+    for box, navg in ref["box_lambda_to_navg"].items():
+        a = float(box)
+        K = int(math.ceil(30.0 / a - 1e-12))
+        _, off, _, _ = geo.group_basis(v, edges, (-15.0, -15.0, -15.0), a, K)
+        got = edges.shape[0] / (off.size - 1)
+        assert abs(got - navg) / navg < 0.01, (box, got, navg)
+
+
+def test_grid_order_reproduces_table_iv(golden_dir):
+    ref = json.load(open(os.path.join(golden_dir, "paper_grid_order.json")))
+    for box, L in ref["box_lambda_to_L"].items():
+        assert geo.grid_order(float(box), ref["digits"]) == L
+
+
+def test_workload_grids_follow_the_rule():
+    for w in [W.SPHERE30, W.SPHERE6, W.SPHERE45, *W.SPHERE20.values()]:
+        L = geo.grid_order(w.box, 5)
+        assert (w.n_theta, w.n_phi) == (L + 1, 2 * L + 1), w.name
+
+
+def test_dense_memory_formula_matches_tables(golden_dir):
+    """Tables I/III: N * (L+1)(2L+1) * 2 polarisations * 16 B, in 2^20-byte MB."""
+    ref = json.load(open(os.path.join(golden_dir, "paper_dense_memory.json")))
+    for case in ref["cases"]:
+        L = case["L"]
+        mb = case["n_basis"] * (L + 1) * (2 * L + 1) * 2 * 16 / 2 ** 20
+        assert abs(mb - case["memory_MB"]) < 1.0
+
+
+@pytest.mark.parametrize("n", [3, 14, 38])
+def test_angular_grid(n):
+    theta, phi, k, th, ph = geo.angular_grid(n, 2 * n - 1)
+    assert np.all(np.diff(theta) > 0) and 0 < theta[0] and theta[-1] < math.pi
+    w = geo.gauss_legendre_weights(n)
+    assert abs(w.sum() - 2.0) < 1e-14
+    x = np.cos(theta)
+    for deg in range(2 * n):   # exact for polynomials of degree <= 2n - 1
+        exact = 0.0 if deg % 2 else 2.0 / (deg + 1)
+        assert abs(np.sum(w * x ** deg) - exact) < 1e-13
+    for a, b in [(k, th), (k, ph), (th, ph)]:
+        assert np.allclose(np.einsum("ij,ij->i", a, b), 0.0, atol=1e-15)
+    for a in (k, th, ph):
+        assert np.allclose(np.linalg.norm(a, axis=1), 1.0, atol=1e-15)
+    # right-handed triad: theta_hat x phi_hat = k_hat
+    assert np.allclose(np.cross(th, ph), k, atol=1e-15)
