@@ -1,0 +1,227 @@
+/*
+ * tuckfmm.h -- C ABI of an MI355X (gfx950) library for the aggregation and
+ * disaggregation stages of the fast multipole method computed directly in Tucker
+ * format, after C. Qian, M. Wang, A. C. Yucel, "Compression of Far-Fields in the
+ * Fast Multipole Method via Tucker Decomposition" (arXiv 2103.05822).
+ *
+ * Notation (paper, Section II): a group is a non-empty FMM box B_v holding n_beta
+ * RWG basis functions; the far-field (aggregation) matrix of a group and
+ * polarisation alpha in {theta, phi} is A^alpha (N_dir x n_beta) with entries
+ * P^{alpha,+}_{n,i} of eq. (4); N_dir = n_theta * n_phi plane-wave directions.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Complex numbers are interleaved (re, im).  "complex128" = two doubles,
+ *    "complex64" = two floats.
+ *  - Basis functions are numbered in group order: group g owns rows
+ *    offsets[g] .. offsets[g+1]-1.  Direction index i = i_theta * n_phi + i_phi.
+ *  - Dense far-field:  [N][2][n_theta][n_phi]   (polarisation 0 = theta, 1 = phi).
+ *  - Vectors carry the right-hand-side index innermost:
+ *        x, V : [N][nrhs]          F, G : [n_groups][2][N_dir][nrhs].
+ *  - Tucker factors exchanged through the ABI use the paper's shapes, row-major:
+ *        core [r_theta][r_phi][r_beta], U^theta [n_theta][r_theta],
+ *        U^phi [n_phi][r_phi], U^beta [n_beta][r_beta]            (eq. (6)).
+ *  - "device" pointers are HIP device memory of the current device, owned by the
+ *    caller; "host" pointers are ordinary host memory, owned by the caller.
+ *  - Compute calls are asynchronous on the given stream (a hipStream_t passed as
+ *    void*, NULL = default stream).  Outputs are overwritten, never accumulated.
+ *  - Every call validates its arguments on the host before launching anything;
+ *    on failure it returns a negative fmm_status and fmm_last_error() describes
+ *    the problem.  Kernel faults surface as FMM_ERR_DEVICE at a later call.
+ *    No call throws or aborts.
+ */
+#ifndef TUCKFMM_H
+#define TUCKFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FMM_OK = 0,
+  FMM_ERR_ARG = -1,          /* null pointer, bad enum, value out of range      */
+  FMM_ERR_SHAPE = -2,        /* inconsistent sizes, ranks or offsets             */
+  FMM_ERR_SIZE = -3,         /* caller buffer too small                          */
+  FMM_ERR_DEVICE = -4,       /* no usable GPU, or a HIP runtime error            */
+  FMM_ERR_NUMERIC = -5,      /* NaN/Inf input or eigensolver failure             */
+  FMM_ERR_UNSUPPORTED = -6,  /* precision or shape not supported by this build   */
+  FMM_ERR_STATE = -7         /* call order violated (e.g. compute before upload) */
+} fmm_status;
+
+/* Storage / arithmetic precision of a compute path.
+ *   FMM_C128   complex128 storage, FP64 arithmetic; x, F, G, V are complex128.
+ *   FMM_C64    complex64 storage,  FP32 arithmetic; x, F, G, V are complex64.
+ *   FMM_BF16X2 factors stored as bf16 hi + lo pairs (same 8 bytes per complex as
+ *              complex64) for the matrix-core path, FP32 accumulation; x, F, G, V
+ *              are complex64.
+ *   FMM_BF16X3 as FMM_BF16X2 with a third (hi, mid, lo) term.                   */
+typedef enum { FMM_C128 = 0, FMM_C64 = 1, FMM_BF16X2 = 2, FMM_BF16X3 = 3 } fmm_prec;
+
+/* Problem layout shared by every group-wise call. */
+typedef struct {
+  int32_t n_theta;           /* n_theta = L + 1 angular samples in theta (Section II.A) */
+  int32_t n_phi;             /* n_phi samples in phi (2L + 1 in the paper)              */
+  int32_t n_groups;          /* number of non-empty boxes                               */
+  int32_t reserved;          /* must be 0                                               */
+  const int64_t* offsets;    /* host, n_groups + 1 entries, offsets[0] = 0, increasing  */
+} fmm_layout;
+
+typedef struct fmm_geometry_s* fmm_geometry_t;   /* mesh, RWG basis, groups, grid   */
+typedef struct fmm_tucker_s* fmm_tucker_t;       /* Tucker-compressed far-fields     */
+typedef struct fmm_dense_s* fmm_dense_t;         /* plan of the dense (plain) method */
+
+/* ------------------------------------------------------------------ status */
+
+/* Message of the last failing call on this thread ("" if none).  The pointer stays
+ * valid until the next library call on the same thread. */
+const char* fmm_last_error(void);
+
+/* Library version string, e.g. "tuckfmm 0.1 gfx950". */
+const char* fmm_version(void);
+
+/* Number of usable HIP devices (0 when no GPU is present).  Never fails. */
+int32_t fmm_device_count(void);
+
+/* ---------------------------------------------------------------- geometry */
+
+/* RWG basis functions (Section II.A, the basis of ref. [20]) and FMM groups
+ * (Section II.A, the box partition of FMM-FFT) of a closed triangle mesh.  Host only.
+ *   verts  host [n_verts][3] double      vertex coordinates (wavelengths)
+ *   tris   host [n_tris][3] int32        triangles, counter-clockwise seen from the
+ *                                        side the normal points to
+ *   origin host [3] double, box > 0, boxes_per_axis >= 1: the cubic box grid;
+ *          a basis function belongs to the box holding its edge midpoint,
+ *          floor((m - origin) / box) clamped to [0, K-1]; groups are the non-empty
+ *          boxes in increasing (ix * K + iy) * K + iz order.
+ *   wavenumber k > 0; n_theta >= 1, n_phi >= 1: the angular grid used by
+ *          fmm_farfield_fill (Gauss-Legendre nodes in cos(theta), increasing theta;
+ *          phi_j = 2 pi j / n_phi).
+ * Every edge must be shared by exactly two triangles traversing it in opposite
+ * directions (FMM_ERR_SHAPE otherwise).  For an edge (a, b), a < b, T+ is the
+ * triangle traversing a -> b; basis functions are first ordered by (a, b), then
+ * stably by group.  The handle copies everything it needs. */
+fmm_status fmm_geometry_build(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                              const double* origin, double box, int32_t boxes_per_axis,
+                              double wavenumber, int32_t n_theta, int32_t n_phi,
+                              fmm_geometry_t* out);
+
+/* Sizes of a geometry: number of basis functions N and of groups. */
+fmm_status fmm_geometry_info(fmm_geometry_t geom, int64_t* n_basis, int32_t* n_groups);
+
+/* Copies of the geometry's tables into caller host buffers (any may be NULL):
+ *   offsets [n_groups+1] int64, perm [N] int64 (edge number of each group-ordered
+ *   basis function), centers [n_groups][3] double (box centres r_v of eq. (4)),
+ *   theta [n_theta] double, phi [n_phi] double. */
+fmm_status fmm_geometry_tables(fmm_geometry_t geom, int64_t* offsets, int64_t* perm, double* centers,
+                               double* theta, double* phi);
+
+/* A layout view of the geometry (offsets pointer owned by the geometry). */
+fmm_status fmm_geometry_layout(fmm_geometry_t geom, fmm_layout* out);
+
+/* Dense far-fields P^{alpha,+} of eq. (4) for groups first_group ..
+ * first_group+count-1, on the device, FP64:
+ *   farfield device complex128 [rows][2][n_theta][n_phi], rows = the groups' basis
+ *   functions, starting at row offsets[first_group].
+ * Each triangle integral uses the symmetric 3-point rule (barycentric
+ * (2/3, 1/6, 1/6), weights A/3); the projector (I - k k) drops out because
+ * alpha_hat is orthogonal to k.  Uploads the geometry to the device on first use. */
+fmm_status fmm_farfield_fill(fmm_geometry_t geom, int32_t first_group, int32_t count,
+                             void* farfield, void* stream);
+
+void fmm_geometry_destroy(fmm_geometry_t geom);
+
+/* ------------------------------------------------------------------ Tucker */
+
+/* Empty Tucker handle for a layout (host only).  Groups are filled by
+ * fmm_farfield_compress or fmm_tucker_set_group. */
+fmm_status fmm_tucker_create(const fmm_layout* layout, fmm_tucker_t* out);
+
+/* Setup: truncated HOSVD (Section II.B, eq. (6)) of the dense far-fields of groups
+ * first_group .. first_group+count-1, one decomposition per group and polarisation.
+ *   farfield device complex128 [rows][2][n_theta][n_phi], starting at row
+ *            offsets[first_group] (so a caller can stream group chunks).
+ *   gamma    tolerance, 0 <= gamma < 1.  Each mode keeps the smallest rank r with
+ *            sqrt(sum_{i>=r} s_i^2) <= gamma/sqrt(3) * ||A||_F (gamma = 0: full rank),
+ *            so that ||A - A_hat||_F <= gamma ||A||_F.
+ * FP64 throughout: the left singular vectors of each mode unfolding come from the
+ * Hermitian eigendecomposition of the unfolding's Gram matrix (s_i^2 = eigenvalues),
+ * the core is A x_1 U^theta* x_2 U^phi* x_3 U^beta*.  If *inout is NULL a handle is
+ * created for the layout, else groups are added to it.  Synchronises the stream. */
+fmm_status fmm_farfield_compress(const fmm_layout* layout, const void* farfield, int32_t first_group,
+                                 int32_t count, double gamma, void* stream, fmm_tucker_t* inout);
+
+/* Set the factors of one (group, polarisation) from host complex128 arrays in the
+ * paper's shapes (see the conventions above).  1 <= r_theta <= n_theta,
+ * 1 <= r_phi <= n_phi, 1 <= r_beta <= n_beta.  Copies the data. */
+fmm_status fmm_tucker_set_group(fmm_tucker_t h, int32_t group, int32_t alpha, int32_t r_theta,
+                                int32_t r_phi, int32_t r_beta, const double* core, const double* u_theta,
+                                const double* u_phi, const double* u_beta);
+
+/* Ranks of every tensor: host int32 [n_groups][2][3] = (r_theta, r_phi, r_beta). */
+fmm_status fmm_tucker_ranks(fmm_tucker_t h, int32_t* ranks);
+
+/* Copy the FP64 factors of one (group, polarisation) into host complex128 buffers in
+ * the paper's shapes (sizes from fmm_tucker_ranks). */
+fmm_status fmm_tucker_export(fmm_tucker_t h, int32_t group, int32_t alpha, double* core,
+                             double* u_theta, double* u_phi, double* u_beta);
+
+/* Bytes of stored factors (paper's memory measure, Section III: core + 3 factors of
+ * every tensor at the precision's element size), and bytes of the device arena the
+ * library needs for that precision (factors with row padding + descriptor tables). */
+fmm_status fmm_tucker_storage_bytes(fmm_tucker_t h, fmm_prec prec, size_t* factor_bytes, size_t* arena_bytes);
+
+/* Convert the FP64 factors to `prec` and copy them into the caller's device arena
+ * (at least arena_bytes from fmm_tucker_storage_bytes, 256-byte aligned).  The
+ * arena must stay allocated and unmodified while the precision is in use; a second
+ * upload of the same precision replaces the first.  Synchronises the stream. */
+fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* arena, size_t bytes, void* stream);
+
+/* Aggregation in Tucker format (Section II.C, Fig. 2(b)) for every group and both
+ * polarisations: F^alpha_g = A_hat^alpha_g x_g, A_hat the Tucker model of eq. (6).
+ *   x device [N][nrhs], F device [n_groups][2][N_dir][nrhs]; complex128 for
+ *   FMM_C128, complex64 otherwise.  Requires a prior upload of `prec`. */
+fmm_status fmm_tucker_aggregate(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F,
+                                void* stream);
+
+/* Disaggregation in Tucker format (Section II.C, Fig. 3(b)), summed over the two
+ * polarisations as in eq. (5): V_g = sum_alpha (A_hat^alpha_g)* G^alpha_g, with *
+ * the conjugate transpose.  G device [n_groups][2][N_dir][nrhs], V device [N][nrhs]. */
+fmm_status fmm_tucker_disaggregate(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* G, void* V,
+                                   void* stream);
+
+/* Capture one aggregation + disaggregation pass (aggregation of x into F, then
+ * disaggregation of G into V) into a HIP graph owned by the handle, replacing a
+ * previous capture.  Buffers must stay valid while the graph is used. */
+fmm_status fmm_graph_capture(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F,
+                             const void* G, void* V, void* stream);
+
+/* Launch the captured pass on `stream`. */
+fmm_status fmm_graph_launch(fmm_tucker_t h, void* stream);
+
+void fmm_tucker_destroy(fmm_tucker_t h);
+
+/* ------------------------------------------------------------------- dense */
+
+/* Plan of the plain method for a layout: uploads the group table to the current
+ * device. */
+fmm_status fmm_dense_create(const fmm_layout* layout, fmm_dense_t* out);
+
+/* Dense aggregation, eq. (3) / Fig. 2(a): F^alpha_g = A^alpha_g x_g.
+ *   farfield device [N][2][n_theta][n_phi] (complex128 for FMM_C128, complex64 for
+ *   FMM_C64; other precisions: FMM_ERR_UNSUPPORTED), x [N][nrhs], F as above. */
+fmm_status fmm_dense_aggregate(fmm_dense_t d, fmm_prec prec, const void* farfield, int32_t nrhs,
+                               const void* x, void* F, void* stream);
+
+/* Dense disaggregation, eq. (5) / Fig. 3(a): V_g = sum_alpha (A^alpha_g)* G^alpha_g. */
+fmm_status fmm_dense_disaggregate(fmm_dense_t d, fmm_prec prec, const void* farfield, int32_t nrhs,
+                                  const void* G, void* V, void* stream);
+
+void fmm_dense_destroy(fmm_dense_t d);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TUCKFMM_H */

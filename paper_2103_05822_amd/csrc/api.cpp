@@ -1,0 +1,565 @@
+// C ABI entry points: argument validation, handles, arena packing and kernel
+// dispatch for the Tucker and dense paths.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <thread>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace tuckfmm {
+
+namespace {
+thread_local std::string g_err;
+}
+
+fmm_status fail(fmm_status st, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+void clear_error() { g_err.clear(); }
+
+const char* last_error_cstr() { return g_err.c_str(); }
+
+bool have_device() {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    fail(FMM_ERR_DEVICE, "no HIP device available");
+    return false;
+  }
+  return true;
+}
+
+fmm_status copy_layout(const fmm_layout* in, Layout* out) {
+  if (!in) return fail(FMM_ERR_ARG, "layout is NULL");
+  if (in->reserved != 0) return fail(FMM_ERR_ARG, "layout.reserved must be 0");
+  if (in->n_theta < 1 || in->n_phi < 1 || (int64_t)in->n_theta * in->n_phi > (1 << 24))
+    return fail(FMM_ERR_SHAPE, "n_theta=%d n_phi=%d out of range", in->n_theta, in->n_phi);
+  if (in->n_groups < 0) return fail(FMM_ERR_SHAPE, "n_groups must be >= 0");
+  if (!in->offsets) return fail(FMM_ERR_ARG, "layout.offsets is NULL");
+  if (in->offsets[0] != 0) return fail(FMM_ERR_SHAPE, "offsets[0] must be 0");
+  for (int32_t g = 0; g < in->n_groups; ++g) {
+    const int64_t nb = in->offsets[g + 1] - in->offsets[g];
+    if (nb < 1) return fail(FMM_ERR_SHAPE, "group %d is empty or offsets decrease", g);
+    if (nb > (1 << 24)) return fail(FMM_ERR_SHAPE, "group %d has too many basis functions", g);
+  }
+  out->n_theta = in->n_theta;
+  out->n_phi = in->n_phi;
+  out->n_groups = in->n_groups;
+  out->offsets.assign(in->offsets, in->offsets + in->n_groups + 1);
+  return FMM_OK;
+}
+
+}  // namespace tuckfmm
+
+using namespace tuckfmm;
+
+namespace {
+
+size_t elem_bytes(fmm_prec p) { return p == FMM_C128 ? 16 : (p == FMM_BF16X3 ? 12 : 8); }
+int pack_elems(fmm_prec p) { return p == FMM_C128 ? 1 : 2; }
+bool prec_valid(int p) { return p >= FMM_C128 && p <= FMM_BF16X3; }
+bool prec_has_kernels(fmm_prec p) { return p == FMM_C128 || p == FMM_C64; }
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+bool aligned(const void* p, size_t a) { return reinterpret_cast<uintptr_t>(p) % a == 0; }
+
+// Device layout of one precision slot, computed identically for sizing and packing.
+struct ArenaPlan {
+  size_t header_bytes = 0, total_bytes = 0, factor_bytes_paper = 0;
+  std::vector<TuckItem> items;
+  std::vector<int32_t> agg_order, dis_order;
+  TuckMax mx{};
+};
+
+// Cost of streaming one tensor (bytes read), used for the work-list order.
+double item_cost(const TuckItem& it) {
+  return (double)it.rb * it.ld_ub + (double)it.rb * it.ld_c + 1e-3 * it.nb;
+}
+
+fmm_status plan_arena(const fmm_tucker_s* h, fmm_prec prec, ArenaPlan* P) {
+  const Layout& L = h->layout;
+  const int G = L.n_groups;
+  const size_t es = elem_bytes(prec);
+  const int E = pack_elems(prec);
+  const size_t blk_align = es == 12 ? 768 : 256;  // a multiple of both 256 bytes and the element size
+  P->items.resize((size_t)2 * G);
+  P->agg_order.resize((size_t)2 * G);
+  P->dis_order.resize((size_t)G);
+  P->header_bytes = align_up((size_t)2 * G * sizeof(TuckItem) + (size_t)3 * G * sizeof(int32_t), 256);
+  size_t off = 0;  // bytes inside the factor area
+  auto block = [&](size_t n_el) {
+    const size_t start = off;
+    off = align_up(off + n_el * es, blk_align);
+    return start;
+  };
+  TuckMax mx{};
+  for (int g = 0; g < G; ++g) {
+    for (int a = 0; a < 2; ++a) {
+      const TensorFactors& tf = h->t[2 * g + a];
+      if (!tf.set()) return fail(FMM_ERR_STATE, "factors of group %d polarisation %d are not set", g, a);
+      TuckItem it{};
+      it.nb = L.nb(g);
+      it.rt = tf.rt;
+      it.rp = tf.rp;
+      it.rb = tf.rb;
+      it.ld_ub = (it.nb + E - 1) / E * E;
+      it.ld_c = (it.rt * it.rp + E - 1) / E * E;
+      it.group = g;
+      it.alpha = a;
+      it.row0 = L.offsets[g];
+      // both orders of the two angular products; take the cheaper one
+      const double c_theta = (double)L.n_theta * it.rp * (it.rt + L.n_phi);
+      const double c_phi = (double)it.rt * L.n_phi * (it.rp + L.n_theta);
+      it.theta_first = c_theta <= c_phi ? 1 : 0;
+      it.off_ubt = (int64_t)(block((size_t)it.rb * it.ld_ub) / es);
+      it.off_core = (int64_t)(block((size_t)it.rb * it.ld_c) / es);
+      it.off_ut = (int64_t)(block((size_t)L.n_theta * it.rt) / es);
+      it.off_up = (int64_t)(block((size_t)L.n_phi * it.rp) / es);
+      it.off_upt = (int64_t)(block((size_t)L.n_phi * it.rp) / es);
+      P->items[2 * g + a] = it;
+      mx.nb = std::max(mx.nb, it.nb);
+      mx.rt = std::max(mx.rt, it.rt);
+      mx.rp = std::max(mx.rp, it.rp);
+      mx.rb = std::max(mx.rb, it.rb);
+      mx.q = std::max(mx.q, it.rt * it.rp);
+      mx.t3 = std::max(mx.t3, it.theta_first ? L.n_theta * it.rp : it.rt * L.n_phi);
+      P->factor_bytes_paper += es * ((size_t)it.rt * it.rp * it.rb + (size_t)L.n_theta * it.rt +
+                                     (size_t)L.n_phi * it.rp + (size_t)it.nb * it.rb);
+    }
+  }
+  P->mx = mx;
+  std::iota(P->agg_order.begin(), P->agg_order.end(), 0);
+  std::stable_sort(P->agg_order.begin(), P->agg_order.end(),
+                   [&](int32_t a, int32_t b) { return item_cost(P->items[a]) > item_cost(P->items[b]); });
+  std::iota(P->dis_order.begin(), P->dis_order.end(), 0);
+  std::stable_sort(P->dis_order.begin(), P->dis_order.end(), [&](int32_t a, int32_t b) {
+    return item_cost(P->items[2 * a]) + item_cost(P->items[2 * a + 1]) >
+           item_cost(P->items[2 * b]) + item_cost(P->items[2 * b + 1]);
+  });
+  P->total_bytes = P->header_bytes + off;
+  return FMM_OK;
+}
+
+template <typename S>
+void put(S* dst, const cd& v);
+template <>
+void put<double>(double* dst, const cd& v) {
+  dst[0] = v.real();
+  dst[1] = v.imag();
+}
+template <>
+void put<float>(float* dst, const cd& v) {
+  dst[0] = (float)v.real();
+  dst[1] = (float)v.imag();
+}
+
+template <typename S>
+void pack_tensor(const Layout& L, const TensorFactors& tf, const TuckItem& it, S* fac) {
+  const int nt = L.n_theta, np = L.n_phi;
+  S* ubt = fac + 2 * it.off_ubt;
+  for (int n = 0; n < it.nb; ++n)
+    for (int b = 0; b < it.rb; ++b) put<S>(ubt + 2 * ((size_t)b * it.ld_ub + n), tf.ub[(size_t)n * it.rb + b]);
+  S* core = fac + 2 * it.off_core;
+  for (int a = 0; a < it.rt; ++a)
+    for (int c = 0; c < it.rp; ++c)
+      for (int b = 0; b < it.rb; ++b)
+        put<S>(core + 2 * ((size_t)b * it.ld_c + a * it.rp + c), tf.core[((size_t)a * it.rp + c) * it.rb + b]);
+  S* ut = fac + 2 * it.off_ut;
+  for (size_t i = 0; i < (size_t)nt * it.rt; ++i) put<S>(ut + 2 * i, tf.ut[i]);
+  S* up = fac + 2 * it.off_up;
+  for (size_t i = 0; i < (size_t)np * it.rp; ++i) put<S>(up + 2 * i, tf.up[i]);
+  S* upt = fac + 2 * it.off_upt;
+  for (int j = 0; j < np; ++j)
+    for (int c = 0; c < it.rp; ++c) put<S>(upt + 2 * ((size_t)c * np + j), tf.up[(size_t)j * it.rp + c]);
+}
+
+fmm_status check_vec(const void* p, size_t align, const char* name) {
+  if (!p) return fail(FMM_ERR_ARG, "%s is NULL", name);
+  if (!aligned(p, align)) return fail(FMM_ERR_ARG, "%s must be %zu-byte aligned", name, align);
+  return FMM_OK;
+}
+
+fmm_status ready_slot(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, PrecSlot** out) {
+  if (!h) return fail(FMM_ERR_ARG, "handle is NULL");
+  if (!prec_valid(prec)) return fail(FMM_ERR_ARG, "bad precision %d", (int)prec);
+  if (nrhs < 1 || nrhs > 65535) return fail(FMM_ERR_ARG, "nrhs must be in [1, 65535]");
+  PrecSlot& s = h->slot[prec];
+  if (!s.ready) return fail(FMM_ERR_STATE, "precision %d has not been uploaded", (int)prec);
+  if (!prec_has_kernels(prec)) return fail(FMM_ERR_UNSUPPORTED, "precision %d has no single-RHS kernels", (int)prec);
+  if (!have_device()) return FMM_ERR_DEVICE;
+  int dev = 0;
+  TFMM_HIP(hipGetDevice(&dev));
+  if (dev != s.device) return fail(FMM_ERR_STATE, "current device %d differs from the arena's device %d", dev, s.device);
+  *out = &s;
+  return FMM_OK;
+}
+
+fmm_status lds_check(size_t bytes) {
+  int dev = 0;
+  TFMM_HIP(hipGetDevice(&dev));
+  int lim = 0;
+  TFMM_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  if (bytes > (size_t)lim)
+    return fail(FMM_ERR_UNSUPPORTED, "kernel needs %zu bytes of LDS, device allows %d", bytes, lim);
+  return FMM_OK;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------- misc
+
+extern "C" const char* fmm_last_error(void) { return tuckfmm::last_error_cstr(); }
+
+extern "C" const char* fmm_version(void) { return "tuckfmm 0.1 gfx950"; }
+
+extern "C" int32_t fmm_device_count(void) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
+}
+
+// --------------------------------------------------------------------- Tucker
+
+extern "C" fmm_status fmm_tucker_create(const fmm_layout* layout, fmm_tucker_t* out) {
+  clear_error();
+  if (!out) return fail(FMM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  auto* h = new fmm_tucker_s();
+  fmm_status st = copy_layout(layout, &h->layout);
+  if (st != FMM_OK) {
+    delete h;
+    return st;
+  }
+  h->t.resize((size_t)2 * h->layout.n_groups);
+  *out = h;
+  return FMM_OK;
+}
+
+extern "C" fmm_status fmm_tucker_set_group(fmm_tucker_t h, int32_t group, int32_t alpha, int32_t r_theta,
+                                           int32_t r_phi, int32_t r_beta, const double* core, const double* u_theta,
+                                           const double* u_phi, const double* u_beta) {
+  clear_error();
+  if (!h) return fail(FMM_ERR_ARG, "handle is NULL");
+  const Layout& L = h->layout;
+  if (group < 0 || group >= L.n_groups) return fail(FMM_ERR_ARG, "group %d out of range", group);
+  if (alpha != 0 && alpha != 1) return fail(FMM_ERR_ARG, "alpha must be 0 or 1");
+  const int nb = L.nb(group);
+  if (r_theta < 1 || r_theta > L.n_theta || r_phi < 1 || r_phi > L.n_phi || r_beta < 1 || r_beta > nb)
+    return fail(FMM_ERR_SHAPE, "ranks (%d, %d, %d) outside [1, (%d, %d, %d)]", r_theta, r_phi, r_beta, L.n_theta,
+                L.n_phi, nb);
+  if (!core || !u_theta || !u_phi || !u_beta) return fail(FMM_ERR_ARG, "factor pointers must be non-NULL");
+  TensorFactors tf;
+  tf.rt = r_theta;
+  tf.rp = r_phi;
+  tf.rb = r_beta;
+  auto take = [](const double* p, size_t n, std::vector<cd>& v) {
+    v.resize(n);
+    for (size_t i = 0; i < n; ++i) v[i] = cd(p[2 * i], p[2 * i + 1]);
+  };
+  take(core, (size_t)r_theta * r_phi * r_beta, tf.core);
+  take(u_theta, (size_t)L.n_theta * r_theta, tf.ut);
+  take(u_phi, (size_t)L.n_phi * r_phi, tf.up);
+  take(u_beta, (size_t)nb * r_beta, tf.ub);
+  for (auto* v : {&tf.core, &tf.ut, &tf.up, &tf.ub})
+    for (const cd& z : *v)
+      if (!std::isfinite(z.real()) || !std::isfinite(z.imag()))
+        return fail(FMM_ERR_NUMERIC, "non-finite factor entry in group %d polarisation %d", group, alpha);
+  h->t[2 * (size_t)group + alpha] = std::move(tf);
+  for (auto& s : h->slot) s.ready = false;  // uploads are stale now
+  return FMM_OK;
+}
+
+extern "C" fmm_status fmm_tucker_ranks(fmm_tucker_t h, int32_t* ranks) {
+  clear_error();
+  if (!h || !ranks) return fail(FMM_ERR_ARG, "handle and ranks must be non-NULL");
+  for (size_t i = 0; i < h->t.size(); ++i) {
+    ranks[3 * i + 0] = h->t[i].rt;
+    ranks[3 * i + 1] = h->t[i].rp;
+    ranks[3 * i + 2] = h->t[i].rb;
+  }
+  return FMM_OK;
+}
+
+extern "C" fmm_status fmm_tucker_export(fmm_tucker_t h, int32_t group, int32_t alpha, double* core,
+                                        double* u_theta, double* u_phi, double* u_beta) {
+  clear_error();
+  if (!h) return fail(FMM_ERR_ARG, "handle is NULL");
+  if (group < 0 || group >= h->layout.n_groups || (alpha != 0 && alpha != 1))
+    return fail(FMM_ERR_ARG, "group/alpha out of range");
+  const TensorFactors& tf = h->t[2 * (size_t)group + alpha];
+  if (!tf.set()) return fail(FMM_ERR_STATE, "factors of group %d polarisation %d are not set", group, alpha);
+  auto give = [](const std::vector<cd>& v, double* p) {
+    if (!p) return;
+    for (size_t i = 0; i < v.size(); ++i) {
+      p[2 * i] = v[i].real();
+      p[2 * i + 1] = v[i].imag();
+    }
+  };
+  give(tf.core, core);
+  give(tf.ut, u_theta);
+  give(tf.up, u_phi);
+  give(tf.ub, u_beta);
+  return FMM_OK;
+}
+
+extern "C" fmm_status fmm_tucker_storage_bytes(fmm_tucker_t h, fmm_prec prec, size_t* factor_bytes,
+                                               size_t* arena_bytes) {
+  clear_error();
+  if (!h) return fail(FMM_ERR_ARG, "handle is NULL");
+  if (!prec_valid(prec)) return fail(FMM_ERR_ARG, "bad precision %d", (int)prec);
+  ArenaPlan P;
+  fmm_status st = plan_arena(h, prec, &P);
+  if (st != FMM_OK) return st;
+  if (factor_bytes) *factor_bytes = P.factor_bytes_paper;
+  if (arena_bytes) *arena_bytes = P.total_bytes;
+  return FMM_OK;
+}
+
+extern "C" fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* arena, size_t bytes, void* stream) {
+  clear_error();
+  if (!h) return fail(FMM_ERR_ARG, "handle is NULL");
+  if (!prec_valid(prec)) return fail(FMM_ERR_ARG, "bad precision %d", (int)prec);
+  if (!prec_has_kernels(prec)) return fail(FMM_ERR_UNSUPPORTED, "precision %d is not available for upload", (int)prec);
+  fmm_status st = check_vec(arena, 256, "arena");
+  if (st != FMM_OK) return st;
+  ArenaPlan P;
+  st = plan_arena(h, prec, &P);
+  if (st != FMM_OK) return st;
+  if (bytes < P.total_bytes) return fail(FMM_ERR_SIZE, "arena has %zu bytes, needs %zu", bytes, P.total_bytes);
+  if (!have_device()) return FMM_ERR_DEVICE;
+  int dev = 0;
+  TFMM_HIP(hipGetDevice(&dev));
+
+  // host image of the whole arena
+  std::vector<char> img(P.total_bytes, 0);
+  std::memcpy(img.data(), P.items.data(), P.items.size() * sizeof(TuckItem));
+  char* p = img.data() + P.items.size() * sizeof(TuckItem);
+  std::memcpy(p, P.agg_order.data(), P.agg_order.size() * sizeof(int32_t));
+  p += P.agg_order.size() * sizeof(int32_t);
+  std::memcpy(p, P.dis_order.data(), P.dis_order.size() * sizeof(int32_t));
+  char* fac = img.data() + P.header_bytes;
+  const size_t n_t = P.items.size();
+  const unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (unsigned w = 0; w < nthreads; ++w)
+    pool.emplace_back([&, w]() {
+      for (size_t i = w; i < n_t; i += nthreads) {
+        if (prec == FMM_C128)
+          pack_tensor<double>(h->layout, h->t[i], P.items[i], reinterpret_cast<double*>(fac));
+        else
+          pack_tensor<float>(h->layout, h->t[i], P.items[i], reinterpret_cast<float*>(fac));
+      }
+    });
+  for (auto& th : pool) th.join();
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  TFMM_HIP(hipMemcpyAsync(arena, img.data(), img.size(), hipMemcpyHostToDevice, s));
+  TFMM_HIP(hipStreamSynchronize(s));
+
+  PrecSlot& sl = h->slot[prec];
+  sl.ready = true;
+  sl.arena = static_cast<char*>(arena);
+  sl.bytes = bytes;
+  sl.device = dev;
+  sl.items = reinterpret_cast<const TuckItem*>(sl.arena);
+  sl.agg_order = reinterpret_cast<const int32_t*>(sl.arena + P.items.size() * sizeof(TuckItem));
+  sl.dis_order = sl.agg_order + P.agg_order.size();
+  sl.factors = sl.arena + P.header_bytes;
+  sl.mx = P.mx;
+  return FMM_OK;
+}
+
+extern "C" fmm_status fmm_tucker_aggregate(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F,
+                                           void* stream) {
+  clear_error();
+  PrecSlot* s = nullptr;
+  fmm_status st = ready_slot(h, prec, nrhs, &s);
+  if (st != FMM_OK) return st;
+  const size_t es = elem_bytes(prec);
+  if ((st = check_vec(x, es, "x")) != FMM_OK || (st = check_vec(F, es, "F")) != FMM_OK) return st;
+  const Layout& L = h->layout;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (prec == FMM_C128) {
+    if ((st = lds_check(tucker_agg_lds_bytes<double>(s->mx))) != FMM_OK) return st;
+    TFMM_HIP(launch_tucker_agg<double>(s->factors, s->items, s->agg_order, 2 * L.n_groups, s->mx, L.n_theta,
+                                       L.n_phi, nrhs, x, F, hs));
+  } else {
+    if ((st = lds_check(tucker_agg_lds_bytes<float>(s->mx))) != FMM_OK) return st;
+    TFMM_HIP(launch_tucker_agg<float>(s->factors, s->items, s->agg_order, 2 * L.n_groups, s->mx, L.n_theta,
+                                      L.n_phi, nrhs, x, F, hs));
+  }
+  return FMM_OK;
+}
+
+extern "C" fmm_status fmm_tucker_disaggregate(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* G, void* V,
+                                              void* stream) {
+  clear_error();
+  PrecSlot* s = nullptr;
+  fmm_status st = ready_slot(h, prec, nrhs, &s);
+  if (st != FMM_OK) return st;
+  const size_t es = elem_bytes(prec);
+  if ((st = check_vec(G, es, "G")) != FMM_OK || (st = check_vec(V, es, "V")) != FMM_OK) return st;
+  const Layout& L = h->layout;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (prec == FMM_C128) {
+    if ((st = lds_check(tucker_disagg_lds_bytes<double>(s->mx))) != FMM_OK) return st;
+    TFMM_HIP(launch_tucker_disagg<double>(s->factors, s->items, s->dis_order, L.n_groups, s->mx, L.n_theta,
+                                          L.n_phi, nrhs, G, V, hs));
+  } else {
+    if ((st = lds_check(tucker_disagg_lds_bytes<float>(s->mx))) != FMM_OK) return st;
+    TFMM_HIP(launch_tucker_disagg<float>(s->factors, s->items, s->dis_order, L.n_groups, s->mx, L.n_theta,
+                                         L.n_phi, nrhs, G, V, hs));
+  }
+  return FMM_OK;
+}
+
+extern "C" fmm_status fmm_graph_capture(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F,
+                                        const void* G, void* V, void* stream) {
+  clear_error();
+  PrecSlot* s = nullptr;
+  fmm_status st = ready_slot(h, prec, nrhs, &s);
+  if (st != FMM_OK) return st;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (hs == nullptr) return fail(FMM_ERR_ARG, "graph capture needs a non-default stream");
+  if (h->graph_exec) {
+    (void)hipGraphExecDestroy(h->graph_exec);
+    h->graph_exec = nullptr;
+  }
+  if (h->graph) {
+    (void)hipGraphDestroy(h->graph);
+    h->graph = nullptr;
+  }
+  TFMM_HIP(hipStreamBeginCapture(hs, hipStreamCaptureModeThreadLocal));
+  fmm_status a = fmm_tucker_aggregate(h, prec, nrhs, x, F, stream);
+  fmm_status d = a == FMM_OK ? fmm_tucker_disaggregate(h, prec, nrhs, G, V, stream) : a;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(hs, &graph);
+  if (d != FMM_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return d;
+  }
+  if (e != hipSuccess) return fail(FMM_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  h->graph = graph;
+  TFMM_HIP(hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0));
+  return FMM_OK;
+}
+
+extern "C" fmm_status fmm_graph_launch(fmm_tucker_t h, void* stream) {
+  clear_error();
+  if (!h) return fail(FMM_ERR_ARG, "handle is NULL");
+  if (!h->graph_exec) return fail(FMM_ERR_STATE, "no captured graph");
+  TFMM_HIP(hipGraphLaunch(h->graph_exec, static_cast<hipStream_t>(stream)));
+  return FMM_OK;
+}
+
+extern "C" void fmm_tucker_destroy(fmm_tucker_t h) {
+  if (!h) return;
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  delete h;
+}
+
+// ---------------------------------------------------------------------- dense
+
+extern "C" fmm_status fmm_dense_create(const fmm_layout* layout, fmm_dense_t* out) {
+  clear_error();
+  if (!out) return fail(FMM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  auto* d = new fmm_dense_s();
+  fmm_status st = copy_layout(layout, &d->layout);
+  if (st != FMM_OK) {
+    delete d;
+    return st;
+  }
+  if (!have_device()) {
+    delete d;
+    return FMM_ERR_DEVICE;
+  }
+  const int G = d->layout.n_groups;
+  std::vector<DenseGroup> grp(G);
+  for (int g = 0; g < G; ++g) grp[g] = DenseGroup{d->layout.offsets[g], d->layout.nb(g), 0};
+  hipError_t e = hipGetDevice(&d->device);
+  if (e == hipSuccess && G > 0) e = hipMalloc(&d->d_groups, sizeof(DenseGroup) * G);
+  if (e == hipSuccess) e = hipMalloc(&d->d_offsets, sizeof(int64_t) * (G + 1));
+  if (e == hipSuccess && G > 0)
+    e = hipMemcpy(d->d_groups, grp.data(), sizeof(DenseGroup) * G, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(d->d_offsets, d->layout.offsets.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    fmm_dense_destroy(d);
+    return fail(FMM_ERR_DEVICE, "dense plan upload: %s", hipGetErrorString(e));
+  }
+  *out = d;
+  return FMM_OK;
+}
+
+namespace {
+fmm_status dense_common(fmm_dense_t d, fmm_prec prec, const void* A, int32_t nrhs, const void* in, void* out) {
+  if (!d) return fail(FMM_ERR_ARG, "plan is NULL");
+  if (!prec_valid(prec)) return fail(FMM_ERR_ARG, "bad precision %d", (int)prec);
+  if (prec != FMM_C128 && prec != FMM_C64)
+    return fail(FMM_ERR_UNSUPPORTED, "the dense path supports FMM_C128 and FMM_C64 only");
+  if (nrhs < 1 || nrhs > 65535) return fail(FMM_ERR_ARG, "nrhs must be in [1, 65535]");
+  const size_t es = elem_bytes(prec);
+  fmm_status st;
+  if ((st = check_vec(A, es, "farfield")) != FMM_OK || (st = check_vec(in, es, "input")) != FMM_OK ||
+      (st = check_vec(out, es, "output")) != FMM_OK)
+    return st;
+  if (!have_device()) return FMM_ERR_DEVICE;
+  int dev = 0;
+  TFMM_HIP(hipGetDevice(&dev));
+  if (dev != d->device) return fail(FMM_ERR_STATE, "current device differs from the plan's device");
+  return FMM_OK;
+}
+}  // namespace
+
+extern "C" fmm_status fmm_dense_aggregate(fmm_dense_t d, fmm_prec prec, const void* farfield, int32_t nrhs,
+                                          const void* x, void* F, void* stream) {
+  clear_error();
+  fmm_status st = dense_common(d, prec, farfield, nrhs, x, F);
+  if (st != FMM_OK) return st;
+  const int ncols = 2 * d->layout.ndir();
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (prec == FMM_C128)
+    TFMM_HIP(launch_dense_agg<double>(farfield, d->d_groups, d->layout.n_groups, ncols, nrhs, x, F, hs));
+  else
+    TFMM_HIP(launch_dense_agg<float>(farfield, d->d_groups, d->layout.n_groups, ncols, nrhs, x, F, hs));
+  return FMM_OK;
+}
+
+extern "C" fmm_status fmm_dense_disaggregate(fmm_dense_t d, fmm_prec prec, const void* farfield, int32_t nrhs,
+                                             const void* G, void* V, void* stream) {
+  clear_error();
+  fmm_status st = dense_common(d, prec, farfield, nrhs, G, V);
+  if (st != FMM_OK) return st;
+  const int ncols = 2 * d->layout.ndir();
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (prec == FMM_C128)
+    TFMM_HIP(launch_dense_disagg<double>(farfield, d->d_offsets, d->layout.n_groups, d->layout.n_basis(), ncols,
+                                         nrhs, G, V, hs));
+  else
+    TFMM_HIP(launch_dense_disagg<float>(farfield, d->d_offsets, d->layout.n_groups, d->layout.n_basis(), ncols,
+                                        nrhs, G, V, hs));
+  return FMM_OK;
+}
+
+extern "C" void fmm_dense_destroy(fmm_dense_t d) {
+  if (!d) return;
+  if (d->d_groups) (void)hipFree(d->d_groups);
+  if (d->d_offsets) (void)hipFree(d->d_offsets);
+  delete d;
+}

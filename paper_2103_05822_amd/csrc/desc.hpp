@@ -1,0 +1,44 @@
+// Descriptors shared by the host runtime and the HIP kernels.
+#pragma once
+#include <cstdint>
+
+namespace tuckfmm {
+
+// One Tucker-compressed tensor (one group, one polarisation) inside a device arena.
+// Offsets count complex elements from the start of the factor area.  Device layouts
+// (chosen for coalesced streaming; the ABI uses the paper's shapes instead):
+//   ubt  : U^beta transposed, [r_beta][ld_ub]          (row b = column b of U^beta)
+//   core : [r_beta][ld_c], column q = theta' * r_phi + phi'
+//   ut   : U^theta [n_theta][r_theta]
+//   up   : U^phi [n_phi][r_phi]
+//   upt  : U^phi transposed, [r_phi][n_phi]
+// Row padding elements are zero.
+struct alignas(16) TuckItem {
+  int64_t off_ubt;
+  int64_t off_core;
+  int64_t off_ut;
+  int64_t off_up;
+  int64_t off_upt;
+  int64_t row0;      // first basis row of the group
+  int32_t nb, rt, rp, rb;
+  int32_t ld_ub, ld_c;
+  int32_t group, alpha;
+  int32_t theta_first;  // 1: contract U^theta before U^phi in the angular stages
+  int32_t pad0, pad1, pad2;
+};
+static_assert(sizeof(TuckItem) == 96, "TuckItem layout");
+
+// Maxima over all items of a precision slot; they size the kernels' LDS.
+struct TuckMax {
+  int32_t nb, rt, rp, rb, q;
+  int32_t t3;   // max of n_theta*r_phi or r_theta*n_phi intermediate
+};
+
+// Dense plan: one group's rows.
+struct DenseGroup {
+  int64_t row0;
+  int32_t nb;
+  int32_t pad;
+};
+
+}  // namespace tuckfmm

@@ -1,0 +1,45 @@
+// Host-side launchers of the HIP kernels (implemented in the *.hip files).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include "desc.hpp"
+
+namespace tuckfmm {
+
+// Tucker aggregation / disaggregation, one workgroup per work item.
+//   fac   : base of the factor area (complex<T> elements)
+//   items : [2 * n_groups] descriptors, item 2g + alpha
+//   order : work list (item indices for aggregation, group indices for
+//           disaggregation), largest first
+template <typename T>
+hipError_t launch_tucker_agg(const void* fac, const TuckItem* items, const int32_t* order, int n_items,
+                             const TuckMax& mx, int n_theta, int n_phi, int nrhs, const void* x, void* F,
+                             hipStream_t s);
+template <typename T>
+hipError_t launch_tucker_disagg(const void* fac, const TuckItem* items, const int32_t* order, int n_groups,
+                                const TuckMax& mx, int n_theta, int n_phi, int nrhs, const void* G, void* V,
+                                hipStream_t s);
+template <typename T>
+size_t tucker_agg_lds_bytes(const TuckMax& mx);
+template <typename T>
+size_t tucker_disagg_lds_bytes(const TuckMax& mx);
+
+// Dense (plain) aggregation / disaggregation.
+template <typename T>
+hipError_t launch_dense_agg(const void* A, const DenseGroup* groups, int n_groups, int ncols, int nrhs,
+                            const void* x, void* F, hipStream_t s);
+template <typename T>
+hipError_t launch_dense_disagg(const void* A, const int64_t* offsets, int n_groups, int64_t n_rows, int ncols,
+                               int nrhs, const void* G, void* V, hipStream_t s);
+
+// Far-field fill, eq. (4): rowdata [rows][kRowDoubles], dirs [ndir][9].
+constexpr int kRowDoubles = 40;  // 6 points x (rel xyz, rho xyz) + scale + pad
+hipError_t launch_farfield_fill(const double* rowdata, int64_t rows, const double* dirs, int ndir, double k,
+                                void* out, hipStream_t s);
+
+// Precision conversion / packing helpers for setup.
+hipError_t launch_select_cols_rev(const void* src, int n, int r, void* dst, hipStream_t s);
+hipError_t launch_gather_slab(const void* farfield, int64_t row0, int nb, int alpha, int n_theta, int n_phi,
+                              void* out_tp, void* out_pt, hipStream_t s);
+
+}  // namespace tuckfmm

@@ -1,0 +1,109 @@
+// Setup kernels: the far-field signatures of eq. (4) and the data movement used by
+// the HOSVD driver.  All FP64.
+#include <hip/hip_runtime.h>
+#include "cplx.hpp"
+#include "kernels.hpp"
+
+namespace tuckfmm {
+
+namespace {
+
+// One workgroup per (basis row, 256 directions).  rowdata holds, for each of the
+// six quadrature points of the two triangles, r_q - r_v and the RWG vector rho_q
+// (r_q - p+ on T+, p- - r_q on T-), then l_n / 6 (3-point rule weight A/3 times
+// the RWG normalisation l_n / (2A)).
+__global__ __launch_bounds__(256) void farfield_fill_kernel(const double* __restrict__ rowdata,
+                                                            const double* __restrict__ dirs, int ndir,
+                                                            double k, double2* __restrict__ out) {
+  const int64_t n = blockIdx.x;
+  const int i = blockIdx.y * 256 + threadIdx.x;
+  if (i >= ndir) return;
+  const double* rd = rowdata + n * kRowDoubles;
+  const double* d = dirs + (int64_t)i * 9;
+  const double kx = d[0], ky = d[1], kz = d[2];
+  const double tx = d[3], ty = d[4], tz = d[5];
+  const double px = d[6], py = d[7], pz = d[8];
+  double2 at = make_double2(0.0, 0.0), ap = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const double* e = rd + q * 6;
+    const double ph = k * (e[0] * kx + e[1] * ky + e[2] * kz);
+    double sn, cs;
+    sincos(ph, &sn, &cs);
+    const double wt = e[3] * tx + e[4] * ty + e[5] * tz;
+    const double wp = e[3] * px + e[4] * py + e[5] * pz;
+    at.x += wt * cs;
+    at.y += wt * sn;
+    ap.x += wp * cs;
+    ap.y += wp * sn;
+  }
+  const double sc = rd[36];
+  out[(n * 2 + 0) * ndir + i] = make_double2(sc * at.x, sc * at.y);
+  out[(n * 2 + 1) * ndir + i] = make_double2(sc * ap.x, sc * ap.y);
+}
+
+// Copy one polarisation of a group's far-field rows into two contiguous slabs:
+//   out_tp [nb][n_theta][n_phi]   and   out_pt [nb][n_phi][n_theta]
+__global__ __launch_bounds__(256) void gather_slab_kernel(const double2* __restrict__ ff, int64_t row0, int nb,
+                                                          int alpha, int n_theta, int n_phi,
+                                                          double2* __restrict__ out_tp,
+                                                          double2* __restrict__ out_pt) {
+  const int ndir = n_theta * n_phi;
+  const int64_t total = (int64_t)nb * ndir;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t n = e / ndir;
+    const int i = (int)(e - n * ndir);
+    const double2 v = ff[((row0 + n) * 2 + alpha) * ndir + i];
+    out_tp[e] = v;
+    if (out_pt) {
+      const int it = i / n_phi, ip = i - it * n_phi;
+      out_pt[n * ndir + (int64_t)ip * n_theta + it] = v;
+    }
+  }
+}
+
+// dst (column-major n x r) = columns n-1, n-2, ..., n-r of src (column-major n x n):
+// eigenvectors returned in ascending eigenvalue order become descending.
+__global__ __launch_bounds__(256) void select_cols_rev_kernel(const double2* __restrict__ src, int n, int r,
+                                                              double2* __restrict__ dst) {
+  const int64_t total = (int64_t)n * r;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t j = e / n, i = e - j * n;
+    dst[e] = src[(int64_t)(n - 1 - j) * n + i];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_select_cols_rev(const void* src, int n, int r, void* dst, hipStream_t s) {
+  const int64_t total = (int64_t)n * r;
+  if (total == 0) return hipSuccess;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(select_cols_rev_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                     static_cast<const double2*>(src), n, r, static_cast<double2*>(dst));
+  return hipGetLastError();
+}
+
+hipError_t launch_farfield_fill(const double* rowdata, int64_t rows, const double* dirs, int ndir, double k,
+                                void* out, hipStream_t s) {
+  if (rows == 0) return hipSuccess;
+  dim3 grid((unsigned)rows, (ndir + 255) / 256);
+  hipLaunchKernelGGL(farfield_fill_kernel, grid, dim3(256), 0, s, rowdata, dirs, ndir, k,
+                     static_cast<double2*>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_slab(const void* farfield, int64_t row0, int nb, int alpha, int n_theta, int n_phi,
+                              void* out_tp, void* out_pt, hipStream_t s) {
+  const int64_t total = (int64_t)nb * n_theta * n_phi;
+  if (total == 0) return hipSuccess;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(gather_slab_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                     static_cast<const double2*>(farfield), row0, nb, alpha, n_theta, n_phi,
+                     static_cast<double2*>(out_tp), static_cast<double2*>(out_pt));
+  return hipGetLastError();
+}
+
+}  // namespace tuckfmm

@@ -1,0 +1,283 @@
+"""GPU parity: the HIP kernels against the FP64 oracle on the same seeded inputs.
+
+Tolerances (relative to the largest reference entry, and relative L2 over all
+outputs): FP64 paths 1e-11; FP32 paths 1e-5, the bound the method's target sets
+for single precision (sums of up to ~2,000 FP32 terms with unit-roundoff 6e-8 stay
+near 1e-6).
+"""
+import numpy as np
+import pytest
+
+import synth
+from synth import workloads as W
+from oracle import geometry as geo
+from oracle import farfield as ff
+from oracle import products as pr
+from gpu_util import dev, host, arena, max_rel, l2_rel, banner
+
+pytestmark = pytest.mark.gpu
+
+T = pytest.importorskip("paper_2103_05822_amd")
+
+TOL = {T.FMM_C128: 1e-11, T.FMM_C64: 1e-5}
+CDT = {T.FMM_C128: np.complex128, T.FMM_C64: np.complex64}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+# ---------------------------------------------------------------------------- helpers
+
+def ragged_layout(n_theta=5, n_phi=9):
+    """Groups of 1, 2, 3, 64, 65, 130, 257 basis functions (tails of every tile size)."""
+    sizes = [1, 2, 3, 64, 65, 130, 257]
+    return T.Layout(n_theta, n_phi, np.concatenate([[0], np.cumsum(sizes)]))
+
+
+def small_problem():
+    w = W.SMALL
+    v, t = synth.icosphere(w.freq, w.radius)
+    return w, v, t, geo.Problem(v, t, w.origin, w.box, w.boxes_per_axis, w.n_theta, w.n_phi)
+
+
+def random_tucker(lay, seed, rank_mode="random"):
+    """Per (group, polarisation) synthetic factors; rank_mode picks edge cases."""
+    rng = synth.rng(seed)
+    out = []
+    for g in range(lay.n_groups):
+        nb = int(lay.offsets[g + 1] - lay.offsets[g])
+        pair = []
+        for a in range(2):
+            if rank_mode == "full":
+                rt, rp, rb = lay.n_theta, lay.n_phi, nb
+            elif rank_mode == "one":
+                rt, rp, rb = 1, 1, 1
+            else:
+                rt, rp, rb = synth.synthetic_ranks(rng, nb, lay.n_theta, lay.n_phi)
+            core, ut, up, ub = synth.synthetic_tucker(rng, lay.n_theta, lay.n_phi, nb, rt, rp, rb)
+            pair.append((core, (ut, up, ub)))
+        out.append(pair)
+    return out
+
+
+def make_handle(lay, tuck):
+    h = T.fmm_tucker_create(lay)
+    for g, pair in enumerate(tuck):
+        for a, (core, (ut, up, ub)) in enumerate(pair):
+            T.fmm_tucker_set_group(h, g, a, core, ut, up, ub)
+    return h
+
+
+def run_tucker(lay, tuck, prec, x, gin, nrhs):
+    h = make_handle(lay, tuck)
+    try:
+        _, nbytes = T.fmm_tucker_storage_bytes(h, prec)
+        ar = arena(nbytes)
+        T.fmm_tucker_upload(h, prec, ar)
+        xd = dev(x, CDT[prec])
+        gd = dev(gin, CDT[prec])
+        F = dev(np.zeros((lay.n_groups, 2, lay.n_dir) + ((nrhs,) if nrhs > 1 else ()), CDT[prec]))
+        V = dev(np.zeros(x.shape, CDT[prec]))
+        T.fmm_tucker_aggregate(h, prec, nrhs, xd, F)
+        T.fmm_tucker_disaggregate(h, prec, nrhs, gd, V)
+        return host(F), host(V)
+    finally:
+        T.fmm_tucker_destroy(h)
+
+
+def oracle_tucker(lay, tuck, x, gin):
+    f = pr.aggregate_all("tucker", tuck, lay.offsets, x)
+    v = pr.disaggregate_all("tucker", tuck, lay.offsets, gin)
+    return f, v
+
+
+# ------------------------------------------------------------------------------ Tucker
+
+@pytest.mark.parametrize("prec", [T.FMM_C128, T.FMM_C64], ids=["c128", "c64"])
+@pytest.mark.parametrize("rank_mode", ["random", "full", "one"])
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_tucker_ragged_layout(prec, rank_mode, nrhs):
+    lay = ragged_layout()
+    banner("tucker ragged prec=%d ranks=%s nrhs=%d" % (prec, rank_mode, nrhs))
+    tuck = random_tucker(lay, 20 + nrhs, rank_mode)
+    rng = synth.rng(5)
+    shp = (nrhs,) if nrhs > 1 else ()
+    x = synth.complex_normal(rng, (lay.n_basis,) + shp)
+    gin = synth.complex_normal(rng, (lay.n_groups, 2, lay.n_dir) + shp)
+    F, V = run_tucker(lay, tuck, prec, x, gin, nrhs)
+    f_ref, v_ref = oracle_tucker(lay, tuck, x, gin)
+    tol = TOL[prec]
+    assert max_rel(F, f_ref) < tol and l2_rel(F, f_ref) < tol
+    assert max_rel(V, v_ref) < tol and l2_rel(V, v_ref) < tol
+
+
+@pytest.mark.parametrize("prec", [T.FMM_C128, T.FMM_C64], ids=["c128", "c64"])
+def test_tucker_paper_grid_realistic_ranks(prec):
+    """38 x 75 grid, group sizes of the 6-lambda sphere at box 2 lambda, ranks near
+    Table IV's 2-lambda row (several column tiles, ragged tails)."""
+    w = W.SPHERE6
+    v, t = synth.icosphere(w.freq, w.radius)
+    P = geo.Problem(v, t, w.origin, w.box, w.boxes_per_axis, w.n_theta, w.n_phi)
+    lay = T.Layout(w.n_theta, w.n_phi, P.offsets)
+    rng = synth.rng(31)
+    tuck = []
+    for g in range(lay.n_groups):
+        nb = int(lay.offsets[g + 1] - lay.offsets[g])
+        pair = []
+        for a in range(2):
+            rt = int(rng.integers(20, 29))
+            rp = int(rng.integers(24, 34))
+            rb = int(min(nb, rng.integers(150, 260)))
+            core, ut, up, ub = synth.synthetic_tucker(rng, w.n_theta, w.n_phi, nb, rt, rp, rb)
+            pair.append((core, (ut, up, ub)))
+        tuck.append(pair)
+    banner("tucker paper grid prec=%d groups=%d N=%d" % (prec, lay.n_groups, lay.n_basis))
+    x = synth.complex_normal(rng, lay.n_basis)
+    gin = synth.complex_normal(rng, (lay.n_groups, 2, lay.n_dir))
+    F, V = run_tucker(lay, tuck, prec, x, gin, 1)
+    f_ref, v_ref = oracle_tucker(lay, tuck, x, gin)
+    tol = TOL[prec]
+    assert max_rel(F, f_ref) < tol and l2_rel(F, f_ref) < tol
+    assert max_rel(V, v_ref) < tol and l2_rel(V, v_ref) < tol
+
+
+def test_tucker_deterministic_and_graph_replays():
+    import torch
+    lay = ragged_layout(6, 11)
+    tuck = random_tucker(lay, 41)
+    rng = synth.rng(6)
+    x = synth.complex_normal(rng, lay.n_basis)
+    gin = synth.complex_normal(rng, (lay.n_groups, 2, lay.n_dir))
+    h = make_handle(lay, tuck)
+    try:
+        prec = T.FMM_C64
+        _, nbytes = T.fmm_tucker_storage_bytes(h, prec)
+        ar = arena(nbytes)
+        T.fmm_tucker_upload(h, prec, ar)
+        xd, gd = dev(x, np.complex64), dev(gin, np.complex64)
+        F = torch.zeros((lay.n_groups, 2, lay.n_dir), dtype=torch.complex64, device="cuda")
+        V = torch.zeros(lay.n_basis, dtype=torch.complex64, device="cuda")
+        banner("tucker eager x2")
+        T.fmm_tucker_aggregate(h, prec, 1, xd, F)
+        T.fmm_tucker_disaggregate(h, prec, 1, gd, V)
+        F0, V0 = host(F).copy(), host(V).copy()
+        T.fmm_tucker_aggregate(h, prec, 1, xd, F)
+        T.fmm_tucker_disaggregate(h, prec, 1, gd, V)
+        assert np.array_equal(host(F), F0) and np.array_equal(host(V), V0)
+        banner("tucker graph capture + 3 replays")
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            T.fmm_graph_capture(h, prec, 1, xd, F, gd, V, s)
+        for rep in range(3):
+            F.zero_()
+            V.zero_()
+            torch.cuda.synchronize()
+            T.fmm_graph_launch(h, s)
+            s.synchronize()
+            assert np.array_equal(host(F), F0), rep
+            assert np.array_equal(host(V), V0), rep
+    finally:
+        T.fmm_tucker_destroy(h)
+
+
+# ------------------------------------------------------------------------------- dense
+
+@pytest.mark.parametrize("prec", [T.FMM_C128, T.FMM_C64], ids=["c128", "c64"])
+@pytest.mark.parametrize("nrhs", [1, 2])
+def test_dense_ragged_layout(prec, nrhs):
+    lay = ragged_layout(7, 13)
+    banner("dense ragged prec=%d nrhs=%d" % (prec, nrhs))
+    rng = synth.rng(9)
+    A = synth.complex_normal(rng, (lay.n_basis, 2, lay.n_theta, lay.n_phi))
+    shp = (nrhs,) if nrhs > 1 else ()
+    x = synth.complex_normal(rng, (lay.n_basis,) + shp)
+    gin = synth.complex_normal(rng, (lay.n_groups, 2, lay.n_dir) + shp)
+    d = T.fmm_dense_create(lay)
+    try:
+        Ad = dev(A, CDT[prec])
+        F = dev(np.zeros(gin.shape, CDT[prec]))
+        V = dev(np.zeros(x.shape, CDT[prec]))
+        T.fmm_dense_aggregate(d, prec, Ad, nrhs, dev(x, CDT[prec]), F)
+        T.fmm_dense_disaggregate(d, prec, Ad, nrhs, dev(gin, CDT[prec]), V)
+        F, V = host(F), host(V)
+    finally:
+        T.fmm_dense_destroy(d)
+    f_ref = pr.aggregate_all("dense", A, lay.offsets, x)
+    v_ref = pr.disaggregate_all("dense", A, lay.offsets, gin)
+    tol = TOL[prec]
+    assert max_rel(F, f_ref) < tol and l2_rel(F, f_ref) < tol
+    assert max_rel(V, v_ref) < tol and l2_rel(V, v_ref) < tol
+
+
+# -------------------------------------------------------------------- far-field + compress
+
+def test_farfield_fill_matches_oracle():
+    w, v, t, P = small_problem()
+    D_ref = ff.farfield_all(P)
+    g = T.fmm_geometry_build(v, t, w.origin, w.box, w.boxes_per_axis, w.k, w.n_theta, w.n_phi)
+    try:
+        banner("farfield fill small")
+        D = dev(np.zeros(D_ref.shape, np.complex128))
+        T.fmm_farfield_fill(g, 0, P.n_groups, D)
+        D = host(D)
+        # a chunk of groups lands at the chunk's first row
+        D2 = dev(np.zeros((int(P.offsets[5] - P.offsets[3]), 2, w.n_theta, w.n_phi), np.complex128))
+        T.fmm_farfield_fill(g, 3, 2, D2)
+        D2 = host(D2)
+    finally:
+        T.fmm_geometry_destroy(g)
+    assert max_rel(D, D_ref) < 1e-13
+    assert np.array_equal(D2, D[P.offsets[3]:P.offsets[5]])
+
+
+@pytest.mark.parametrize("gamma", [1e-6, 1e-4, 0.0])
+def test_compress_end_to_end(gamma):
+    """GPU far-field -> GPU HOSVD -> GPU Tucker products against the oracle's dense
+    products with its own far-field: the difference is the compression error,
+    bounded by gamma ||A||_F ||x|| per tensor (plus rounding)."""
+    w, v, t, P = small_problem()
+    D_ref = ff.farfield_all(P)
+    lay = T.Layout(w.n_theta, w.n_phi, P.offsets)
+    g = T.fmm_geometry_build(v, t, w.origin, w.box, w.boxes_per_axis, w.k, w.n_theta, w.n_phi)
+    h = None
+    try:
+        banner("compress small gamma=%g" % gamma)
+        D = dev(np.zeros(D_ref.shape, np.complex128))
+        T.fmm_farfield_fill(g, 0, P.n_groups, D)
+        h = T.fmm_farfield_compress(lay, D, 0, P.n_groups, gamma)
+        ranks = T.fmm_tucker_ranks(h, P.n_groups)
+        rng = synth.rng(w.seeds["x"])
+        x = synth.complex_normal(rng, P.n_basis)
+        _, nbytes = T.fmm_tucker_storage_bytes(h, T.FMM_C128)
+        ar = arena(nbytes)
+        T.fmm_tucker_upload(h, T.FMM_C128, ar)
+        F = dev(np.zeros((P.n_groups, 2, P.n_dir), np.complex128))
+        T.fmm_tucker_aggregate(h, T.FMM_C128, 1, dev(x), F)
+        F = host(F)
+        facs = [[T.fmm_tucker_export(h, gg, a, ranks[gg, a], w.n_theta, w.n_phi,
+                                     int(P.offsets[gg + 1] - P.offsets[gg])) for a in range(2)]
+                for gg in range(P.n_groups)]
+    finally:
+        if h:
+            T.fmm_tucker_destroy(h)
+        T.fmm_geometry_destroy(g)
+    from oracle import hosvd as H
+    for gg in range(P.n_groups):
+        blk = D_ref[P.offsets[gg]:P.offsets[gg + 1]]
+        xs = x[P.offsets[gg]:P.offsets[gg + 1]]
+        f_dense = pr.dense_aggregate(blk, xs)
+        for a in range(2):
+            core, ut, up, ub = facs[gg][a]
+            for u in (ut, up, ub):                     # orthonormal factors
+                assert np.allclose(u.conj().T @ u, np.eye(u.shape[1]), atol=1e-12)
+            bound = gamma * np.linalg.norm(blk[:, a]) * np.linalg.norm(xs)
+            err = np.linalg.norm(F[gg, a] - f_dense[a])
+            assert err <= bound * (1 + 1e-6) + 1e-12 * np.linalg.norm(f_dense[a]), (gg, a, err, bound)
+            # ranks agree with the oracle's HOSVD up to ties at the threshold
+            c_ref, _, _ = H.hosvd(H.tensorize(blk, a), gamma)
+            assert np.all(np.abs(np.array(core.shape) - np.array(c_ref.shape)) <= 1), (core.shape, c_ref.shape)
