@@ -192,9 +192,15 @@ fmm_status fmm_tucker_aggregate(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, con
 fmm_status fmm_tucker_disaggregate(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* G, void* V,
                                    void* stream);
 
-/* Capture one aggregation + disaggregation pass (aggregation of x into F, then
- * disaggregation of G into V) into a HIP graph owned by the handle, replacing a
- * previous capture.  Buffers must stay valid while the graph is used. */
+/* One aggregation + disaggregation pass in a single launch: F = aggregation of x and
+ * V = disaggregation of G exactly as fmm_tucker_aggregate and fmm_tucker_disaggregate
+ * compute them (same arithmetic, bitwise equal results), with the work items of both
+ * stages interleaved in one longest-first work list.  F must not alias G, x or V. */
+fmm_status fmm_tucker_pass(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F, const void* G,
+                           void* V, void* stream);
+
+/* Capture fmm_tucker_pass with these buffers into a HIP graph owned by the handle,
+ * replacing a previous capture.  Buffers must stay valid while the graph is used. */
 fmm_status fmm_graph_capture(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F,
                              const void* G, void* V, void* stream);
 

@@ -22,7 +22,7 @@ __all__ = [
     "fmm_geometry_build", "fmm_geometry_info", "fmm_geometry_tables", "fmm_geometry_layout", "fmm_farfield_fill",
     "fmm_geometry_destroy", "fmm_tucker_create", "fmm_farfield_compress", "fmm_tucker_set_group",
     "fmm_tucker_ranks", "fmm_tucker_export", "fmm_tucker_storage_bytes", "fmm_tucker_upload",
-    "fmm_tucker_aggregate", "fmm_tucker_disaggregate", "fmm_graph_capture", "fmm_graph_launch",
+    "fmm_tucker_aggregate", "fmm_tucker_disaggregate", "fmm_tucker_pass", "fmm_graph_capture", "fmm_graph_launch",
     "fmm_tucker_destroy", "fmm_dense_create", "fmm_dense_aggregate", "fmm_dense_disaggregate",
     "fmm_dense_destroy",
 ]
@@ -33,7 +33,7 @@ STATUS = {0: "FMM_OK", -1: "FMM_ERR_ARG", -2: "FMM_ERR_SHAPE", -3: "FMM_ERR_SIZE
 FMM_C128, FMM_C64, FMM_BF16X2, FMM_BF16X3 = 0, 1, 2, 3
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libtuckfmm.so is not built; run `python -m paper_2103_05822_amd.build` "
+    raise ImportError("libtuckfmm.so is not built; run `python paper_2103_05822_amd/build.py` "
                       "or __graft_entry__.build() first")
 # torch brings its own HIP runtime (SONAME libamdhip64.so.7).  Loading torch first makes
 # the library's libamdhip64.so.7 / librocblas.so.5 dependencies resolve to the copies
@@ -81,6 +81,7 @@ _SIGS = {
     "fmm_tucker_upload": (_st, [_vp, _st, _vp, _sz, _vp]),
     "fmm_tucker_aggregate": (_st, [_vp, _st, _i32, _vp, _vp, _vp]),
     "fmm_tucker_disaggregate": (_st, [_vp, _st, _i32, _vp, _vp, _vp]),
+    "fmm_tucker_pass": (_st, [_vp, _st, _i32, _vp, _vp, _vp, _vp, _vp]),
     "fmm_graph_capture": (_st, [_vp, _st, _i32, _vp, _vp, _vp, _vp, _vp]),
     "fmm_graph_launch": (_st, [_vp, _vp]),
     "fmm_tucker_destroy": (None, [_vp]),
@@ -271,6 +272,10 @@ def fmm_tucker_aggregate(h, prec, nrhs, x, F, stream=None):
 
 def fmm_tucker_disaggregate(h, prec, nrhs, G, V, stream=None):
     _check(_lib.fmm_tucker_disaggregate(h, int(prec), int(nrhs), _ptr(G), _ptr(V), _stream(stream)))
+
+
+def fmm_tucker_pass(h, prec, nrhs, x, F, G, V, stream=None):
+    _check(_lib.fmm_tucker_pass(h, int(prec), int(nrhs), _ptr(x), _ptr(F), _ptr(G), _ptr(V), _stream(stream)))
 
 
 def fmm_graph_capture(h, prec, nrhs, x, F, G, V, stream):

@@ -1,6 +1,6 @@
 """Build ``libtuckfmm.so`` (the C-ABI library) for gfx950 with hipcc.
 
-Usage: ``python -m paper_2103_05822_amd.build`` or ``build()`` from Python.  Objects
+Usage: ``python paper_2103_05822_amd/build.py`` or ``__graft_entry__.build()``.  Objects
 go to ``_build/`` at the repository root; the shared library is written next to
 this file, where the binding loads it.
 """

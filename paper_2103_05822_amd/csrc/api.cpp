@@ -74,18 +74,17 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 bool aligned(const void* p, size_t a) { return reinterpret_cast<uintptr_t>(p) % a == 0; }
 
-// Device layout of one precision slot, computed identically for sizing and packing.
+// Device layout of one precision slot, computed identically for sizing and packing:
+// [header: items, work list, pass list][factors].
 struct ArenaPlan {
-  size_t header_bytes = 0, total_bytes = 0, factor_bytes_paper = 0;
+  size_t header_bytes = 0, factor_bytes = 0, total_bytes = 0, factor_bytes_paper = 0;
   std::vector<TuckItem> items;
-  std::vector<int32_t> agg_order, dis_order;
+  std::vector<int32_t> order, pass;
   TuckMax mx{};
 };
 
-// Cost of streaming one tensor (bytes read), used for the work-list order.
-double item_cost(const TuckItem& it) {
-  return (double)it.rb * it.ld_ub + (double)it.rb * it.ld_c + 1e-3 * it.nb;
-}
+// Bytes streamed by one item (U^beta and the core), the key of the work lists.
+double item_cost(const TuckItem& it) { return (double)it.rb * ((double)it.ld_ub + (double)it.ld_c); }
 
 fmm_status plan_arena(const fmm_tucker_s* h, fmm_prec prec, ArenaPlan* P) {
   const Layout& L = h->layout;
@@ -94,9 +93,6 @@ fmm_status plan_arena(const fmm_tucker_s* h, fmm_prec prec, ArenaPlan* P) {
   const int E = pack_elems(prec);
   const size_t blk_align = es == 12 ? 768 : 256;  // a multiple of both 256 bytes and the element size
   P->items.resize((size_t)2 * G);
-  P->agg_order.resize((size_t)2 * G);
-  P->dis_order.resize((size_t)G);
-  P->header_bytes = align_up((size_t)2 * G * sizeof(TuckItem) + (size_t)3 * G * sizeof(int32_t), 256);
   size_t off = 0;  // bytes inside the factor area
   auto block = [&](size_t n_el) {
     const size_t start = off;
@@ -139,15 +135,21 @@ fmm_status plan_arena(const fmm_tucker_s* h, fmm_prec prec, ArenaPlan* P) {
     }
   }
   P->mx = mx;
-  std::iota(P->agg_order.begin(), P->agg_order.end(), 0);
-  std::stable_sort(P->agg_order.begin(), P->agg_order.end(),
+  // work lists in longest-processing-time order
+  const int n = 2 * G;
+  P->order.resize(n);
+  std::iota(P->order.begin(), P->order.end(), 0);
+  std::stable_sort(P->order.begin(), P->order.end(),
                    [&](int32_t a, int32_t b) { return item_cost(P->items[a]) > item_cost(P->items[b]); });
-  std::iota(P->dis_order.begin(), P->dis_order.end(), 0);
-  std::stable_sort(P->dis_order.begin(), P->dis_order.end(), [&](int32_t a, int32_t b) {
-    return item_cost(P->items[2 * a]) + item_cost(P->items[2 * a + 1]) >
-           item_cost(P->items[2 * b]) + item_cost(P->items[2 * b + 1]);
-  });
-  P->total_bytes = P->header_bytes + off;
+  P->pass.resize((size_t)2 * n);
+  for (int i = 0; i < n; ++i) {
+    P->pass[2 * i] = P->order[i];        // aggregation of the i-th largest item
+    P->pass[2 * i + 1] = ~P->order[i];   // and its disaggregation
+  }
+  P->header_bytes =
+      align_up(P->items.size() * sizeof(TuckItem) + (P->order.size() + P->pass.size()) * sizeof(int32_t), 256);
+  P->factor_bytes = off;
+  P->total_bytes = P->header_bytes + P->factor_bytes;
   return FMM_OK;
 }
 
@@ -346,11 +348,14 @@ extern "C" fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* are
 
   // host image of the whole arena
   std::vector<char> img(P.total_bytes, 0);
-  std::memcpy(img.data(), P.items.data(), P.items.size() * sizeof(TuckItem));
-  char* p = img.data() + P.items.size() * sizeof(TuckItem);
-  std::memcpy(p, P.agg_order.data(), P.agg_order.size() * sizeof(int32_t));
-  p += P.agg_order.size() * sizeof(int32_t);
-  std::memcpy(p, P.dis_order.data(), P.dis_order.size() * sizeof(int32_t));
+  char* p = img.data();
+  std::memcpy(p, P.items.data(), P.items.size() * sizeof(TuckItem));
+  p += P.items.size() * sizeof(TuckItem);
+  const size_t order_off = (size_t)(p - img.data());
+  std::memcpy(p, P.order.data(), P.order.size() * sizeof(int32_t));
+  p += P.order.size() * sizeof(int32_t);
+  const size_t pass_off = (size_t)(p - img.data());
+  std::memcpy(p, P.pass.data(), P.pass.size() * sizeof(int32_t));
   char* fac = img.data() + P.header_bytes;
   const size_t n_t = P.items.size();
   const unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -375,11 +380,14 @@ extern "C" fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* are
   sl.arena = static_cast<char*>(arena);
   sl.bytes = bytes;
   sl.device = dev;
-  sl.items = reinterpret_cast<const TuckItem*>(sl.arena);
-  sl.agg_order = reinterpret_cast<const int32_t*>(sl.arena + P.items.size() * sizeof(TuckItem));
-  sl.dis_order = sl.agg_order + P.agg_order.size();
-  sl.factors = sl.arena + P.header_bytes;
-  sl.mx = P.mx;
+  TuckPlan& pl = sl.plan;
+  pl.items = reinterpret_cast<const TuckItem*>(sl.arena);
+  pl.order = reinterpret_cast<const int32_t*>(sl.arena + order_off);
+  pl.pass_list = reinterpret_cast<const int32_t*>(sl.arena + pass_off);
+  pl.n_items = (int)P.items.size();
+  pl.n_basis = h->layout.n_basis();
+  pl.factors = sl.arena + P.header_bytes;
+  pl.mx = P.mx;
   return FMM_OK;
 }
 
@@ -394,13 +402,11 @@ extern "C" fmm_status fmm_tucker_aggregate(fmm_tucker_t h, fmm_prec prec, int32_
   const Layout& L = h->layout;
   hipStream_t hs = static_cast<hipStream_t>(stream);
   if (prec == FMM_C128) {
-    if ((st = lds_check(tucker_agg_lds_bytes<double>(s->mx))) != FMM_OK) return st;
-    TFMM_HIP(launch_tucker_agg<double>(s->factors, s->items, s->agg_order, 2 * L.n_groups, s->mx, L.n_theta,
-                                       L.n_phi, nrhs, x, F, hs));
+    if ((st = lds_check(tucker_lds_bytes<double>(s->plan.mx))) != FMM_OK) return st;
+    TFMM_HIP(launch_tucker_agg<double>(s->plan, L.n_theta, L.n_phi, nrhs, x, F, hs));
   } else {
-    if ((st = lds_check(tucker_agg_lds_bytes<float>(s->mx))) != FMM_OK) return st;
-    TFMM_HIP(launch_tucker_agg<float>(s->factors, s->items, s->agg_order, 2 * L.n_groups, s->mx, L.n_theta,
-                                      L.n_phi, nrhs, x, F, hs));
+    if ((st = lds_check(tucker_lds_bytes<float>(s->plan.mx))) != FMM_OK) return st;
+    TFMM_HIP(launch_tucker_agg<float>(s->plan, L.n_theta, L.n_phi, nrhs, x, F, hs));
   }
   return FMM_OK;
 }
@@ -416,13 +422,33 @@ extern "C" fmm_status fmm_tucker_disaggregate(fmm_tucker_t h, fmm_prec prec, int
   const Layout& L = h->layout;
   hipStream_t hs = static_cast<hipStream_t>(stream);
   if (prec == FMM_C128) {
-    if ((st = lds_check(tucker_disagg_lds_bytes<double>(s->mx))) != FMM_OK) return st;
-    TFMM_HIP(launch_tucker_disagg<double>(s->factors, s->items, s->dis_order, L.n_groups, s->mx, L.n_theta,
-                                          L.n_phi, nrhs, G, V, hs));
+    if ((st = lds_check(tucker_lds_bytes<double>(s->plan.mx))) != FMM_OK) return st;
+    TFMM_HIP(launch_tucker_disagg<double>(s->plan, L.n_theta, L.n_phi, nrhs, G, V, hs));
   } else {
-    if ((st = lds_check(tucker_disagg_lds_bytes<float>(s->mx))) != FMM_OK) return st;
-    TFMM_HIP(launch_tucker_disagg<float>(s->factors, s->items, s->dis_order, L.n_groups, s->mx, L.n_theta,
-                                         L.n_phi, nrhs, G, V, hs));
+    if ((st = lds_check(tucker_lds_bytes<float>(s->plan.mx))) != FMM_OK) return st;
+    TFMM_HIP(launch_tucker_disagg<float>(s->plan, L.n_theta, L.n_phi, nrhs, G, V, hs));
+  }
+  return FMM_OK;
+}
+
+extern "C" fmm_status fmm_tucker_pass(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F,
+                                      const void* G, void* V, void* stream) {
+  clear_error();
+  PrecSlot* s = nullptr;
+  fmm_status st = ready_slot(h, prec, nrhs, &s);
+  if (st != FMM_OK) return st;
+  const size_t es = elem_bytes(prec);
+  if ((st = check_vec(x, es, "x")) != FMM_OK || (st = check_vec(F, es, "F")) != FMM_OK ||
+      (st = check_vec(G, es, "G")) != FMM_OK || (st = check_vec(V, es, "V")) != FMM_OK)
+    return st;
+  const Layout& L = h->layout;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (prec == FMM_C128) {
+    if ((st = lds_check(tucker_lds_bytes<double>(s->plan.mx))) != FMM_OK) return st;
+    TFMM_HIP(launch_tucker_pass<double>(s->plan, L.n_theta, L.n_phi, nrhs, x, F, G, V, hs));
+  } else {
+    if ((st = lds_check(tucker_lds_bytes<float>(s->plan.mx))) != FMM_OK) return st;
+    TFMM_HIP(launch_tucker_pass<float>(s->plan, L.n_theta, L.n_phi, nrhs, x, F, G, V, hs));
   }
   return FMM_OK;
 }
@@ -444,8 +470,7 @@ extern "C" fmm_status fmm_graph_capture(fmm_tucker_t h, fmm_prec prec, int32_t n
     h->graph = nullptr;
   }
   TFMM_HIP(hipStreamBeginCapture(hs, hipStreamCaptureModeThreadLocal));
-  fmm_status a = fmm_tucker_aggregate(h, prec, nrhs, x, F, stream);
-  fmm_status d = a == FMM_OK ? fmm_tucker_disaggregate(h, prec, nrhs, G, V, stream) : a;
+  fmm_status d = fmm_tucker_pass(h, prec, nrhs, x, F, G, V, stream);
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(hs, &graph);
   if (d != FMM_OK) {

@@ -2,18 +2,26 @@
 // FP64 on the device.
 //
 // For each (group, polarisation) tensor A (n_theta x n_phi x n_beta):
-//   1. the three mode unfoldings' Gram matrices with rocBLAS ZHERK;
-//   2. their Hermitian eigendecompositions with rocSOLVER ZHEEVD: the eigenvectors
-//      are the left singular vectors of the unfoldings and the eigenvalues their
-//      squared singular values;
+//   1. the Gram matrices of the three mode unfoldings: the basis mode with rocBLAS
+//      ZHERK, the two angular modes with mode_gram (a tall-skinny reduction that
+//      ZHERK handles poorly);
+//   2. their Hermitian eigendecompositions with rocSOLVER ZHEEVD: eigenvectors are
+//      the left singular vectors of the unfoldings, eigenvalues the squared
+//      singular values;
 //   3. per mode, the smallest rank whose discarded tail satisfies
 //      sum_{i>=r} s_i^2 <= gamma^2/3 ||A||_F^2 (host, FP64);
 //   4. the core C = A x_3 U^beta* x_1 U^theta* x_2 U^phi* with three ZGEMMs.
+// The eigensolver is latency-bound for these sizes, so tensors are spread over
+// several worker threads, each with its own stream, rocBLAS handle and workspace.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdlib>
+#include <mutex>
+#include <thread>
 
 #include "internal.hpp"
 #include "kernels.hpp"
@@ -22,31 +30,13 @@ using namespace tuckfmm;
 
 namespace {
 
-struct DevBuf {
-  void* p = nullptr;
-  ~DevBuf() {
-    if (p) (void)hipFree(p);
-  }
-  hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes ? bytes : 16); }
-  template <typename T>
-  T* as() const {
-    return static_cast<T*>(p);
-  }
-};
-
-struct BlasHandle {
-  rocblas_handle h = nullptr;
-  ~BlasHandle() {
-    if (h) rocblas_destroy_handle(h);
-  }
-};
-
-#define TFMM_BLAS(expr)                                                                \
-  do {                                                                                 \
-    rocblas_status s_ = (expr);                                                        \
-    if (s_ != rocblas_status_success)                                                  \
-      return fail(FMM_ERR_DEVICE, "%s failed: %s", #expr, rocblas_status_to_string(s_)); \
-  } while (0)
+// Worker threads of the HOSVD driver (TUCKFMM_COMPRESS_WORKERS overrides; 1 runs the
+// tensors one after another on one stream).
+int worker_count() {
+  const char* e = std::getenv("TUCKFMM_COMPRESS_WORKERS");
+  const int n = e ? std::atoi(e) : 8;
+  return std::min(std::max(n, 1), 32);
+}
 
 // Smallest r >= 1 with sum_{i >= r} lam_desc[i] <= thr2 (lam sorted descending);
 // thr2 <= 0 keeps everything.
@@ -55,13 +45,199 @@ int truncation_rank(const std::vector<double>& lam_desc, double thr2) {
   if (thr2 <= 0.0) return n;
   double tail = 0.0;
   int r = n;
-  // walk from the smallest eigenvalue up while the tail stays within the budget
   for (int i = n - 1; i >= 1; --i) {
     tail += std::max(lam_desc[i], 0.0);
-    if (tail <= thr2) r = i;
-    else break;
+    if (tail <= thr2)
+      r = i;
+    else
+      break;
   }
   return std::max(r, 1);
+}
+
+struct Shared {
+  std::mutex mu;
+  fmm_status status = FMM_OK;
+  std::string message;
+  std::atomic<int> next{0};
+  void error(fmm_status st, const std::string& msg) {
+    std::lock_guard<std::mutex> lk(mu);
+    if (status == FMM_OK) {
+      status = st;
+      message = msg;
+    }
+  }
+  bool failed() {
+    std::lock_guard<std::mutex> lk(mu);
+    return status != FMM_OK;
+  }
+};
+
+struct Worker {
+  hipStream_t s = nullptr;
+  rocblas_handle h = nullptr;
+  void* buf[9] = {};
+  ~Worker() {
+    for (void* p : buf)
+      if (p) (void)hipFree(p);
+    if (h) rocblas_destroy_handle(h);
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
+
+struct Job {
+  const Layout* L;
+  const void* farfield;
+  int64_t base_row;
+  int first_group;
+  int n_tensors;
+  int nb_max;
+  double gamma;
+  fmm_tucker_s* handle;
+};
+
+std::string hip_msg(const char* what, hipError_t e) { return std::string(what) + ": " + hipGetErrorString(e); }
+
+// Decompose tensor t of the job on worker w.  Returns an empty string on success.
+std::string decompose(const Job& J, Worker& w, int t) {
+  const Layout& L = *J.L;
+  const int g = J.first_group + t / 2, alpha = t % 2;
+  const int nt = L.n_theta, np = L.n_phi, nd = L.ndir();
+  const int nb = L.nb(g);
+  const int64_t row0 = L.offsets[g] - J.base_row;
+  using Z = rocblas_double_complex;
+  Z* slab = static_cast<Z*>(w.buf[0]);
+  Z* gb = static_cast<Z*>(w.buf[1]);
+  Z* gt = static_cast<Z*>(w.buf[2]);
+  Z* gp = static_cast<Z*>(w.buf[3]);
+  double* lam = static_cast<double*>(w.buf[4]);
+  Z* part = static_cast<Z*>(w.buf[5]);
+  Z* vb = static_cast<Z*>(w.buf[6]);
+  Z* y = static_cast<Z*>(w.buf[7]);
+  Z* z = static_cast<Z*>(w.buf[8]);
+  Z* ut = gt + (size_t)nt * nt;  // selected columns live after each Gram matrix
+  Z* up = gp + (size_t)np * np;
+  double* lb = lam;
+  double* lt = lb + J.nb_max;
+  double* lp = lt + nt;
+  double* ework = lp + np;
+  rocblas_int* info = reinterpret_cast<rocblas_int*>(ework + J.nb_max + nt + np);
+
+  hipError_t he = launch_gather_slab(J.farfield, row0, nb, alpha, nt, np, slab, nullptr, w.s);
+  if (he != hipSuccess) return hip_msg("gather kernel", he);
+  const double one = 1.0, zero = 0.0;
+  rocblas_status bs = rocblas_zherk(w.h, rocblas_fill_upper, rocblas_operation_conjugate_transpose, nb, nd, &one,
+                                    slab, nd, &zero, gb, nb);
+  if (bs != rocblas_status_success) return std::string("zherk: ") + rocblas_status_to_string(bs);
+  he = launch_mode_gram(slab, nb, nt, np, part, gt, gp, w.s);
+  if (he != hipSuccess) return hip_msg("mode_gram kernel", he);
+  bs = rocsolver_zheevd(w.h, rocblas_evect_original, rocblas_fill_upper, nb, gb, nb, lb, ework, info);
+  if (bs == rocblas_status_success)
+    bs = rocsolver_zheevd(w.h, rocblas_evect_original, rocblas_fill_upper, nt, gt, nt, lt, ework, info + 1);
+  if (bs == rocblas_status_success)
+    bs = rocsolver_zheevd(w.h, rocblas_evect_original, rocblas_fill_upper, np, gp, np, lp, ework, info + 2);
+  if (bs != rocblas_status_success) return std::string("zheevd: ") + rocblas_status_to_string(bs);
+
+  std::vector<double> lam_h((size_t)J.nb_max + nt + np);
+  rocblas_int info_h[3];
+  if ((he = hipMemcpyAsync(lam_h.data(), lam, sizeof(double) * lam_h.size(), hipMemcpyDeviceToHost, w.s)) !=
+          hipSuccess ||
+      (he = hipMemcpyAsync(info_h, info, sizeof(info_h), hipMemcpyDeviceToHost, w.s)) != hipSuccess ||
+      (he = hipStreamSynchronize(w.s)) != hipSuccess)
+    return hip_msg("eigenvalue copy", he);
+  if (info_h[0] != 0 || info_h[1] != 0 || info_h[2] != 0) return "NUMERIC:eigensolver did not converge";
+  auto desc = [](const double* a, int n) {
+    std::vector<double> v(n);
+    for (int i = 0; i < n; ++i) v[i] = a[n - 1 - i];
+    return v;
+  };
+  const std::vector<double> eb = desc(lam_h.data(), nb);
+  const std::vector<double> et = desc(lam_h.data() + J.nb_max, nt);
+  const std::vector<double> ep = desc(lam_h.data() + J.nb_max + nt, np);
+  double norm2 = 0.0;
+  for (double v : eb) {
+    if (!std::isfinite(v)) return "NUMERIC:non-finite far-field values";
+    norm2 += std::max(v, 0.0);
+  }
+  const double thr2 = J.gamma * J.gamma / 3.0 * norm2;
+  const int rb = truncation_rank(eb, thr2);
+  const int rt = truncation_rank(et, thr2);
+  const int rp = truncation_rank(ep, thr2);
+
+  if ((he = launch_select_cols_rev(gb, nb, rb, vb, w.s)) != hipSuccess ||
+      (he = launch_select_cols_rev(gt, nt, rt, ut, w.s)) != hipSuccess ||
+      (he = launch_select_cols_rev(gp, np, rp, up, w.s)) != hipSuccess)
+    return hip_msg("column select kernel", he);
+  const Z cone = {1.0, 0.0}, czero = {0.0, 0.0};
+  // Y (nd x rb) = A^T conj(U^beta); the eigenvectors of conj(A A^H) are conj(U^beta)
+  bs = rocblas_zgemm(w.h, rocblas_operation_none, rocblas_operation_none, nd, rb, nb, &cone, slab, nd, vb, nb,
+                     &czero, y, nd);
+  // Z_b (r_theta x n_phi) = U^theta^H Y_b^T for every b
+  if (bs == rocblas_status_success)
+    bs = rocblas_zgemm_strided_batched(w.h, rocblas_operation_conjugate_transpose, rocblas_operation_transpose, rt,
+                                       np, nt, &cone, ut, nt, 0, y, np, nd, &czero, z, rt, (rocblas_stride)rt * np, rb);
+  // C_b^T (r_phi x r_theta) = U^phi^H Z_b^T, i.e. row-major [theta'][phi'] per b; reuse slab
+  Z* cb = slab;
+  if (bs == rocblas_status_success)
+    bs = rocblas_zgemm_strided_batched(w.h, rocblas_operation_conjugate_transpose, rocblas_operation_transpose, rp,
+                                       rt, np, &cone, up, np, 0, z, rt, (rocblas_stride)rt * np, &czero, cb, rp,
+                                       (rocblas_stride)rt * rp, rb);
+  if (bs != rocblas_status_success) return std::string("core projection: ") + rocblas_status_to_string(bs);
+
+  std::vector<cd> vb_h((size_t)nb * rb), ut_h((size_t)nt * rt), up_h((size_t)np * rp), cb_h((size_t)rb * rt * rp);
+  const size_t cz = sizeof(Z);
+  if ((he = hipMemcpyAsync(vb_h.data(), vb, cz * vb_h.size(), hipMemcpyDeviceToHost, w.s)) != hipSuccess ||
+      (he = hipMemcpyAsync(ut_h.data(), ut, cz * ut_h.size(), hipMemcpyDeviceToHost, w.s)) != hipSuccess ||
+      (he = hipMemcpyAsync(up_h.data(), up, cz * up_h.size(), hipMemcpyDeviceToHost, w.s)) != hipSuccess ||
+      (he = hipMemcpyAsync(cb_h.data(), cb, cz * cb_h.size(), hipMemcpyDeviceToHost, w.s)) != hipSuccess ||
+      (he = hipStreamSynchronize(w.s)) != hipSuccess)
+    return hip_msg("factor copy", he);
+  TensorFactors tf;
+  tf.rt = rt;
+  tf.rp = rp;
+  tf.rb = rb;
+  tf.ub.resize((size_t)nb * rb);
+  for (int n = 0; n < nb; ++n)
+    for (int b = 0; b < rb; ++b) tf.ub[(size_t)n * rb + b] = std::conj(vb_h[(size_t)b * nb + n]);
+  tf.ut.resize((size_t)nt * rt);
+  for (int i = 0; i < nt; ++i)
+    for (int a = 0; a < rt; ++a) tf.ut[(size_t)i * rt + a] = ut_h[(size_t)a * nt + i];
+  tf.up.resize((size_t)np * rp);
+  for (int j = 0; j < np; ++j)
+    for (int c = 0; c < rp; ++c) tf.up[(size_t)j * rp + c] = up_h[(size_t)c * np + j];
+  tf.core.resize((size_t)rt * rp * rb);
+  for (int b = 0; b < rb; ++b)
+    for (int a = 0; a < rt; ++a)
+      for (int c = 0; c < rp; ++c)
+        tf.core[((size_t)a * rp + c) * rb + b] = cb_h[(size_t)b * rt * rp + (size_t)a * rp + c];
+  J.handle->t[2 * (size_t)g + alpha] = std::move(tf);
+  return std::string();
+}
+
+std::string setup_worker(Worker& w, const Job& J, int device) {
+  hipError_t he = hipSetDevice(device);
+  if (he != hipSuccess) return hip_msg("hipSetDevice", he);
+  if ((he = hipStreamCreateWithFlags(&w.s, hipStreamNonBlocking)) != hipSuccess) return hip_msg("stream", he);
+  rocblas_status bs = rocblas_create_handle(&w.h);
+  if (bs == rocblas_status_success) bs = rocblas_set_stream(w.h, w.s);
+  if (bs != rocblas_status_success) return std::string("rocblas handle: ") + rocblas_status_to_string(bs);
+  const int nt = J.L->n_theta, np = J.L->n_phi, nd = J.L->ndir();
+  const size_t nbm = (size_t)J.nb_max;
+  const size_t cz = 16;
+  const size_t sizes[9] = {
+      cz * nbm * nd,                                               // slab (also the core output)
+      cz * nbm * nbm,                                              // basis-mode Gram / eigenvectors
+      cz * (size_t)nt * nt * 2,                                    // theta Gram + selected columns
+      cz * (size_t)np * np * 2,                                    // phi Gram + selected columns
+      sizeof(double) * 2 * (nbm + nt + np) + 64,                   // eigenvalues, work, info
+      cz * (size_t)mode_gram_chunks(J.nb_max) * (nt * nt + np * np),  // Gram partials
+      cz * nbm * nbm,                                              // selected basis-mode columns
+      cz * (size_t)nd * nbm,                                       // Y
+      cz * nbm * nd,                                               // Z
+  };
+  for (int i = 0; i < 9; ++i)
+    if ((he = hipMalloc(&w.buf[i], sizes[i])) != hipSuccess) return hip_msg("workspace hipMalloc", he);
+  return std::string();
 }
 
 }  // namespace
@@ -81,40 +257,20 @@ extern "C" fmm_status fmm_farfield_compress(const fmm_layout* layout, const void
     if (H.n_theta != L.n_theta || H.n_phi != L.n_phi || H.offsets != L.offsets)
       return fail(FMM_ERR_SHAPE, "layout differs from the handle's layout");
   }
-  if (count == 0) {
-    if (!*inout) return fmm_tucker_create(layout, inout);
-    return FMM_OK;
-  }
+  if (count == 0) return *inout ? FMM_OK : fmm_tucker_create(layout, inout);
   if (!farfield) return fail(FMM_ERR_ARG, "farfield is NULL");
   if (reinterpret_cast<uintptr_t>(farfield) % 16) return fail(FMM_ERR_ARG, "farfield must be 16-byte aligned");
   if (!have_device()) return FMM_ERR_DEVICE;
-
-  const int nt = L.n_theta, np = L.n_phi, nd = L.ndir();
-  int nb_max = 0;
-  for (int g = first_group; g < first_group + count; ++g) nb_max = std::max(nb_max, L.nb(g));
-  const int64_t base_row = L.offsets[first_group];
-  hipStream_t hs = static_cast<hipStream_t>(stream);
-
-  BlasHandle bh;
-  TFMM_BLAS(rocblas_create_handle(&bh.h));
-  TFMM_BLAS(rocblas_set_stream(bh.h, hs));
-
-  const size_t cz = sizeof(rocblas_double_complex);
-  DevBuf s_tp, s_pt, gb, gt, gp, lam, work_e, info, vb, ut, up, y, z, cb;
-  TFMM_HIP(s_tp.alloc(cz * (size_t)nb_max * nd));
-  TFMM_HIP(s_pt.alloc(cz * (size_t)nb_max * nd));
-  TFMM_HIP(gb.alloc(cz * (size_t)nb_max * nb_max));
-  TFMM_HIP(gt.alloc(cz * (size_t)nt * nt));
-  TFMM_HIP(gp.alloc(cz * (size_t)np * np));
-  TFMM_HIP(lam.alloc(sizeof(double) * ((size_t)nb_max + nt + np)));
-  TFMM_HIP(work_e.alloc(sizeof(double) * ((size_t)nb_max + nt + np)));
-  TFMM_HIP(info.alloc(sizeof(rocblas_int) * 4));
-  TFMM_HIP(vb.alloc(cz * (size_t)nb_max * nb_max));
-  TFMM_HIP(ut.alloc(cz * (size_t)nt * nt));
-  TFMM_HIP(up.alloc(cz * (size_t)np * np));
-  TFMM_HIP(y.alloc(cz * (size_t)nd * nb_max));
-  TFMM_HIP(z.alloc(cz * (size_t)nb_max * nt * np));
-  TFMM_HIP(cb.alloc(cz * (size_t)nb_max * nt * np));
+  int dev = 0;
+  TFMM_HIP(hipGetDevice(&dev));
+  {
+    int lim = 0;
+    TFMM_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    if ((size_t)16 * L.n_theta * L.n_phi > (size_t)lim)
+      return fail(FMM_ERR_UNSUPPORTED, "angular grid %dx%d too large for the Gram kernel's LDS", L.n_theta, L.n_phi);
+  }
+  // the far-field may still be in flight on the caller's stream
+  TFMM_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
 
   bool created = false;
   if (!*inout) {
@@ -122,131 +278,50 @@ extern "C" fmm_status fmm_farfield_compress(const fmm_layout* layout, const void
     if (st != FMM_OK) return st;
     created = true;
   }
-  fmm_tucker_t h = *inout;
-  auto bail = [&](fmm_status s) {
+  Job J;
+  J.L = &L;
+  J.farfield = farfield;
+  J.base_row = L.offsets[first_group];
+  J.first_group = first_group;
+  J.n_tensors = 2 * count;
+  J.nb_max = 0;
+  for (int g = first_group; g < first_group + count; ++g) J.nb_max = std::max(J.nb_max, L.nb(g));
+  J.gamma = gamma;
+  J.handle = *inout;
+
+  Shared sh;
+  const int nw = std::min(worker_count(), J.n_tensors);
+  std::vector<std::thread> pool;
+  for (int i = 0; i < nw; ++i)
+    pool.emplace_back([&]() {
+      Worker w;
+      std::string msg = setup_worker(w, J, dev);
+      if (!msg.empty()) {
+        sh.error(FMM_ERR_DEVICE, msg);
+        return;
+      }
+      for (;;) {
+        const int t = sh.next.fetch_add(1);
+        if (t >= J.n_tensors || sh.failed()) break;
+        msg = decompose(J, w, t);
+        if (!msg.empty()) {
+          const bool numeric = msg.rfind("NUMERIC:", 0) == 0;
+          sh.error(numeric ? FMM_ERR_NUMERIC : FMM_ERR_DEVICE,
+                   "group " + std::to_string(J.first_group + t / 2) + " polarisation " + std::to_string(t % 2) +
+                       ": " + (numeric ? msg.substr(8) : msg));
+          break;
+        }
+      }
+      (void)hipStreamSynchronize(w.s);
+    });
+  for (auto& th : pool) th.join();
+  if (sh.status != FMM_OK) {
     if (created) {
-      fmm_tucker_destroy(h);
+      fmm_tucker_destroy(*inout);
       *inout = nullptr;
     }
-    return s;
-  };
-
-  const double one = 1.0, zero = 0.0;
-  const rocblas_double_complex cone = {1.0, 0.0}, czero = {0.0, 0.0};
-  std::vector<double> lam_h((size_t)nb_max + nt + np);
-  rocblas_int info_h[3];
-
-  for (int g = first_group; g < first_group + count; ++g) {
-    const int nb = L.nb(g);
-    const int64_t row0 = L.offsets[g] - base_row;
-    for (int alpha = 0; alpha < 2; ++alpha) {
-      if (launch_gather_slab(farfield, row0, nb, alpha, nt, np, s_tp.p, s_pt.p, hs) != hipSuccess)
-        return bail(fail(FMM_ERR_DEVICE, "gather kernel launch failed"));
-      auto* A_tp = s_tp.as<rocblas_double_complex>();
-      auto* A_pt = s_pt.as<rocblas_double_complex>();
-      // Gram matrices (upper triangles)
-      rocblas_status bs;
-      bs = rocblas_zherk(bh.h, rocblas_fill_upper, rocblas_operation_conjugate_transpose, nb, nd, &one, A_tp, nd,
-                         &zero, gb.as<rocblas_double_complex>(), nb);
-      if (bs == rocblas_status_success)
-        bs = rocblas_zherk(bh.h, rocblas_fill_upper, rocblas_operation_none, nt, nb * np, &one, A_pt, nt, &zero,
-                           gt.as<rocblas_double_complex>(), nt);
-      if (bs == rocblas_status_success)
-        bs = rocblas_zherk(bh.h, rocblas_fill_upper, rocblas_operation_none, np, nb * nt, &one, A_tp, np, &zero,
-                           gp.as<rocblas_double_complex>(), np);
-      // eigendecompositions (ascending eigenvalues, eigenvectors in place)
-      double* lb = lam.as<double>();
-      double* lt = lb + nb_max;
-      double* lp = lt + nt;
-      double* ew = work_e.as<double>();
-      rocblas_int* inf = info.as<rocblas_int>();
-      if (bs == rocblas_status_success)
-        bs = rocsolver_zheevd(bh.h, rocblas_evect_original, rocblas_fill_upper, nb, gb.as<rocblas_double_complex>(),
-                              nb, lb, ew, inf);
-      if (bs == rocblas_status_success)
-        bs = rocsolver_zheevd(bh.h, rocblas_evect_original, rocblas_fill_upper, nt, gt.as<rocblas_double_complex>(),
-                              nt, lt, ew, inf + 1);
-      if (bs == rocblas_status_success)
-        bs = rocsolver_zheevd(bh.h, rocblas_evect_original, rocblas_fill_upper, np, gp.as<rocblas_double_complex>(),
-                              np, lp, ew, inf + 2);
-      if (bs != rocblas_status_success)
-        return bail(fail(FMM_ERR_DEVICE, "rocBLAS/rocSOLVER call failed for group %d: %s", g,
-                         rocblas_status_to_string(bs)));
-      if (hipMemcpyAsync(lam_h.data(), lb, sizeof(double) * ((size_t)nb_max + nt + np), hipMemcpyDeviceToHost, hs) !=
-              hipSuccess ||
-          hipMemcpyAsync(info_h, inf, sizeof(info_h), hipMemcpyDeviceToHost, hs) != hipSuccess ||
-          hipStreamSynchronize(hs) != hipSuccess)
-        return bail(fail(FMM_ERR_DEVICE, "eigenvalue copy failed"));
-      if (info_h[0] != 0 || info_h[1] != 0 || info_h[2] != 0)
-        return bail(fail(FMM_ERR_NUMERIC, "eigensolver did not converge for group %d polarisation %d", g, alpha));
-      auto desc = [](const double* a, int n) {
-        std::vector<double> v(n);
-        for (int i = 0; i < n; ++i) v[i] = a[n - 1 - i];
-        return v;
-      };
-      const std::vector<double> eb = desc(lam_h.data(), nb);
-      const std::vector<double> et = desc(lam_h.data() + nb_max, nt);
-      const std::vector<double> ep = desc(lam_h.data() + nb_max + nt, np);
-      double norm2 = 0.0;
-      for (double v : eb) norm2 += std::max(v, 0.0);
-      for (double v : eb)
-        if (!std::isfinite(v)) return bail(fail(FMM_ERR_NUMERIC, "non-finite far-field in group %d", g));
-      const double thr2 = gamma * gamma / 3.0 * norm2;
-      const int rb = truncation_rank(eb, thr2);
-      const int rt = truncation_rank(et, thr2);
-      const int rp = truncation_rank(ep, thr2);
-
-      // leading eigenvectors, largest first
-      if (launch_select_cols_rev(gb.p, nb, rb, vb.p, hs) != hipSuccess ||
-          launch_select_cols_rev(gt.p, nt, rt, ut.p, hs) != hipSuccess ||
-          launch_select_cols_rev(gp.p, np, rp, up.p, hs) != hipSuccess)
-        return bail(fail(FMM_ERR_DEVICE, "column select launch failed"));
-      // Y (nd x rb) = A^T conj(U^beta): the eigenvectors of conj(A A^H) are conj(U^beta)
-      bs = rocblas_zgemm(bh.h, rocblas_operation_none, rocblas_operation_none, nd, rb, nb, &cone, A_tp, nd,
-                         vb.as<rocblas_double_complex>(), nb, &czero, y.as<rocblas_double_complex>(), nd);
-      // Z_b (r_theta x n_phi) = U^theta^H Y_b^T for every b
-      if (bs == rocblas_status_success)
-        bs = rocblas_zgemm_strided_batched(bh.h, rocblas_operation_conjugate_transpose, rocblas_operation_transpose,
-                                           rt, np, nt, &cone, ut.as<rocblas_double_complex>(), nt, 0,
-                                           y.as<rocblas_double_complex>(), np, nd, &czero,
-                                           z.as<rocblas_double_complex>(), rt, (rocblas_stride)rt * np, rb);
-      // C_b^T (r_phi x r_theta) = U^phi^H Z_b^T: row-major [theta'][phi'] per b
-      if (bs == rocblas_status_success)
-        bs = rocblas_zgemm_strided_batched(bh.h, rocblas_operation_conjugate_transpose, rocblas_operation_transpose,
-                                           rp, rt, np, &cone, up.as<rocblas_double_complex>(), np, 0,
-                                           z.as<rocblas_double_complex>(), rt, (rocblas_stride)rt * np, &czero,
-                                           cb.as<rocblas_double_complex>(), rp, (rocblas_stride)rt * rp, rb);
-      if (bs != rocblas_status_success)
-        return bail(fail(FMM_ERR_DEVICE, "core projection failed for group %d: %s", g, rocblas_status_to_string(bs)));
-
-      TensorFactors tf;
-      tf.rt = rt;
-      tf.rp = rp;
-      tf.rb = rb;
-      std::vector<cd> vb_h((size_t)nb * rb), ut_h((size_t)nt * rt), up_h((size_t)np * rp), cb_h((size_t)rb * rt * rp);
-      if (hipMemcpyAsync(vb_h.data(), vb.p, cz * vb_h.size(), hipMemcpyDeviceToHost, hs) != hipSuccess ||
-          hipMemcpyAsync(ut_h.data(), ut.p, cz * ut_h.size(), hipMemcpyDeviceToHost, hs) != hipSuccess ||
-          hipMemcpyAsync(up_h.data(), up.p, cz * up_h.size(), hipMemcpyDeviceToHost, hs) != hipSuccess ||
-          hipMemcpyAsync(cb_h.data(), cb.p, cz * cb_h.size(), hipMemcpyDeviceToHost, hs) != hipSuccess ||
-          hipStreamSynchronize(hs) != hipSuccess)
-        return bail(fail(FMM_ERR_DEVICE, "factor copy failed"));
-      tf.ub.resize((size_t)nb * rb);
-      for (int n = 0; n < nb; ++n)
-        for (int b = 0; b < rb; ++b) tf.ub[(size_t)n * rb + b] = std::conj(vb_h[(size_t)b * nb + n]);
-      tf.ut.resize((size_t)nt * rt);
-      for (int i = 0; i < nt; ++i)
-        for (int a = 0; a < rt; ++a) tf.ut[(size_t)i * rt + a] = ut_h[(size_t)a * nt + i];
-      tf.up.resize((size_t)np * rp);
-      for (int j = 0; j < np; ++j)
-        for (int c = 0; c < rp; ++c) tf.up[(size_t)j * rp + c] = up_h[(size_t)c * np + j];
-      tf.core.resize((size_t)rt * rp * rb);
-      for (int b = 0; b < rb; ++b)
-        for (int a = 0; a < rt; ++a)
-          for (int c = 0; c < rp; ++c)
-            tf.core[((size_t)a * rp + c) * rb + b] = cb_h[(size_t)b * rt * rp + (size_t)a * rp + c];
-      h->t[2 * (size_t)g + alpha] = std::move(tf);
-    }
+    return fail(sh.status, "%s", sh.message.c_str());
   }
-  for (auto& s : h->slot) s.ready = false;
+  for (auto& s : (*inout)->slot) s.ready = false;
   return FMM_OK;
 }

@@ -67,6 +67,11 @@ __device__ __forceinline__ void paxpy(float4& o, float4 a, float2 s) {
 }
 __device__ __forceinline__ void paxpy(double2& o, double2 a, double2 s) { cfma(o, a, s); }
 
+__device__ __forceinline__ float4 padd(float4 a, float4 b) {
+  return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+}
+__device__ __forceinline__ double2 padd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
 template <typename P> __device__ __forceinline__ P pzero();
 template <> __device__ __forceinline__ float4 pzero<float4>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
 template <> __device__ __forceinline__ double2 pzero<double2>() { return make_double2(0.0, 0.0); }

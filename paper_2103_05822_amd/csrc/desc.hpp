@@ -34,6 +34,20 @@ struct TuckMax {
   int32_t t3;   // max of n_theta*r_phi or r_theta*n_phi intermediate
 };
 
+// Device pointers and sizes of one uploaded precision.
+//   order     : the 2G items, largest first
+//   pass_list : the 4G entries of a whole pass, largest first; entry e >= 0 is the
+//               aggregation of item e, e < 0 the disaggregation of item ~e
+struct TuckPlan {
+  const void* factors = nullptr;
+  const TuckItem* items = nullptr;
+  const int32_t* order = nullptr;
+  const int32_t* pass_list = nullptr;
+  int n_items = 0;
+  int64_t n_basis = 0;
+  TuckMax mx{};
+};
+
 // Dense plan: one group's rows.
 struct DenseGroup {
   int64_t row0;

@@ -54,11 +54,7 @@ struct PrecSlot {
   char* arena = nullptr;   // caller-owned device memory
   size_t bytes = 0;
   int device = -1;
-  const TuckItem* items = nullptr;     // device, inside the arena
-  const int32_t* agg_order = nullptr;  // device
-  const int32_t* dis_order = nullptr;  // device
-  const void* factors = nullptr;       // device, start of the factor area
-  TuckMax mx{};
+  TuckPlan plan;          // device pointers into the arena
 };
 
 }  // namespace tuckfmm

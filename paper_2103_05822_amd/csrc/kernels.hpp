@@ -6,23 +6,19 @@
 
 namespace tuckfmm {
 
-// Tucker aggregation / disaggregation, one workgroup per work item.
-//   fac   : base of the factor area (complex<T> elements)
-//   items : [2 * n_groups] descriptors, item 2g + alpha
-//   order : work list (item indices for aggregation, group indices for
-//           disaggregation), largest first
+// Tucker aggregation / disaggregation / whole pass over an uploaded plan.
 template <typename T>
-hipError_t launch_tucker_agg(const void* fac, const TuckItem* items, const int32_t* order, int n_items,
-                             const TuckMax& mx, int n_theta, int n_phi, int nrhs, const void* x, void* F,
+hipError_t launch_tucker_agg(const TuckPlan& pl, int n_theta, int n_phi, int nrhs, const void* x, void* F,
                              hipStream_t s);
 template <typename T>
-hipError_t launch_tucker_disagg(const void* fac, const TuckItem* items, const int32_t* order, int n_groups,
-                                const TuckMax& mx, int n_theta, int n_phi, int nrhs, const void* G, void* V,
+hipError_t launch_tucker_disagg(const TuckPlan& pl, int n_theta, int n_phi, int nrhs, const void* G, void* V,
                                 hipStream_t s);
 template <typename T>
-size_t tucker_agg_lds_bytes(const TuckMax& mx);
+hipError_t launch_tucker_pass(const TuckPlan& pl, int n_theta, int n_phi, int nrhs, const void* x, void* F,
+                              const void* G, void* V, hipStream_t s);
+// Largest dynamic LDS request of the Tucker kernels.
 template <typename T>
-size_t tucker_disagg_lds_bytes(const TuckMax& mx);
+size_t tucker_lds_bytes(const TuckMax& mx);
 
 // Dense (plain) aggregation / disaggregation.
 template <typename T>
@@ -38,6 +34,12 @@ hipError_t launch_farfield_fill(const double* rowdata, int64_t rows, const doubl
                                 void* out, hipStream_t s);
 
 // Precision conversion / packing helpers for setup.
+// Gram matrices of the theta and phi unfoldings of a slab [nb][nt][np] (column-major
+// outputs); `part` holds mode_gram_chunks(nb) * (nt*nt + np*np) complex values.
+constexpr int kGramRows = 8;
+int mode_gram_chunks(int nb);
+hipError_t launch_mode_gram(const void* slab, int nb, int nt, int np, void* part, void* gt, void* gp,
+                            hipStream_t s);
 hipError_t launch_select_cols_rev(const void* src, int n, int r, void* dst, hipStream_t s);
 hipError_t launch_gather_slab(const void* farfield, int64_t row0, int nb, int alpha, int n_theta, int n_phi,
                               void* out_tp, void* out_pt, hipStream_t s);

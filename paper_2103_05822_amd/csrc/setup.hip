@@ -73,7 +73,121 @@ __global__ __launch_bounds__(256) void select_cols_rev_kernel(const double2* __r
   }
 }
 
+// Gram matrices of the theta and phi unfoldings of one tensor held as a slab
+// s [nb][nt][np] (one n_theta x n_phi block S_n per basis function):
+//   Gt = sum_n S_n S_n^H  (nt x nt),   Gp = sum_n S_n^T conj(S_n)  (np x np).
+// Stage 1: workgroup (c, y) sums rows n of chunk c for 4x4 output tiles
+// y*512 .. y*512+511 (theta tiles first, then phi tiles) into part[c][.]
+// (entries [0, nt*nt) column-major Gt, then [nt*nt, nt*nt + np*np) column-major Gp).
+constexpr int kGramThreads = 512;
+__global__ __launch_bounds__(kGramThreads) void mode_gram_partial_kernel(const double2* __restrict__ s, int nb,
+                                                                         int nt, int np, int rows_per,
+                                                                         double2* __restrict__ part) {
+  extern __shared__ double2 slab[];  // nt * np
+  const int c = blockIdx.x;
+  const int n0 = c * rows_per, n1 = min(nb, n0 + rows_per);
+  const int tnt = (nt + 3) / 4, tnp = (np + 3) / 4;
+  const int tt = tnt * tnt, pt = tnp * tnp;
+  const int task = blockIdx.y * kGramThreads + threadIdx.x;
+  int kind = -1, bi = 0, bk = 0;
+  if (task < tt) {
+    kind = 0;
+    bi = task / tnt;
+    bk = task - bi * tnt;
+  } else if (task < tt + pt) {
+    kind = 1;
+    bi = (task - tt) / tnp;
+    bk = (task - tt) - bi * tnp;
+  }
+  double2 acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = make_double2(0.0, 0.0);
+  const int nd = nt * np;
+  for (int n = n0; n < n1; ++n) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < nd; e += kGramThreads) slab[e] = s[(int64_t)n * nd + e];
+    __syncthreads();
+    if (kind == 0) {
+      for (int j = 0; j < np; ++j) {
+        double2 a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = 4 * bi + u, k = 4 * bk + u;
+          a[u] = i < nt ? slab[i * np + j] : make_double2(0.0, 0.0);
+          b[u] = k < nt ? slab[k * np + j] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) cfma_conj(acc[u][v], b[v], a[u]);
+      }
+    } else if (kind == 1) {
+      for (int i = 0; i < nt; ++i) {
+        double2 a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = 4 * bi + u, l = 4 * bk + u;
+          a[u] = j < np ? slab[i * np + j] : make_double2(0.0, 0.0);
+          b[u] = l < np ? slab[i * np + l] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) cfma_conj(acc[u][v], b[v], a[u]);
+      }
+    }
+  }
+  if (kind < 0) return;
+  const int m = kind == 0 ? nt : np;
+  double2* out = part + (int64_t)c * (nt * nt + np * np) + (kind == 0 ? 0 : nt * nt);
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 4 * bi + u, q = 4 * bk + v;
+      if (r < m && q < m) out[r + (int64_t)q * m] = acc[u][v];  // column-major (r, q)
+    }
+}
+
+// Stage 2: Gt / Gp = sum of the parts in chunk order (deterministic).
+__global__ __launch_bounds__(256) void mode_gram_reduce_kernel(const double2* __restrict__ part, int nchunks,
+                                                               int nt, int np, double2* __restrict__ gt,
+                                                               double2* __restrict__ gp) {
+  const int total = nt * nt + np * np;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int c = 0; c < nchunks; ++c) {
+    const double2 v = part[(int64_t)c * total + e];
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  if (e < nt * nt) gt[e] = acc;
+  else gp[e - nt * nt] = acc;
+}
+
 }  // namespace
+
+int mode_gram_chunks(int nb) { return (nb + kGramRows - 1) / kGramRows; }
+
+hipError_t launch_mode_gram(const void* slab, int nb, int nt, int np, void* part, void* gt, void* gp,
+                            hipStream_t s) {
+  const int nchunks = mode_gram_chunks(nb);
+  const int tasks = ((nt + 3) / 4) * ((nt + 3) / 4) + ((np + 3) / 4) * ((np + 3) / 4);
+  dim3 grid(nchunks, (tasks + kGramThreads - 1) / kGramThreads);
+  const size_t lds = sizeof(double2) * (size_t)nt * np;
+  hipLaunchKernelGGL(mode_gram_partial_kernel, grid, dim3(kGramThreads), lds, s,
+                     static_cast<const double2*>(slab), nb, nt, np, kGramRows, static_cast<double2*>(part));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int total = nt * nt + np * np;
+  hipLaunchKernelGGL(mode_gram_reduce_kernel, dim3((total + 255) / 256), dim3(256), 0, s,
+                     static_cast<const double2*>(part), nchunks, nt, np, static_cast<double2*>(gt),
+                     static_cast<double2*>(gp));
+  return hipGetLastError();
+}
 
 hipError_t launch_select_cols_rev(const void* src, int n, int r, void* dst, hipStream_t s) {
   const int64_t total = (int64_t)n * r;

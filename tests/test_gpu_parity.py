@@ -146,6 +146,37 @@ def test_tucker_paper_grid_realistic_ranks(prec):
     assert max_rel(V, v_ref) < tol and l2_rel(V, v_ref) < tol
 
 
+@pytest.mark.parametrize("prec", [T.FMM_C128, T.FMM_C64], ids=["c128", "c64"])
+@pytest.mark.parametrize("nrhs", [1, 2])
+def test_tucker_pass_equals_separate_stages(prec, nrhs):
+    """The one-launch pass computes exactly what the two stage calls compute."""
+    import torch
+    lay = ragged_layout(6, 11)
+    tuck = random_tucker(lay, 50 + nrhs)
+    rng = synth.rng(8)
+    shp = (nrhs,) if nrhs > 1 else ()
+    x = synth.complex_normal(rng, (lay.n_basis,) + shp)
+    gin = synth.complex_normal(rng, (lay.n_groups, 2, lay.n_dir) + shp)
+    h = make_handle(lay, tuck)
+    try:
+        _, nbytes = T.fmm_tucker_storage_bytes(h, prec)
+        ar = arena(nbytes)
+        T.fmm_tucker_upload(h, prec, ar)
+        xd, gd = dev(x, CDT[prec]), dev(gin, CDT[prec])
+        F1, F2 = dev(np.zeros(gin.shape, CDT[prec])), dev(np.zeros(gin.shape, CDT[prec]))
+        V1, V2 = dev(np.full(x.shape, 7.0, CDT[prec])), dev(np.full(x.shape, 7.0, CDT[prec]))
+        banner("tucker pass vs stages prec=%d nrhs=%d" % (prec, nrhs))
+        T.fmm_tucker_aggregate(h, prec, nrhs, xd, F1)
+        T.fmm_tucker_disaggregate(h, prec, nrhs, gd, V1)
+        T.fmm_tucker_pass(h, prec, nrhs, xd, F2, gd, V2)
+        assert np.array_equal(host(F1), host(F2))
+        assert np.array_equal(host(V1), host(V2))
+        f_ref, v_ref = oracle_tucker(lay, tuck, x, gin)
+        assert l2_rel(host(F2), f_ref) < TOL[prec] and l2_rel(host(V2), v_ref) < TOL[prec]
+    finally:
+        T.fmm_tucker_destroy(h)
+
+
 def test_tucker_deterministic_and_graph_replays():
     import torch
     lay = ragged_layout(6, 11)
