@@ -45,6 +45,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU timing")
     p.add_argument("--no-oracle", action="store_true", help="skip accuracy sampling and the CPU baseline")
     p.add_argument("--no-dense", action="store_true", help="Tucker stages only (profiling runs)")
+    p.add_argument("--save-factors", default=None, help="write the compressed factors to this .npz")
+    p.add_argument("--load-factors", default=None, help="read the factors from this .npz instead of compressing")
     return p.parse_args()
 
 
@@ -67,6 +69,29 @@ def dense_stage_bytes(offsets, n_theta, n_phi, es):
     n = int(offsets[-1])
     g = offsets.size - 1
     return int(es * (n * 2 * n_theta * n_phi + n + 2 * g * n_theta * n_phi))
+
+
+def save_factors(T, h, lay, ranks, path):
+    """All (group, polarisation) factors in the ABI's shapes, FP64, one .npz."""
+    arrs = {"ranks": ranks, "offsets": lay.offsets, "grid": np.array([lay.n_theta, lay.n_phi])}
+    for g in range(lay.n_groups):
+        nb = int(lay.offsets[g + 1] - lay.offsets[g])
+        for a in range(2):
+            c, ut, up, ub = T.fmm_tucker_export(h, g, a, ranks[g, a], lay.n_theta, lay.n_phi, nb)
+            arrs["%d_%d_c" % (g, a)], arrs["%d_%d_t" % (g, a)] = c, ut
+            arrs["%d_%d_p" % (g, a)], arrs["%d_%d_b" % (g, a)] = up, ub
+    np.savez(path, **arrs)
+
+
+def load_factors(T, lay, path):
+    z = np.load(path)
+    assert np.array_equal(z["offsets"], lay.offsets), "factor file is for another layout"
+    h = T.fmm_tucker_create(lay)
+    for g in range(lay.n_groups):
+        for a in range(2):
+            T.fmm_tucker_set_group(h, g, a, z["%d_%d_c" % (g, a)], z["%d_%d_t" % (g, a)],
+                                   z["%d_%d_p" % (g, a)], z["%d_%d_b" % (g, a)])
+    return h
 
 
 def main():
@@ -96,9 +121,22 @@ def main():
     T.fmm_farfield_fill(geom, 0, G, dense)
     torch.cuda.synchronize()
     t0 = time.time()
-    h = T.fmm_farfield_compress(lay, dense, 0, G, w.gamma)
+    if args.load_factors:
+        h = load_factors(T, lay, args.load_factors)
+        log("factors loaded from %s (%.1f s)" % (args.load_factors, time.time() - t0))
+    else:
+        h = None
+        chunk = 128
+        for g0 in range(0, G, chunk):   # group chunks, so progress shows during long setups
+            cnt = min(chunk, G - g0)
+            rows0 = int(lay.offsets[g0])
+            h = T.fmm_farfield_compress(lay, dense[rows0:], g0, cnt, w.gamma, handle=h)
+            log("compress: groups %d..%d done (%.1f s)" % (g0, g0 + cnt - 1, time.time() - t0))
     t_compress = time.time() - t0
     ranks = T.fmm_tucker_ranks(h, G)
+    if args.save_factors:
+        save_factors(T, h, lay, ranks, args.save_factors)
+        log("factors saved to %s" % args.save_factors)
     log("compress: %.1f s, mean ranks %s" % (t_compress, ranks.reshape(-1, 3).mean(0).round(1)))
     arenas = {}
     for prec in (T.FMM_C64,):
@@ -164,6 +202,19 @@ def main():
         ms[name] = float(np.mean([a.elapsed_time(b) for a, b in evs]))
     log("stage ms: %s" % {k: round(v, 4) for k, v in ms.items()})
 
+    # practical-bandwidth reference: a plain 2 GiB device-to-device copy
+    csrc = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")
+    cdst = torch.empty_like(csrc)
+    cdst.copy_(csrc)
+    cev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+    for a, b in cev:
+        a.record()
+        cdst.copy_(csrc)
+        b.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * csrc.numel() / (min(a.elapsed_time(b) for a, b in cev) * 1e-3) / 1e9
+    del csrc, cdst
+
     b_t32, fac32 = tucker_stage_bytes(ranks, lay.offsets, w.n_theta, w.n_phi, 8)
     b_d64 = dense_stage_bytes(lay.offsets, w.n_theta, w.n_phi, 16)
     per_stage_bytes = {"tucker_pass_f32": 2 * b_t32, "tucker_agg_f32": b_t32, "tucker_disagg_f32": b_t32,
@@ -195,6 +246,7 @@ def main():
                      "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(gbs[dom] / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_launch": per_stage_bytes[dom]},
+        "copy_GBps": round(copy_gbs, 1),
         "memory_MB": {"tucker_factors_f32": round(fac32 / 2 ** 20, 1),
                       "dense_f64": round(2 * N * nd * 16 / 2 ** 20, 1)},
         "ranks_mean": [round(float(v), 2) for v in ranks.reshape(-1, 3).mean(0)],

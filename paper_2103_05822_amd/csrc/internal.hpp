@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/tuckfmm.h"
+#include "tuckfmm.h"
 #include "desc.hpp"
 
 namespace tuckfmm {

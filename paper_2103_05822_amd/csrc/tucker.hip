@@ -5,10 +5,7 @@
 // streamed once from HBM with 16-byte coalesced loads; every intermediate stays in
 // LDS.  Work lists are sorted by decreasing cost, so the hardware dispatcher hands
 // out the largest items first (longest-processing-time order).  The pass kernel
-// runs the aggregation and disaggregation items of all groups in one launch: the
-// angular phases of some workgroups (small LDS products, no HBM traffic) overlap
-// with the streaming phases of others, and small items of either stage fill the
-// end of the launch.
+// runs the aggregation and disaggregation items of all groups in one launch.
 //
 // Aggregation of item (g, alpha), contraction order chosen per item on the host:
 //   y[b]    = sum_n U^beta[n][b] x[n]          row-dot of each U^beta^T row (one
@@ -163,6 +160,49 @@ __device__ __forceinline__ void block_colaxpy(const typename Tr<T>::c* rows, int
   }
 }
 
+// out(m, n) = sum_k a(m, k) * b(k, n) for m < M, n < N: a small complex product
+// computed by the whole workgroup in tiles of four rows per thread, n across
+// threads, so that a(m, k) is a broadcast load shared by the four accumulators and
+// b(k, n) a coalesced load.
+template <typename C, class FA, class FB, class FO>
+__device__ __forceinline__ void tile_product(int M, int N, int K, FA a, FB b, FO out, int tid) {
+  const int tasks = (M + 3) / 4 * N;
+  for (int task = tid; task < tasks; task += kThreads) {
+    const int m0 = task / N * 4, n = task - task / N * N;
+    C acc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = czero<C>();
+    if (m0 + 3 < M) {
+      int k = 0;
+      for (; k + 1 < K; k += 2) {
+        const C b0 = b(k, n), b1 = b(k + 1, n);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          cfma(acc[u], a(m0 + u, k), b0);
+          cfma(acc[u], a(m0 + u, k + 1), b1);
+        }
+      }
+      if (k < K) {
+        const C b0 = b(k, n);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cfma(acc[u], a(m0 + u, k), b0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) out(m0 + u, n, acc[u]);
+    } else {
+      for (int k = 0; k < K; ++k) {
+        const C b0 = b(k, n);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (m0 + u < M) cfma(acc[u], a(m0 + u, k), b0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (m0 + u < M) out(m0 + u, n, acc[u]);
+    }
+  }
+}
+
 __device__ __forceinline__ void atomic_add_c(float2* p, float2 v) {
   atomicAdd(&p->x, v.x);
   atomicAdd(&p->y, v.y);
@@ -174,18 +214,19 @@ __device__ __forceinline__ void atomic_add_c(double2* p, double2 v) {
 
 // ------------------------------------------------------------------ aggregation
 
+// Streaming phase: y = U^beta^T x (row-dots), then t = core^T y (column axpy) written
+// as packs to `t_out` in LDS.  t[q], q = theta' r_phi + phi'.
 template <typename T>
-__device__ __forceinline__ void agg_item(const typename Tr<T>::c* __restrict__ fac, const TuckItem& it,
-                                         const Lds<T>& L, unsigned char* smem, int n_theta, int n_phi, int nrhs,
-                                         int r, const typename Tr<T>::c* __restrict__ x,
-                                         typename Tr<T>::c* __restrict__ F) {
+__device__ __forceinline__ void agg_stream(const typename Tr<T>::c* __restrict__ fac, const TuckItem& it,
+                                           const Lds<T>& L, unsigned char* smem, int nrhs, int r,
+                                           const typename Tr<T>::c* __restrict__ x, typename Tr<T>::c* t_out) {
   using C = typename Tr<T>::c;
   using P = typename Tr<T>::pack;
   constexpr int E = Tr<T>::E;
-  C* xs = reinterpret_cast<C*>(smem);  // x, then t
-  C* ys = xs + L.r1;                   // y, then the angular intermediate
+  C* xs = reinterpret_cast<C*>(smem);
+  C* ys = xs + L.r1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nb = it.nb, rb = it.rb, rt = it.rt, rp = it.rp, Q = rt * rp;
+  const int nb = it.nb, rb = it.rb, Q = it.rt * it.rp;
   const int nbp = round_up(nb, E);
 
   // x of the group into LDS (zero padded to whole packs)
@@ -197,9 +238,8 @@ __device__ __forceinline__ void agg_item(const typename Tr<T>::c* __restrict__ f
                   lane);
   __syncthreads();
 
-  // t = core^T y   (t[q], q = theta' * r_phi + phi'), written over x (no longer read)
+  // t = core^T y; t_out may alias x, which is no longer read
   const int qpk = round_up(Q, E) / E;
-  C* ts = xs;
   for (int base = 0; base < qpk; base += kThreads * kColPacks) {
     P acc[kColPacks];
 #pragma unroll
@@ -208,113 +248,114 @@ __device__ __forceinline__ void agg_item(const typename Tr<T>::c* __restrict__ f
 #pragma unroll
     for (int j = 0; j < kColPacks; ++j) {
       const int p = base + tid + kThreads * j;
-      if (p < qpk) reinterpret_cast<P*>(ts)[p] = acc[j];
+      if (p < qpk) reinterpret_cast<P*>(t_out)[p] = acc[j];
     }
   }
-  __syncthreads();
+}
 
-  // angular stages; y is free now and holds the intermediate
+// Angular phase: F = U^theta t U^phi^T from t in LDS (`ts`); the intermediate uses
+// LDS region r2.
+template <typename T>
+__device__ __forceinline__ void agg_angular(const typename Tr<T>::c* __restrict__ fac, const TuckItem& it,
+                                            const Lds<T>& L, unsigned char* smem, const typename Tr<T>::c* ts,
+                                            int n_theta, int n_phi, int nrhs, int r,
+                                            typename Tr<T>::c* __restrict__ F) {
+  using C = typename Tr<T>::c;
+  C* t3 = reinterpret_cast<C*>(smem) + L.r1;
+  const int tid = threadIdx.x;
+  const int rt = it.rt, rp = it.rp;
   const C* ut = fac + it.off_ut;    // [n_theta][rt]
   const C* upt = fac + it.off_upt;  // [rp][n_phi]
-  C* t3 = ys;
   const int ndir = n_theta * n_phi;
   C* Fo = F + ((int64_t)(it.group * 2 + it.alpha) * ndir) * nrhs + r;
   if (it.theta_first) {
     // t3[i][c] = sum_a U^theta[i][a] t[a][c]           (n_theta x r_phi)
-    for (int o = tid; o < n_theta * rp; o += kThreads) {
-      const int i = o / rp, c = o - i * rp;
-      C acc = czero<C>();
-      for (int a = 0; a < rt; ++a) cfma(acc, ut[i * rt + a], ts[a * rp + c]);
-      t3[o] = acc;
-    }
+    tile_product<C>(
+        n_theta, rp, rt, [&](int i, int a) { return ut[i * rt + a]; }, [&](int a, int c) { return ts[a * rp + c]; },
+        [&](int i, int c, C v) { t3[i * rp + c] = v; }, tid);
     __syncthreads();
     // F[i][j] = sum_c t3[i][c] U^phi[j][c]
-    for (int o = tid; o < ndir; o += kThreads) {
-      const int i = o / n_phi, j = o - i * n_phi;
-      C acc = czero<C>();
-      for (int c = 0; c < rp; ++c) cfma(acc, t3[i * rp + c], upt[c * n_phi + j]);
-      Fo[(int64_t)o * nrhs] = acc;
-    }
+    tile_product<C>(
+        n_theta, n_phi, rp, [&](int i, int c) { return t3[i * rp + c]; },
+        [&](int c, int j) { return upt[c * n_phi + j]; },
+        [&](int i, int j, C v) { Fo[(int64_t)(i * n_phi + j) * nrhs] = v; }, tid);
   } else {
     // t3[a][j] = sum_c t[a][c] U^phi[j][c]             (r_theta x n_phi)
-    for (int o = tid; o < rt * n_phi; o += kThreads) {
-      const int a = o / n_phi, j = o - a * n_phi;
-      C acc = czero<C>();
-      for (int c = 0; c < rp; ++c) cfma(acc, ts[a * rp + c], upt[c * n_phi + j]);
-      t3[o] = acc;
-    }
+    tile_product<C>(
+        rt, n_phi, rp, [&](int a, int c) { return ts[a * rp + c]; }, [&](int c, int j) { return upt[c * n_phi + j]; },
+        [&](int a, int j, C v) { t3[a * n_phi + j] = v; }, tid);
     __syncthreads();
     // F[i][j] = sum_a U^theta[i][a] t3[a][j]
-    for (int o = tid; o < ndir; o += kThreads) {
-      const int i = o / n_phi, j = o - i * n_phi;
-      C acc = czero<C>();
-      for (int a = 0; a < rt; ++a) cfma(acc, ut[i * rt + a], t3[a * n_phi + j]);
-      Fo[(int64_t)o * nrhs] = acc;
-    }
+    tile_product<C>(
+        n_theta, n_phi, rt, [&](int i, int a) { return ut[i * rt + a]; },
+        [&](int a, int j) { return t3[a * n_phi + j]; },
+        [&](int i, int j, C v) { Fo[(int64_t)(i * n_phi + j) * nrhs] = v; }, tid);
   }
 }
 
 // --------------------------------------------------------------- disaggregation
 
+// Angular phase: S = U^theta^T conj(G) U^phi, written with its pack padding to
+// `S2` in LDS.  With zero_v the item also clears its rows of V.
 template <typename T>
-__device__ __forceinline__ void dis_item(const typename Tr<T>::c* __restrict__ fac, const TuckItem& it,
-                                         const Lds<T>& L, unsigned char* smem, int n_theta, int n_phi, int nrhs,
-                                         int r, const typename Tr<T>::c* __restrict__ Gin,
-                                         typename Tr<T>::c* __restrict__ V) {
+__device__ __forceinline__ void dis_angular(const typename Tr<T>::c* __restrict__ fac, const TuckItem& it,
+                                            const Lds<T>& L, unsigned char* smem, int n_theta, int n_phi,
+                                            int nrhs, int r, const typename Tr<T>::c* __restrict__ Gin,
+                                            typename Tr<T>::c* S2, bool zero_v, typename Tr<T>::c* __restrict__ V) {
   using C = typename Tr<T>::c;
-  using P = typename Tr<T>::pack;
   constexpr int E = Tr<T>::E;
   C* s1 = reinterpret_cast<C*>(smem);
-  C* S2 = s1 + L.s1;
-  C* s3 = S2 + L.s2;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   const int ndir = n_theta * n_phi;
-  const int rt = it.rt, rp = it.rp, rb = it.rb, Q = rt * rp;
+  const int rt = it.rt, rp = it.rp, Q = rt * rp;
   const C* ut = fac + it.off_ut;  // [n_theta][rt]
   const C* up = fac + it.off_up;  // [n_phi][rp]
   const C* Gi = Gin + ((int64_t)(it.group * 2 + it.alpha) * ndir) * nrhs + r;
+  if (zero_v)
+    for (int n = tid; n < it.nb; n += kThreads) V[(it.row0 + n) * nrhs + r] = czero<C>();
   // the angular order mirrors the aggregation choice
   if (!it.theta_first) {
     // s1[a][j] = sum_i U^theta[i][a] conj(G[i][j])     (r_theta x n_phi)
-    for (int o = tid; o < rt * n_phi; o += kThreads) {
-      const int a = o / n_phi, j = o - a * n_phi;
-      C acc = czero<C>();
-      for (int i = 0; i < n_theta; ++i) cfma(acc, ut[i * rt + a], conjc(Gi[(int64_t)(i * n_phi + j) * nrhs]));
-      s1[o] = acc;
-    }
+    tile_product<C>(
+        rt, n_phi, n_theta, [&](int a, int i) { return ut[i * rt + a]; },
+        [&](int i, int j) { return conjc(Gi[(int64_t)(i * n_phi + j) * nrhs]); },
+        [&](int a, int j, C v) { s1[a * n_phi + j] = v; }, tid);
     __syncthreads();
     // S[a][c] = sum_j s1[a][j] U^phi[j][c]
-    for (int o = tid; o < Q; o += kThreads) {
-      const int a = o / rp, c = o - a * rp;
-      C acc = czero<C>();
-      for (int j = 0; j < n_phi; ++j) cfma(acc, s1[a * n_phi + j], up[j * rp + c]);
-      S2[o] = acc;
-    }
+    tile_product<C>(
+        rt, rp, n_phi, [&](int a, int j) { return s1[a * n_phi + j]; }, [&](int j, int c) { return up[j * rp + c]; },
+        [&](int a, int c, C v) { S2[a * rp + c] = v; }, tid);
   } else {
     // s1[i][c] = sum_j conj(G[i][j]) U^phi[j][c]       (n_theta x r_phi)
-    for (int o = tid; o < n_theta * rp; o += kThreads) {
-      const int i = o / rp, c = o - i * rp;
-      C acc = czero<C>();
-      for (int j = 0; j < n_phi; ++j) cfma(acc, up[j * rp + c], conjc(Gi[(int64_t)(i * n_phi + j) * nrhs]));
-      s1[o] = acc;
-    }
+    tile_product<C>(
+        n_theta, rp, n_phi, [&](int i, int j) { return conjc(Gi[(int64_t)(i * n_phi + j) * nrhs]); },
+        [&](int j, int c) { return up[j * rp + c]; }, [&](int i, int c, C v) { s1[i * rp + c] = v; }, tid);
     __syncthreads();
     // S[a][c] = sum_i U^theta[i][a] s1[i][c]
-    for (int o = tid; o < Q; o += kThreads) {
-      const int a = o / rp, c = o - a * rp;
-      C acc = czero<C>();
-      for (int i = 0; i < n_theta; ++i) cfma(acc, ut[i * rt + a], s1[i * rp + c]);
-      S2[o] = acc;
-    }
+    tile_product<C>(
+        rt, rp, n_theta, [&](int a, int i) { return ut[i * rt + a]; }, [&](int i, int c) { return s1[i * rp + c]; },
+        [&](int a, int c, C v) { S2[a * rp + c] = v; }, tid);
   }
   for (int o = Q + tid; o < round_up(Q, E); o += kThreads) S2[o] = czero<C>();  // pack padding
-  __syncthreads();
+}
 
+// Streaming phase: s = core S (row-dots) with S in LDS region s2, then
+// V[n] += conj(sum_b U^beta[n][b] s[b]) (column axpy, atomic adds).
+template <typename T>
+__device__ __forceinline__ void dis_stream(const typename Tr<T>::c* __restrict__ fac, const TuckItem& it,
+                                           const Lds<T>& L, unsigned char* smem, int nrhs, int r,
+                                           typename Tr<T>::c* __restrict__ V) {
+  using C = typename Tr<T>::c;
+  using P = typename Tr<T>::pack;
+  constexpr int E = Tr<T>::E;
+  C* S2 = reinterpret_cast<C*>(smem) + L.s1;
+  C* s3 = S2 + L.s2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rb = it.rb, Q = it.rt * it.rp;
   // s[b] = sum_q core[b][q] S[q]
   wave_rowdots<T>(fac + it.off_core, it.ld_c, wave, rb, kWaves, reinterpret_cast<const P*>(S2),
                   round_up(Q, E) / E, s3, lane);
   __syncthreads();
-
   // V[n] += conj(sum_b U^beta[n][b] s[b])
   const int nb = it.nb;
   const int npk = round_up(nb, E) / E;
@@ -348,9 +389,14 @@ __global__ __launch_bounds__(kThreads) void tucker_agg_kernel(const typename Tr<
                                                               int n_theta, int n_phi, int nrhs,
                                                               const typename Tr<T>::c* __restrict__ x,
                                                               typename Tr<T>::c* __restrict__ F) {
+  using C = typename Tr<T>::c;
   extern __shared__ __align__(16) unsigned char smem[];
   const TuckItem it = items[order[blockIdx.x]];
-  agg_item<T>(fac, it, Lds<T>(mx), smem, n_theta, n_phi, nrhs, blockIdx.y, x, F);
+  const Lds<T> L(mx);
+  C* ts = reinterpret_cast<C*>(smem);  // t over x
+  agg_stream<T>(fac, it, L, smem, nrhs, blockIdx.y, x, ts);
+  __syncthreads();
+  agg_angular<T>(fac, it, L, smem, ts, n_theta, n_phi, nrhs, blockIdx.y, F);
 }
 
 template <typename T>
@@ -360,13 +406,19 @@ __global__ __launch_bounds__(kThreads) void tucker_dis_kernel(const typename Tr<
                                                               int n_theta, int n_phi, int nrhs,
                                                               const typename Tr<T>::c* __restrict__ G,
                                                               typename Tr<T>::c* __restrict__ V) {
+  using C = typename Tr<T>::c;
   extern __shared__ __align__(16) unsigned char smem[];
   const TuckItem it = items[order[blockIdx.x]];
-  dis_item<T>(fac, it, Lds<T>(mx), smem, n_theta, n_phi, nrhs, blockIdx.y, G, V);
+  const Lds<T> L(mx);
+  dis_angular<T>(fac, it, L, smem, n_theta, n_phi, nrhs, blockIdx.y, G, reinterpret_cast<C*>(smem) + L.s1, false, V);
+  __syncthreads();
+  dis_stream<T>(fac, it, L, smem, nrhs, blockIdx.y, V);
 }
 
 // One launch for a whole aggregation + disaggregation pass: work-list entry e is
-// aggregation item e if e >= 0 and disaggregation item ~e otherwise.
+// aggregation item e if e >= 0 and disaggregation item ~e otherwise.  Both stages'
+// items interleave in one longest-first list, so small items of either stage fill
+// the end of the launch.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void tucker_pass_kernel(const typename Tr<T>::c* __restrict__ fac,
                                                                const TuckItem* __restrict__ items,
@@ -376,15 +428,22 @@ __global__ __launch_bounds__(kThreads) void tucker_pass_kernel(const typename Tr
                                                                typename Tr<T>::c* __restrict__ F,
                                                                const typename Tr<T>::c* __restrict__ G,
                                                                typename Tr<T>::c* __restrict__ V) {
+  using C = typename Tr<T>::c;
   extern __shared__ __align__(16) unsigned char smem[];
   const int32_t e = list[blockIdx.x];
   const Lds<T> L(mx);
+  const int r = blockIdx.y;
   if (e >= 0) {
     const TuckItem it = items[e];
-    agg_item<T>(fac, it, L, smem, n_theta, n_phi, nrhs, blockIdx.y, x, F);
+    C* ts = reinterpret_cast<C*>(smem);  // t over x
+    agg_stream<T>(fac, it, L, smem, nrhs, r, x, ts);
+    __syncthreads();
+    agg_angular<T>(fac, it, L, smem, ts, n_theta, n_phi, nrhs, r, F);
   } else {
     const TuckItem it = items[~e];
-    dis_item<T>(fac, it, L, smem, n_theta, n_phi, nrhs, blockIdx.y, G, V);
+    dis_angular<T>(fac, it, L, smem, n_theta, n_phi, nrhs, r, G, reinterpret_cast<C*>(smem) + L.s1, false, V);
+    __syncthreads();
+    dis_stream<T>(fac, it, L, smem, nrhs, r, V);
   }
 }
 
