@@ -52,12 +52,26 @@ typedef enum {
 } fmm_status;
 
 /* Storage / arithmetic precision of a compute path.
- *   FMM_C128   complex128 storage, FP64 arithmetic; x, F, G, V are complex128.
- *   FMM_C64    complex64 storage,  FP32 arithmetic; x, F, G, V are complex64.
- *   FMM_BF16X2 factors stored as bf16 hi + lo pairs (same 8 bytes per complex as
- *              complex64) for the matrix-core path, FP32 accumulation; x, F, G, V
- *              are complex64.
- *   FMM_BF16X3 as FMM_BF16X2 with a third (hi, mid, lo) term.                   */
+ *   FMM_C128   complex128 factors, FP64 arithmetic; x, F, G, V are complex128.
+ *   FMM_C64    complex64 factors, FP32 arithmetic; x, F, G, V are complex64.
+ *   FMM_BF16X2 complex64 factors and vectors; the products run on the bf16 matrix
+ *              cores: every FP32 operand is split into two bf16 pieces (hi + lo) and
+ *              each product accumulates hi*hi + hi*lo + lo*hi in FP32 (relative
+ *              error of a product about 2^-16).  Needs an even nrhs.
+ *   FMM_BF16X3 as FMM_BF16X2 with three pieces (hi + mid + lo) and the six products
+ *              down to order 2^-16 (FP32-level error).  Needs an even nrhs.
+ *
+ * Kernels.  FMM_C128 always runs the streaming kernels (one workgroup per
+ * (group, polarisation, right-hand side), factors streamed from HBM once per
+ * right-hand side).  FMM_C64 runs the streaming kernels for an odd nrhs or
+ * nrhs < 8 and the FP32 matrix-core products otherwise, unless fmm_tucker_tune chose
+ * differently for that nrhs.  The matrix-core path computes every contraction of
+ * Section II.C as one grouped complex GEMM over all (group, polarisation) items for a
+ * chunk of right-hand sides (factors read once per chunk); it needs 16-byte aligned
+ * vectors and keeps library-owned device tables and scratch per nrhs (freed by a new
+ * upload, fmm_tucker_set_group or fmm_tucker_destroy).  Calls of one handle and
+ * precision that use the matrix-core path share that scratch: they must not run
+ * concurrently on different streams. */
 typedef enum { FMM_C128 = 0, FMM_C64 = 1, FMM_BF16X2 = 2, FMM_BF16X3 = 3 } fmm_prec;
 
 /* Problem layout shared by every group-wise call. */
@@ -192,20 +206,41 @@ fmm_status fmm_tucker_aggregate(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, con
 fmm_status fmm_tucker_disaggregate(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* G, void* V,
                                    void* stream);
 
-/* One aggregation + disaggregation pass in a single launch: F = aggregation of x and
- * V = disaggregation of G exactly as fmm_tucker_aggregate and fmm_tucker_disaggregate
- * compute them (same arithmetic, bitwise equal results), with the work items of both
- * stages interleaved in one longest-first work list.  F must not alias G, x or V. */
+/* One aggregation + disaggregation pass: F = aggregation of x and V = disaggregation
+ * of G exactly as fmm_tucker_aggregate and fmm_tucker_disaggregate compute them (same
+ * arithmetic, bitwise equal results), with the work of both stages interleaved in
+ * longest-first work lists (streaming kernels: one launch; matrix-core path: four
+ * grouped launches per chunk of right-hand sides).  F must not alias G, x or V. */
 fmm_status fmm_tucker_pass(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F, const void* G,
                            void* V, void* stream);
 
 /* Capture fmm_tucker_pass with these buffers into a HIP graph owned by the handle,
- * replacing a previous capture.  Buffers must stay valid while the graph is used. */
+ * replacing a previous capture (device tables are built before the capture starts).
+ * Buffers must stay valid while the graph is used.  A new upload, set_group or tune
+ * call drops the graph (fmm_graph_launch then returns FMM_ERR_STATE). */
 fmm_status fmm_graph_capture(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F,
                              const void* G, void* V, void* stream);
 
 /* Launch the captured pass on `stream`. */
 fmm_status fmm_graph_launch(fmm_tucker_t h, void* stream);
+
+/* Result of fmm_tucker_tune: path 0 = streaming kernels, 1 = matrix-core products
+ * with `tile_steps` K steps per workgroup and `rhs_chunk` right-hand sides per chunk;
+ * ms = mean time of one pass of the winner. */
+typedef struct {
+  int32_t path;
+  int32_t tile_steps;
+  int32_t rhs_chunk;
+  float ms;
+} fmm_tune_result;
+
+/* Autotuner: times fmm_tucker_pass with these buffers under each candidate
+ * configuration for (prec, nrhs) (1 warm-up + 3 timed passes each, HIP events on the
+ * stream), keeps the fastest for later calls with this nrhs and reports it in *out
+ * (may be NULL).  Overwrites F and V; synchronises the stream; drops a captured graph.
+ * Not allowed while the stream is capturing. */
+fmm_status fmm_tucker_tune(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F, const void* G,
+                           void* V, void* stream, fmm_tune_result* out);
 
 void fmm_tucker_destroy(fmm_tucker_t h);
 

@@ -23,7 +23,7 @@ __all__ = [
     "fmm_geometry_destroy", "fmm_tucker_create", "fmm_farfield_compress", "fmm_tucker_set_group",
     "fmm_tucker_ranks", "fmm_tucker_export", "fmm_tucker_storage_bytes", "fmm_tucker_upload",
     "fmm_tucker_aggregate", "fmm_tucker_disaggregate", "fmm_tucker_pass", "fmm_graph_capture", "fmm_graph_launch",
-    "fmm_tucker_destroy", "fmm_dense_create", "fmm_dense_aggregate", "fmm_dense_disaggregate",
+    "fmm_tucker_tune", "fmm_tucker_destroy", "fmm_dense_create", "fmm_dense_aggregate", "fmm_dense_disaggregate",
     "fmm_dense_destroy",
 ]
 
@@ -55,6 +55,11 @@ class fmm_layout(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("offsets", ctypes.POINTER(ctypes.c_int64))]
 
 
+class fmm_tune_result(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("tile_steps", ctypes.c_int32), ("rhs_chunk", ctypes.c_int32),
+                ("ms", ctypes.c_float)]
+
+
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
 _i64 = ctypes.c_int64
@@ -84,6 +89,7 @@ _SIGS = {
     "fmm_tucker_pass": (_st, [_vp, _st, _i32, _vp, _vp, _vp, _vp, _vp]),
     "fmm_graph_capture": (_st, [_vp, _st, _i32, _vp, _vp, _vp, _vp, _vp]),
     "fmm_graph_launch": (_st, [_vp, _vp]),
+    "fmm_tucker_tune": (_st, [_vp, _st, _i32, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(fmm_tune_result)]),
     "fmm_tucker_destroy": (None, [_vp]),
     "fmm_dense_create": (_st, [ctypes.POINTER(fmm_layout), ctypes.POINTER(_vp)]),
     "fmm_dense_aggregate": (_st, [_vp, _st, _vp, _i32, _vp, _vp, _vp]),
@@ -284,6 +290,14 @@ def fmm_graph_capture(h, prec, nrhs, x, F, G, V, stream):
 
 def fmm_graph_launch(h, stream=None):
     _check(_lib.fmm_graph_launch(h, _stream(stream)))
+
+
+def fmm_tucker_tune(h, prec, nrhs, x, F, G, V, stream=None):
+    """Returns a dict with the chosen path, tile_steps, rhs_chunk and ms per pass."""
+    r = fmm_tune_result()
+    _check(_lib.fmm_tucker_tune(h, int(prec), int(nrhs), _ptr(x), _ptr(F), _ptr(G), _ptr(V), _stream(stream),
+                                ctypes.byref(r)))
+    return {"path": r.path, "tile_steps": r.tile_steps, "rhs_chunk": r.rhs_chunk, "ms": r.ms}
 
 
 def fmm_tucker_destroy(h):

@@ -66,10 +66,14 @@ using namespace tuckfmm;
 
 namespace {
 
-size_t elem_bytes(fmm_prec p) { return p == FMM_C128 ? 16 : (p == FMM_BF16X3 ? 12 : 8); }
+// Every precision but FMM_C128 stores complex64 factors and takes complex64 vectors.
+size_t elem_bytes(fmm_prec p) { return p == FMM_C128 ? 16 : 8; }
 int pack_elems(fmm_prec p) { return p == FMM_C128 ? 1 : 2; }
 bool prec_valid(int p) { return p >= FMM_C128 && p <= FMM_BF16X3; }
-bool prec_has_kernels(fmm_prec p) { return p == FMM_C128 || p == FMM_C64; }
+bool prec_is_split(fmm_prec p) { return p == FMM_BF16X2 || p == FMM_BF16X3; }
+
+// Smallest even nrhs for which FMM_C64 takes the matrix-core products when untuned.
+constexpr int kMfmaMinRhs = 8;
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 bool aligned(const void* p, size_t a) { return reinterpret_cast<uintptr_t>(p) % a == 0; }
@@ -91,7 +95,7 @@ fmm_status plan_arena(const fmm_tucker_s* h, fmm_prec prec, ArenaPlan* P) {
   const int G = L.n_groups;
   const size_t es = elem_bytes(prec);
   const int E = pack_elems(prec);
-  const size_t blk_align = es == 12 ? 768 : 256;  // a multiple of both 256 bytes and the element size
+  const size_t blk_align = 256;
   P->items.resize((size_t)2 * G);
   size_t off = 0;  // bytes inside the factor area
   auto block = [&](size_t n_el) {
@@ -198,7 +202,6 @@ fmm_status ready_slot(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, PrecSlot** ou
   if (nrhs < 1 || nrhs > 65535) return fail(FMM_ERR_ARG, "nrhs must be in [1, 65535]");
   PrecSlot& s = h->slot[prec];
   if (!s.ready) return fail(FMM_ERR_STATE, "precision %d has not been uploaded", (int)prec);
-  if (!prec_has_kernels(prec)) return fail(FMM_ERR_UNSUPPORTED, "precision %d has no single-RHS kernels", (int)prec);
   if (!have_device()) return FMM_ERR_DEVICE;
   int dev = 0;
   TFMM_HIP(hipGetDevice(&dev));
@@ -215,6 +218,69 @@ fmm_status lds_check(size_t bytes) {
   if (bytes > (size_t)lim)
     return fail(FMM_ERR_UNSUPPORTED, "kernel needs %zu bytes of LDS, device allows %d", bytes, lim);
   return FMM_OK;
+}
+
+// Which kernels run a call with nrhs right-hand sides.
+struct Route {
+  bool mfma = false;  // matrix-core products (else the streaming kernels)
+  int variant = 0;    // grouped GEMM arithmetic: 0 FP32, 1 BF16x2, 2 BF16x3
+  int tile_steps = 0, rhs_chunk = 0;
+};
+
+fmm_status route_of(const PrecSlot& s, fmm_prec prec, int nrhs, Route* r) {
+  *r = Route{};
+  if (prec == FMM_C128) return FMM_OK;
+  if (prec_is_split(prec)) {
+    if (nrhs % 2) return fail(FMM_ERR_UNSUPPORTED, "the bf16 split precisions need an even nrhs");
+    r->mfma = true;
+    r->variant = prec == FMM_BF16X2 ? 1 : 2;
+  } else {
+    r->mfma = nrhs % 2 == 0 && nrhs >= kMfmaMinRhs;
+  }
+  for (const TuneChoice& t : s.tuned)
+    if (t.nrhs == nrhs) {
+      r->mfma = t.path == 1;
+      r->tile_steps = t.tile_steps;
+      r->rhs_chunk = t.rhs_chunk;
+    }
+  return FMM_OK;
+}
+
+// Launches one stage (0 aggregation, 1 disaggregation, 2 both) for a validated call.
+fmm_status run_stage(fmm_tucker_t h, PrecSlot& s, fmm_prec prec, int nrhs, int stage, const void* x, void* F,
+                     const void* G, void* V, hipStream_t hs) {
+  const Layout& L = h->layout;
+  Route r;
+  fmm_status st = route_of(s, prec, nrhs, &r);
+  if (st != FMM_OK) return st;
+  if (r.mfma) {
+    // 16-byte operand loads: with an even nrhs every row offset keeps this alignment
+    for (const void* p : {x, (const void*)F, G, (const void*)V})
+      if (p && !aligned(p, 16)) return fail(FMM_ERR_ARG, "the matrix-core path needs 16-byte aligned vectors");
+    MrhsPlan* mp = nullptr;
+    if ((st = mrhs_get(s, L, nrhs, r.tile_steps, r.rhs_chunk, &mp)) != FMM_OK) return st;
+    return mrhs_run(*mp, s, r.variant, stage, x, F, G, V, hs);
+  }
+  if (prec == FMM_C128) {
+    if ((st = lds_check(tucker_lds_bytes<double>(s.plan.mx))) != FMM_OK) return st;
+    if (stage == 0) TFMM_HIP(launch_tucker_agg<double>(s.plan, L.n_theta, L.n_phi, nrhs, x, F, hs));
+    if (stage == 1) TFMM_HIP(launch_tucker_disagg<double>(s.plan, L.n_theta, L.n_phi, nrhs, G, V, hs));
+    if (stage == 2) TFMM_HIP(launch_tucker_pass<double>(s.plan, L.n_theta, L.n_phi, nrhs, x, F, G, V, hs));
+  } else {
+    if ((st = lds_check(tucker_lds_bytes<float>(s.plan.mx))) != FMM_OK) return st;
+    if (stage == 0) TFMM_HIP(launch_tucker_agg<float>(s.plan, L.n_theta, L.n_phi, nrhs, x, F, hs));
+    if (stage == 1) TFMM_HIP(launch_tucker_disagg<float>(s.plan, L.n_theta, L.n_phi, nrhs, G, V, hs));
+    if (stage == 2) TFMM_HIP(launch_tucker_pass<float>(s.plan, L.n_theta, L.n_phi, nrhs, x, F, G, V, hs));
+  }
+  return FMM_OK;
+}
+
+// Drops a captured graph (it may point at tables or factors about to change).
+void drop_graph(fmm_tucker_t h) {
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->graph_exec = nullptr;
+  h->graph = nullptr;
 }
 
 }  // namespace
@@ -281,7 +347,12 @@ extern "C" fmm_status fmm_tucker_set_group(fmm_tucker_t h, int32_t group, int32_
       if (!std::isfinite(z.real()) || !std::isfinite(z.imag()))
         return fail(FMM_ERR_NUMERIC, "non-finite factor entry in group %d polarisation %d", group, alpha);
   h->t[2 * (size_t)group + alpha] = std::move(tf);
-  for (auto& s : h->slot) s.ready = false;  // uploads are stale now
+  drop_graph(h);
+  for (auto& s : h->slot) {  // uploads are stale now
+    s.ready = false;
+    mrhs_release(s);
+    s.tuned.clear();
+  }
   return FMM_OK;
 }
 
@@ -335,7 +406,6 @@ extern "C" fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* are
   clear_error();
   if (!h) return fail(FMM_ERR_ARG, "handle is NULL");
   if (!prec_valid(prec)) return fail(FMM_ERR_ARG, "bad precision %d", (int)prec);
-  if (!prec_has_kernels(prec)) return fail(FMM_ERR_UNSUPPORTED, "precision %d is not available for upload", (int)prec);
   fmm_status st = check_vec(arena, 256, "arena");
   if (st != FMM_OK) return st;
   ArenaPlan P;
@@ -376,6 +446,10 @@ extern "C" fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* are
   TFMM_HIP(hipStreamSynchronize(s));
 
   PrecSlot& sl = h->slot[prec];
+  drop_graph(h);
+  mrhs_release(sl);
+  sl.tuned.clear();
+  sl.items = P.items;
   sl.ready = true;
   sl.arena = static_cast<char*>(arena);
   sl.bytes = bytes;
@@ -399,16 +473,7 @@ extern "C" fmm_status fmm_tucker_aggregate(fmm_tucker_t h, fmm_prec prec, int32_
   if (st != FMM_OK) return st;
   const size_t es = elem_bytes(prec);
   if ((st = check_vec(x, es, "x")) != FMM_OK || (st = check_vec(F, es, "F")) != FMM_OK) return st;
-  const Layout& L = h->layout;
-  hipStream_t hs = static_cast<hipStream_t>(stream);
-  if (prec == FMM_C128) {
-    if ((st = lds_check(tucker_lds_bytes<double>(s->plan.mx))) != FMM_OK) return st;
-    TFMM_HIP(launch_tucker_agg<double>(s->plan, L.n_theta, L.n_phi, nrhs, x, F, hs));
-  } else {
-    if ((st = lds_check(tucker_lds_bytes<float>(s->plan.mx))) != FMM_OK) return st;
-    TFMM_HIP(launch_tucker_agg<float>(s->plan, L.n_theta, L.n_phi, nrhs, x, F, hs));
-  }
-  return FMM_OK;
+  return run_stage(h, *s, prec, nrhs, 0, x, F, nullptr, nullptr, static_cast<hipStream_t>(stream));
 }
 
 extern "C" fmm_status fmm_tucker_disaggregate(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* G, void* V,
@@ -419,58 +484,49 @@ extern "C" fmm_status fmm_tucker_disaggregate(fmm_tucker_t h, fmm_prec prec, int
   if (st != FMM_OK) return st;
   const size_t es = elem_bytes(prec);
   if ((st = check_vec(G, es, "G")) != FMM_OK || (st = check_vec(V, es, "V")) != FMM_OK) return st;
-  const Layout& L = h->layout;
-  hipStream_t hs = static_cast<hipStream_t>(stream);
-  if (prec == FMM_C128) {
-    if ((st = lds_check(tucker_lds_bytes<double>(s->plan.mx))) != FMM_OK) return st;
-    TFMM_HIP(launch_tucker_disagg<double>(s->plan, L.n_theta, L.n_phi, nrhs, G, V, hs));
-  } else {
-    if ((st = lds_check(tucker_lds_bytes<float>(s->plan.mx))) != FMM_OK) return st;
-    TFMM_HIP(launch_tucker_disagg<float>(s->plan, L.n_theta, L.n_phi, nrhs, G, V, hs));
-  }
-  return FMM_OK;
+  return run_stage(h, *s, prec, nrhs, 1, nullptr, nullptr, G, V, static_cast<hipStream_t>(stream));
 }
 
-extern "C" fmm_status fmm_tucker_pass(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F,
-                                      const void* G, void* V, void* stream) {
-  clear_error();
-  PrecSlot* s = nullptr;
-  fmm_status st = ready_slot(h, prec, nrhs, &s);
+namespace {
+fmm_status pass_checks(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F, const void* G, void* V,
+                       PrecSlot** s) {
+  fmm_status st = ready_slot(h, prec, nrhs, s);
   if (st != FMM_OK) return st;
   const size_t es = elem_bytes(prec);
   if ((st = check_vec(x, es, "x")) != FMM_OK || (st = check_vec(F, es, "F")) != FMM_OK ||
       (st = check_vec(G, es, "G")) != FMM_OK || (st = check_vec(V, es, "V")) != FMM_OK)
     return st;
-  const Layout& L = h->layout;
-  hipStream_t hs = static_cast<hipStream_t>(stream);
-  if (prec == FMM_C128) {
-    if ((st = lds_check(tucker_lds_bytes<double>(s->plan.mx))) != FMM_OK) return st;
-    TFMM_HIP(launch_tucker_pass<double>(s->plan, L.n_theta, L.n_phi, nrhs, x, F, G, V, hs));
-  } else {
-    if ((st = lds_check(tucker_lds_bytes<float>(s->plan.mx))) != FMM_OK) return st;
-    TFMM_HIP(launch_tucker_pass<float>(s->plan, L.n_theta, L.n_phi, nrhs, x, F, G, V, hs));
-  }
   return FMM_OK;
+}
+}  // namespace
+
+extern "C" fmm_status fmm_tucker_pass(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F,
+                                      const void* G, void* V, void* stream) {
+  clear_error();
+  PrecSlot* s = nullptr;
+  fmm_status st = pass_checks(h, prec, nrhs, x, F, G, V, &s);
+  if (st != FMM_OK) return st;
+  return run_stage(h, *s, prec, nrhs, 2, x, F, G, V, static_cast<hipStream_t>(stream));
 }
 
 extern "C" fmm_status fmm_graph_capture(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F,
                                         const void* G, void* V, void* stream) {
   clear_error();
   PrecSlot* s = nullptr;
-  fmm_status st = ready_slot(h, prec, nrhs, &s);
+  fmm_status st = pass_checks(h, prec, nrhs, x, F, G, V, &s);
   if (st != FMM_OK) return st;
   hipStream_t hs = static_cast<hipStream_t>(stream);
   if (hs == nullptr) return fail(FMM_ERR_ARG, "graph capture needs a non-default stream");
-  if (h->graph_exec) {
-    (void)hipGraphExecDestroy(h->graph_exec);
-    h->graph_exec = nullptr;
-  }
-  if (h->graph) {
-    (void)hipGraphDestroy(h->graph);
-    h->graph = nullptr;
+  drop_graph(h);
+  // build the multi-RHS tables now: nothing may allocate or copy inside the capture
+  Route r;
+  if ((st = route_of(*s, prec, nrhs, &r)) != FMM_OK) return st;
+  if (r.mfma) {
+    MrhsPlan* mp = nullptr;
+    if ((st = mrhs_get(*s, h->layout, nrhs, r.tile_steps, r.rhs_chunk, &mp)) != FMM_OK) return st;
   }
   TFMM_HIP(hipStreamBeginCapture(hs, hipStreamCaptureModeThreadLocal));
-  fmm_status d = fmm_tucker_pass(h, prec, nrhs, x, F, G, V, stream);
+  fmm_status d = run_stage(h, *s, prec, nrhs, 2, x, F, G, V, hs);
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(hs, &graph);
   if (d != FMM_OK) {
@@ -480,6 +536,89 @@ extern "C" fmm_status fmm_graph_capture(fmm_tucker_t h, fmm_prec prec, int32_t n
   if (e != hipSuccess) return fail(FMM_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
   h->graph = graph;
   TFMM_HIP(hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0));
+  return FMM_OK;
+}
+
+extern "C" fmm_status fmm_tucker_tune(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F,
+                                      const void* G, void* V, void* stream, fmm_tune_result* out) {
+  clear_error();
+  PrecSlot* s = nullptr;
+  fmm_status st = pass_checks(h, prec, nrhs, x, F, G, V, &s);
+  if (st != FMM_OK) return st;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  TFMM_HIP(hipStreamIsCapturing(hs, &cs));
+  if (cs != hipStreamCaptureStatusNone) return fail(FMM_ERR_STATE, "cannot tune inside a stream capture");
+  // candidates: the streaming kernels (FP64, FP32) and the matrix-core products with
+  // several tile sizes and right-hand-side chunks (even nrhs)
+  std::vector<TuneChoice> cand;
+  if (!prec_is_split(prec)) cand.push_back(TuneChoice{nrhs, 0, 0, 0});
+  if (prec != FMM_C128 && nrhs % 2 == 0) {
+    std::vector<int> chunks{std::min<int>(nrhs, kMrhsDefaultChunk)};
+    if (nrhs > 2 * kMrhsDefaultChunk) chunks.push_back(2 * kMrhsDefaultChunk);
+    if (nrhs >= kMrhsDefaultChunk) chunks.push_back(kMrhsDefaultChunk / 2);
+    for (int ts : {8, 16, 32})
+      for (int rc : chunks) cand.push_back(TuneChoice{nrhs, 1, ts, rc});
+  }
+  if (cand.empty()) return fail(FMM_ERR_UNSUPPORTED, "no kernels for precision %d with nrhs %d", (int)prec, nrhs);
+  // keep only the tables that existed before and the winner's
+  std::vector<const MrhsPlan*> before;
+  for (const MrhsPlan& p : s->mrhs) before.push_back(&p);
+  const std::vector<TuneChoice> saved = s->tuned;
+  drop_graph(h);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  TFMM_HIP(hipEventCreate(&e0));
+  hipError_t he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(FMM_ERR_DEVICE, "hipEventCreate: %s", hipGetErrorString(he));
+  }
+  const int reps = 3;
+  float best = -1.f;
+  TuneChoice win{};
+  for (const TuneChoice& c : cand) {
+    s->tuned.assign(1, c);
+    st = run_stage(h, *s, prec, nrhs, 2, x, F, G, V, hs);  // warm-up (builds the tables)
+    if (st != FMM_OK) break;
+    he = hipEventRecord(e0, hs);
+    for (int i = 0; i < reps && st == FMM_OK; ++i) st = run_stage(h, *s, prec, nrhs, 2, x, F, G, V, hs);
+    if (he == hipSuccess) he = hipEventRecord(e1, hs);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (st != FMM_OK || he != hipSuccess) break;
+    ms /= reps;
+    if (best < 0.f || ms < best) {
+      best = ms;
+      win = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  s->tuned = saved;
+  if (st == FMM_OK && he != hipSuccess) st = fail(FMM_ERR_DEVICE, "tuning timer: %s", hipGetErrorString(he));
+  // free the tables of the losing candidates
+  for (auto it = s->mrhs.begin(); it != s->mrhs.end();) {
+    const bool old = std::find(before.begin(), before.end(), &*it) != before.end();
+    const bool keep = old || (st == FMM_OK && win.path == 1 && it->nrhs == nrhs && it->tile_steps == win.tile_steps &&
+                              it->rhs_chunk == std::min(win.rhs_chunk, nrhs));
+    if (keep) {
+      ++it;
+    } else {
+      mrhs_free(*it);
+      it = s->mrhs.erase(it);
+    }
+  }
+  if (st != FMM_OK) return st;
+  s->tuned.erase(std::remove_if(s->tuned.begin(), s->tuned.end(), [&](const TuneChoice& t) { return t.nrhs == nrhs; }),
+                 s->tuned.end());
+  s->tuned.push_back(win);
+  if (out) {
+    out->path = win.path;
+    out->tile_steps = win.tile_steps;
+    out->rhs_chunk = win.path == 1 ? std::min(win.rhs_chunk, nrhs) : 0;
+    out->ms = best;
+  }
   return FMM_OK;
 }
 
@@ -493,8 +632,8 @@ extern "C" fmm_status fmm_graph_launch(fmm_tucker_t h, void* stream) {
 
 extern "C" void fmm_tucker_destroy(fmm_tucker_t h) {
   if (!h) return;
-  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
-  if (h->graph) (void)hipGraphDestroy(h->graph);
+  drop_graph(h);
+  for (auto& s : h->slot) mrhs_release(s);
   delete h;
 }
 

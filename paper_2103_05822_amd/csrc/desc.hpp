@@ -48,6 +48,37 @@ struct TuckPlan {
   TuckMax mx{};
 };
 
+// One complex product C(m, n) (+)= sum_k opA(m, k) opB(k, n) of the multi-RHS path.
+// Offsets and strides count complex elements from the base pointer selected by
+// abase / bbase / cbase (an index into CGemmBases):
+//   A(m, k) at a + m lda_m + k lda_k
+//   B(k, n) at b + k ldb_k + (n / b_ni) b_shi + n % b_ni
+//   C(m, n) at c + m ldc_m + (n / c_ni) c_shi + n % c_ni
+enum : int32_t { kConjA = 1, kConjB = 2, kConjC = 4, kAtomicC = 8 };
+struct CGemm {
+  int64_t a, b, c;
+  int32_t abase, bbase, cbase;
+  int32_t M, N, K;
+  int32_t lda_m, lda_k;
+  int32_t ldb_k, b_ni, b_shi;
+  int32_t ldc_m, c_ni, c_shi;
+  int32_t flags;
+  int32_t pad;
+};
+static_assert(sizeof(CGemm) == 88, "CGemm layout");
+
+// Base pointers of a grouped launch: factors, scratch, x, F, G, V.
+enum : int32_t { kBaseFactors = 0, kBaseScratch = 1, kBaseX = 2, kBaseF = 3, kBaseG = 4, kBaseV = 5 };
+struct CGemmBases {
+  void* p[6];
+};
+
+// One workgroup of the grouped product: rows m0 .. m0 + 63 and complex columns
+// n0 .. n1 - 1 (in blocks of 32) of problem `prob`.
+struct CTile {
+  int32_t prob, m0, n0, n1;
+};
+
 // Dense plan: one group's rows.
 struct DenseGroup {
   int64_t row0;

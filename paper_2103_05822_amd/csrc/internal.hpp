@@ -5,6 +5,7 @@
 #include <complex>
 #include <cstdarg>
 #include <cstdint>
+#include <list>
 #include <string>
 #include <vector>
 
@@ -49,13 +50,67 @@ struct TensorFactors {
   bool set() const { return rt > 0; }
 };
 
+// One chunk of right-hand sides of the multi-RHS path (columns r0 .. r0 + rc - 1).
+// Launch j (0..3) of a stage computes contraction j of every item; the aggregation,
+// disaggregation and merged pass tile lists index the chunk's problem table.
+struct MrhsChunk {
+  int r0 = 0, rc = 0;
+  const CGemm* probs = nullptr;         // device
+  const CTile* tiles[3][4] = {};        // [agg, dis, pass][launch], device
+  int n_tiles[3][4] = {};
+};
+
+// Library-owned device tables and scratch of the multi-RHS path for one nrhs.
+struct MrhsPlan {
+  int nrhs = 0;
+  int rhs_chunk = 0;   // columns per chunk
+  int tile_steps = 0;  // K steps a workgroup aims to run (column blocks per tile)
+  char* dev = nullptr;  // one allocation: problem tables, tile lists, scratch
+  size_t dev_bytes = 0;
+  char* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  std::vector<MrhsChunk> chunks;
+};
+
+// Tuned choice for one nrhs: path 0 = streaming kernels, 1 = matrix-core products.
+struct TuneChoice {
+  int nrhs = 0, path = 0, tile_steps = 0, rhs_chunk = 0;
+};
+
 struct PrecSlot {
   bool ready = false;
   char* arena = nullptr;   // caller-owned device memory
   size_t bytes = 0;
   int device = -1;
   TuckPlan plan;          // device pointers into the arena
+  std::vector<TuckItem> items;      // host copy of the item table
+  std::list<MrhsPlan> mrhs;         // built on first use per (nrhs, knobs); stable addresses
+  std::vector<TuneChoice> tuned;
 };
+
+// Multi-RHS path (mrhs_plan.cpp).
+constexpr int kMrhsDefaultSteps = 16;
+constexpr int kMrhsDefaultChunk = 64;
+// Host image of the tables: problems [8][n_items] (product j of item i at j n_items + i)
+// and tile lists [agg, dis, pass][launch] per chunk; scratch offsets in complex elements.
+struct MrhsHostChunk {
+  int r0 = 0, rc = 0;
+  std::vector<CGemm> probs;
+  std::vector<CTile> lists[3][4];
+};
+struct MrhsHost {
+  int64_t scratch_elems = 0;
+  std::vector<MrhsHostChunk> chunks;
+};
+void mrhs_build_host(const std::vector<TuckItem>& items, const Layout& L, int nrhs, int tile_steps, int rhs_chunk,
+                     MrhsHost* out);
+// Plan for (slot, nrhs) with the given knobs (0 = defaults), built on first use.
+fmm_status mrhs_get(PrecSlot& s, const Layout& L, int nrhs, int tile_steps, int rhs_chunk, MrhsPlan** out);
+// stage: 0 aggregation, 1 disaggregation, 2 both (merged launches).
+fmm_status mrhs_run(const MrhsPlan& p, const PrecSlot& s, int variant, int stage, const void* x, void* F,
+                    const void* G, void* V, hipStream_t st);
+void mrhs_free(MrhsPlan& p);
+void mrhs_release(PrecSlot& s);
 
 }  // namespace tuckfmm
 

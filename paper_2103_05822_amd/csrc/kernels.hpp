@@ -20,6 +20,12 @@ hipError_t launch_tucker_pass(const TuckPlan& pl, int n_theta, int n_phi, int nr
 template <typename T>
 size_t tucker_lds_bytes(const TuckMax& mx);
 
+// Grouped complex GEMM of the multi-RHS path (variant 0: FP32 MFMA, 1: BF16 two-piece
+// split, 2: BF16 three-piece split; FP32 accumulation), one workgroup per tile.
+hipError_t launch_cgemm(int variant, const CGemm* probs, const CTile* tiles, int n_tiles, const CGemmBases& b,
+                        hipStream_t s);
+hipError_t launch_zero_c64(void* v, int64_t n, hipStream_t s);
+
 // Dense (plain) aggregation / disaggregation.
 template <typename T>
 hipError_t launch_dense_agg(const void* A, const DenseGroup* groups, int n_groups, int ncols, int nrhs,

@@ -1,0 +1,263 @@
+"""GPU parity of the multi-right-hand-side (matrix-core) path against the FP64 oracle.
+
+The path runs each contraction of the Tucker aggregation / disaggregation as a grouped
+complex GEMM on the MFMA units: FP32 (FMM_C64 with an even nrhs >= 8), or with the
+operands split into bf16 pieces (FMM_BF16X2: hi + lo, FMM_BF16X3: hi + mid + lo).
+
+Tolerances, relative L2 over all outputs and max error relative to the largest
+reference entry:
+  - FP32 and BF16x3: 1e-5, the single-precision target of the method (sums of a few
+    thousand terms with unit roundoff 6e-8).
+  - BF16x2: each operand v = hi + lo carries a representation error below 2^-17 |v|
+    (the lo piece rounds the residual to 8 significant bits) and the dropped lo*lo
+    term is below 2^-18 relative, so a product of two split operands is off by at
+    most ~3 2^-18 = 1.1e-5 relative per term; four chained products with
+    independent rounding give about 2 x 1.1e-5 in L2.  The bound used is 4e-5 (L2) and
+    1e-4 (max).
+"""
+import numpy as np
+import pytest
+
+import synth
+from synth import workloads as W
+from oracle import geometry as geo
+from oracle import products as pr
+from gpu_util import dev, host, arena, max_rel, l2_rel, banner
+
+pytestmark = pytest.mark.gpu
+
+T = pytest.importorskip("paper_2103_05822_amd")
+
+C64 = np.complex64
+TOL = {T.FMM_C64: (1e-5, 1e-5), T.FMM_BF16X2: (4e-5, 1e-4), T.FMM_BF16X3: (1e-5, 1e-5)}
+PRECS = [T.FMM_C64, T.FMM_BF16X2, T.FMM_BF16X3]
+PIDS = ["c64", "bf16x2", "bf16x3"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def ragged_layout(n_theta=5, n_phi=9):
+    sizes = [1, 2, 3, 64, 65, 130, 257]
+    return T.Layout(n_theta, n_phi, np.concatenate([[0], np.cumsum(sizes)]))
+
+
+def random_tucker(lay, seed, rank_mode="random"):
+    rng = synth.rng(seed)
+    out = []
+    for g in range(lay.n_groups):
+        nb = int(lay.offsets[g + 1] - lay.offsets[g])
+        pair = []
+        for a in range(2):
+            if rank_mode == "full":
+                rt, rp, rb = lay.n_theta, lay.n_phi, nb
+            elif rank_mode == "one":
+                rt, rp, rb = 1, 1, 1
+            else:
+                rt, rp, rb = synth.synthetic_ranks(rng, nb, lay.n_theta, lay.n_phi)
+            core, ut, up, ub = synth.synthetic_tucker(rng, lay.n_theta, lay.n_phi, nb, rt, rp, rb)
+            pair.append((core, (ut, up, ub)))
+        out.append(pair)
+    return out
+
+
+def paper_grid_tucker(seed=31):
+    """38 x 75 grid with the group sizes of the 6-lambda sphere at box 2 lambda and
+    ranks near Table IV's 2-lambda row."""
+    w = W.SPHERE6
+    v, t = synth.icosphere(w.freq, w.radius)
+    P = geo.Problem(v, t, w.origin, w.box, w.boxes_per_axis, w.n_theta, w.n_phi)
+    lay = T.Layout(w.n_theta, w.n_phi, P.offsets)
+    rng = synth.rng(seed)
+    tuck = []
+    for g in range(lay.n_groups):
+        nb = int(lay.offsets[g + 1] - lay.offsets[g])
+        pair = []
+        for a in range(2):
+            rt = int(rng.integers(20, 29))
+            rp = int(rng.integers(24, 34))
+            rb = int(min(nb, rng.integers(150, 260)))
+            core, ut, up, ub = synth.synthetic_tucker(rng, w.n_theta, w.n_phi, nb, rt, rp, rb)
+            pair.append((core, (ut, up, ub)))
+        tuck.append(pair)
+    return lay, tuck
+
+
+class Handle:
+    def __init__(self, lay, tuck, prec):
+        self.h = T.fmm_tucker_create(lay)
+        for g, pair in enumerate(tuck):
+            for a, (core, (ut, up, ub)) in enumerate(pair):
+                T.fmm_tucker_set_group(self.h, g, a, core, ut, up, ub)
+        _, nbytes = T.fmm_tucker_storage_bytes(self.h, prec)
+        self.arena = arena(nbytes)
+        T.fmm_tucker_upload(self.h, prec, self.arena)
+
+    def close(self):
+        T.fmm_tucker_destroy(self.h)
+
+
+def inputs(lay, nrhs, seed):
+    rng = synth.rng(seed)
+    x = synth.complex_normal(rng, (lay.n_basis, nrhs))
+    gin = synth.complex_normal(rng, (lay.n_groups, 2, lay.n_dir, nrhs))
+    return x, gin
+
+
+def check(prec, F, V, f_ref, v_ref):
+    tl2, tmax = TOL[prec]
+    res = (l2_rel(F, f_ref), max_rel(F, f_ref), l2_rel(V, v_ref), max_rel(V, v_ref))
+    print("  errors: F l2 %.2e max %.2e | V l2 %.2e max %.2e" % res, flush=True)
+    assert res[0] < tl2 and res[1] < tmax, res
+    assert res[2] < tl2 and res[3] < tmax, res
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=PIDS)
+@pytest.mark.parametrize("rank_mode", ["random", "full", "one"])
+@pytest.mark.parametrize("nrhs", [2, 8, 66])
+def test_mrhs_ragged_layout(prec, rank_mode, nrhs):
+    """Ragged groups (tails of every tile), both angular orders, one and two RHS chunks."""
+    lay = ragged_layout()
+    banner("mrhs ragged prec=%d ranks=%s nrhs=%d" % (prec, rank_mode, nrhs))
+    tuck = random_tucker(lay, 40 + nrhs, rank_mode)
+    x, gin = inputs(lay, nrhs, 6)
+    f_ref = pr.aggregate_all("tucker", tuck, lay.offsets, x)
+    v_ref = pr.disaggregate_all("tucker", tuck, lay.offsets, gin)
+    H = Handle(lay, tuck, prec)
+    try:
+        F = dev(np.zeros(f_ref.shape, C64))
+        V = dev(np.zeros(v_ref.shape, C64))
+        T.fmm_tucker_aggregate(H.h, prec, nrhs, dev(x, C64), F)
+        T.fmm_tucker_disaggregate(H.h, prec, nrhs, dev(gin, C64), V)
+        check(prec, host(F), host(V), f_ref, v_ref)
+    finally:
+        H.close()
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=PIDS)
+def test_mrhs_paper_grid(prec):
+    """38 x 75 grid, realistic ranks, 8 right-hand sides: pass and separate stages."""
+    lay, tuck = paper_grid_tucker()
+    nrhs = 8
+    banner("mrhs paper grid prec=%d groups=%d N=%d nrhs=%d" % (prec, lay.n_groups, lay.n_basis, nrhs))
+    x, gin = inputs(lay, nrhs, 7)
+    f_ref = pr.aggregate_all("tucker", tuck, lay.offsets, x)
+    v_ref = pr.disaggregate_all("tucker", tuck, lay.offsets, gin)
+    H = Handle(lay, tuck, prec)
+    try:
+        xd, gd = dev(x, C64), dev(gin, C64)
+        F = dev(np.zeros(f_ref.shape, C64))
+        V = dev(np.zeros(v_ref.shape, C64))
+        T.fmm_tucker_pass(H.h, prec, nrhs, xd, F, gd, V)
+        Fp, Vp = host(F), host(V)
+        check(prec, Fp, Vp, f_ref, v_ref)
+        F2 = dev(np.zeros(f_ref.shape, C64))
+        V2 = dev(np.zeros(v_ref.shape, C64))
+        T.fmm_tucker_aggregate(H.h, prec, nrhs, xd, F2)
+        T.fmm_tucker_disaggregate(H.h, prec, nrhs, gd, V2)
+        # the merged pass runs the same tiles with the same arithmetic: bitwise equal
+        assert np.array_equal(host(F2), Fp)
+        assert np.array_equal(host(V2), Vp)
+    finally:
+        H.close()
+
+
+def test_mrhs_matches_streaming_fp32():
+    """FMM_C64 with 8 RHS (matrix cores) against the same precision's streaming kernels
+    (odd nrhs = 7 on the first seven columns)."""
+    lay = ragged_layout(7, 13)
+    tuck = random_tucker(lay, 77)
+    x, gin = inputs(lay, 8, 8)
+    banner("mrhs vs streaming c64")
+    H = Handle(lay, tuck, T.FMM_C64)
+    try:
+        F8 = dev(np.zeros((lay.n_groups, 2, lay.n_dir, 8), C64))
+        V8 = dev(np.zeros((lay.n_basis, 8), C64))
+        T.fmm_tucker_pass(H.h, T.FMM_C64, 8, dev(x, C64), F8, dev(gin, C64), V8)
+        F7 = dev(np.zeros((lay.n_groups, 2, lay.n_dir, 7), C64))
+        V7 = dev(np.zeros((lay.n_basis, 7), C64))
+        T.fmm_tucker_pass(H.h, T.FMM_C64, 7, dev(x[:, :7], C64), F7, dev(gin[..., :7], C64), V7)
+        a, b = host(F8)[..., :7], host(F7)
+        c, d = host(V8)[..., :7], host(V7)
+        assert l2_rel(a, b) < 1e-5 and l2_rel(c, d) < 1e-5
+    finally:
+        H.close()
+
+
+@pytest.mark.parametrize("prec", [T.FMM_C64, T.FMM_BF16X2], ids=["c64", "bf16x2"])
+def test_mrhs_graph_replays(prec):
+    """The captured pass (zero kernel + grouped launches) replayed several times, with
+    eager work and synchronisations between replays; every replay equals the eager pass."""
+    import torch
+    lay = ragged_layout()
+    tuck = random_tucker(lay, 91)
+    nrhs = 10
+    x, gin = inputs(lay, nrhs, 9)
+    banner("mrhs graph prec=%d" % prec)
+    H = Handle(lay, tuck, prec)
+    try:
+        xd, gd = dev(x, C64), dev(gin, C64)
+        F = dev(np.zeros((lay.n_groups, 2, lay.n_dir, nrhs), C64))
+        V = dev(np.zeros((lay.n_basis, nrhs), C64))
+        T.fmm_tucker_pass(H.h, prec, nrhs, xd, F, gd, V)
+        Fe, Ve = host(F), host(V)
+        s = torch.cuda.Stream()
+        T.fmm_graph_capture(H.h, prec, nrhs, xd, F, gd, V, s)
+        for rep in range(4):
+            F.fill_(float("nan"))
+            V.fill_(7.0)
+            torch.cuda.synchronize()
+            T.fmm_graph_launch(H.h, s)
+            s.synchronize()
+            assert np.array_equal(host(F), Fe), rep
+            assert np.array_equal(host(V), Ve), rep
+            _ = (xd * 2).sum().item()  # eager work between replays
+    finally:
+        H.close()
+
+
+@pytest.mark.parametrize("prec", [T.FMM_C64, T.FMM_BF16X3], ids=["c64", "bf16x3"])
+def test_mrhs_tune(prec):
+    """The autotuner picks a configuration; later calls with that nrhs use it and stay
+    within tolerance."""
+    lay, tuck = paper_grid_tucker(seed=33)
+    nrhs = 16
+    x, gin = inputs(lay, nrhs, 10)
+    f_ref = pr.aggregate_all("tucker", tuck, lay.offsets, x)
+    v_ref = pr.disaggregate_all("tucker", tuck, lay.offsets, gin)
+    banner("mrhs tune prec=%d" % prec)
+    H = Handle(lay, tuck, prec)
+    try:
+        xd, gd = dev(x, C64), dev(gin, C64)
+        F = dev(np.zeros(f_ref.shape, C64))
+        V = dev(np.zeros(v_ref.shape, C64))
+        r = T.fmm_tucker_tune(H.h, prec, nrhs, xd, F, gd, V)
+        print("  tuned:", r, flush=True)
+        assert r["path"] in (0, 1) and r["ms"] > 0
+        if prec != T.FMM_C64:
+            assert r["path"] == 1
+        F.zero_()
+        V.zero_()
+        T.fmm_tucker_pass(H.h, prec, nrhs, xd, F, gd, V)
+        check(prec, host(F), host(V), f_ref, v_ref)
+    finally:
+        H.close()
+
+
+def test_split_precisions_need_even_nrhs():
+    lay = ragged_layout()
+    tuck = random_tucker(lay, 3)
+    H = Handle(lay, tuck, T.FMM_BF16X2)
+    try:
+        x, gin = inputs(lay, 3, 1)
+        F = dev(np.zeros((lay.n_groups, 2, lay.n_dir, 3), C64))
+        with pytest.raises(T.FmmError) as e:
+            T.fmm_tucker_aggregate(H.h, T.FMM_BF16X2, 3, dev(x, C64), F)
+        assert e.value.status == -6
+    finally:
+        H.close()
