@@ -13,20 +13,24 @@
 // A complex product C = A B runs on real MFMA instructions through the identity
 //   [Re C, Im C] = [Re A, Im A] [[Re B, Im B], [-Im B, Re B]]
 // with A read as a real matrix whose columns interleave (Re, Im) -- the stored
-// layout -- and B expanded on the fly: no arithmetic is wasted (8 real flops per
-// complex multiply-add).  Workgroup tile: 64 rows x 32 complex columns, K in steps of
-// 16 complex values, operands staged through LDS (double buffered), four wavefronts
-// each owning 16 rows x 64 real columns = four 16x16 MFMA accumulators.
+// layout -- and B expanded to the 2 x 2 real blocks: no arithmetic is wasted (8 real
+// flops per complex multiply-add).
+//
+// Workgroup tile: 64 rows x 64 complex columns (128 real), K in steps of 16 complex
+// values (32 real).  Four wavefronts, each owning 16 rows x 128 real columns = eight
+// 16 x 16 MFMA accumulators.  A workgroup walks its column blocks and K steps as one
+// flat pipeline: the global loads of step s + 1 are in flight while step s runs on the
+// matrix cores from LDS (double buffered); conjugation, B expansion and the bf16
+// split happen when a step is written to LDS.
 //
 // Arithmetic variants (factors are stored as complex64 in every variant):
 //   0  FP32    v_mfma_f32_16x16x4_f32 on the FP32 operands;
 //   1  BF16x2  v_mfma_f32_16x16x32_bf16; both operands are split into bf16 pieces
-//              v = hi + lo while they are read from LDS, and each product accumulates
-//              hi*hi + hi*lo + lo*hi in FP32 (the dropped terms are below 2^-16
-//              relative);
+//              v = hi + lo and each product accumulates hi*hi + hi*lo + lo*hi in FP32
+//              (the dropped lo*lo term is below 2^-16 relative);
 //   2  BF16x3  three pieces v = hi + mid + lo and the six products whose order is at
 //              most 2^-16 (hi*hi, hi*mid, mid*hi, hi*lo, mid*mid, lo*hi): FP32-level
-//              accuracy at six bf16 instructions per step.
+//              accuracy at six bf16 instructions per product.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,126 +44,181 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-constexpr int kMT = 256;  // threads
-constexpr int kBM = 64;   // rows per tile
-constexpr int kBN = 32;   // complex columns per tile
-constexpr int kKC = 16;   // complex K per step
-constexpr int kAS = kKC + 2;  // LDS row stride of A (complex), keeps 16-byte alignment
-constexpr int kBS = kBN + 2;  // LDS row stride of B (complex)
+constexpr int kMT = 256;           // threads
+constexpr int kBM = 64;            // rows per tile
+constexpr int kBN = 64;            // complex columns per block
+constexpr int kKC = 16;            // complex K per step
+constexpr int kKR = 2 * kKC;       // real K per step
+constexpr int kNT = 2 * kBN / 16;  // 16-column accumulators per wavefront (8)
+// FP32 LDS strides (complex): padding keeps 16-byte alignment and spreads banks
+constexpr int kAS = kKC + 2;
+constexpr int kBS = kBN + 2;
 
 __device__ __forceinline__ int64_t col_off(int n, int ni, int shi) { return (int64_t)(n / ni) * shi + n % ni; }
 
-// -------------------------------------------------------------------- staging
-// Global -> registers for one K step: A tile (kBM x kKC complex), B tile (kKC x kBN).
+__device__ __forceinline__ float2* base_ptr(const CGemmBases& b, int i) {
+  // i is uniform across the workgroup: a select chain, no indexed private array
+  void* p = i == 0 ? b.p[0] : i == 1 ? b.p[1] : i == 2 ? b.p[2] : i == 3 ? b.p[3] : i == 4 ? b.p[4] : b.p[5];
+  return static_cast<float2*>(p);
+}
+
+// ------------------------------------------------------------------ global loads
+// One K step of raw operands in registers: two complex pairs of A and two of B per
+// thread, plus validity bits.  Every load is unconditional (an invalid element reads
+// the operand's first element instead) and nothing consumes the loaded values before
+// the step is written to LDS, so the loads stay in flight while the previous step
+// runs on the matrix cores.  AVEC (uniform per product): A pairs are loaded as one
+// 16-byte access; the second element of a pair at the K (or M) tail then lies in the
+// zero padding of the factor row (rows are padded to an even length), and is masked.
 struct Stage {
-  float4 a[2];  // two complex pairs of A per thread
-  float4 b;     // one complex pair of B per thread
+  float4 a[2];
+  float4 b[2];
+  uint32_t ok;  // bits 0-3: A halves (pair j: bits 2j, 2j+1); bits 4-5: B pairs
 };
 
-__device__ __forceinline__ float2 cj(float2 v, bool c) { return c ? make_float2(v.x, -v.y) : v; }
-
+template <bool AVEC>
 __device__ __forceinline__ void load_stage(const CGemm& p, const float2* A, const float2* B, int m0, int n0, int k0,
                                            int tid, Stage& st) {
-  const bool ca = p.flags & kConjA, cb = p.flags & kConjB;
-  // 16-byte loads need an even complex offset for every pair
-  const bool avec = !((p.a | (p.lda_k == 1 ? p.lda_m : p.lda_k)) & 1);
+  uint32_t ok = 0;
+  const float2* a0 = A + p.a;
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int pr = tid + kMT * j;  // pair index 0..511
-    float2 v0 = make_float2(0.f, 0.f), v1 = v0;
-    if (p.lda_k == 1) {  // K contiguous: pair = (m, 2kp), (m, 2kp + 1)
+    bool ok0, ok1;
+    int64_t i0, i1;
+    if (p.lda_k == 1) {  // K contiguous: pair = (m, k), (m, k + 1)
       const int m = m0 + pr / 8, k = k0 + 2 * (pr % 8);
-      if (m < p.M) {
-        const float2* src = A + p.a + (int64_t)m * p.lda_m + k;
-        if (k + 1 < p.K && avec) {
-          const float4 q = *reinterpret_cast<const float4*>(src);
-          v0 = make_float2(q.x, q.y);
-          v1 = make_float2(q.z, q.w);
-        } else {
-          if (k < p.K) v0 = src[0];
-          if (k + 1 < p.K) v1 = src[1];
-        }
-      }
-    } else {  // M contiguous: pair = (2mp, k), (2mp + 1, k)
+      ok0 = m < p.M && k < p.K;
+      ok1 = m < p.M && k + 1 < p.K;
+      i0 = (int64_t)m * p.lda_m + k;
+      i1 = i0 + 1;
+    } else {  // M contiguous: pair = (m, k), (m + 1, k)
       const int k = k0 + pr / 32, m = m0 + 2 * (pr % 32);
-      if (k < p.K) {
-        const float2* src = A + p.a + m + (int64_t)k * p.lda_k;
-        if (m + 1 < p.M && avec) {
-          const float4 q = *reinterpret_cast<const float4*>(src);
-          v0 = make_float2(q.x, q.y);
-          v1 = make_float2(q.z, q.w);
-        } else {
-          if (m < p.M) v0 = src[0];
-          if (m + 1 < p.M) v1 = src[1];
-        }
-      }
+      ok0 = k < p.K && m < p.M;
+      ok1 = k < p.K && m + 1 < p.M;
+      i0 = m + (int64_t)k * p.lda_k;
+      i1 = i0 + 1;
     }
-    v0 = cj(v0, ca);
-    v1 = cj(v1, ca);
-    st.a[j] = make_float4(v0.x, v0.y, v1.x, v1.y);
-  }
-  {
-    const int k = k0 + tid / 16, n = n0 + 2 * (tid % 16);
-    float2 v0 = make_float2(0.f, 0.f), v1 = v0;
-    if (k < p.K && n < p.N) {  // N and the column blocks are even: the pair never splits
-      const float4 q =
-          *reinterpret_cast<const float4*>(B + p.b + (int64_t)k * p.ldb_k + col_off(n, p.b_ni, p.b_shi));
-      v0 = cj(make_float2(q.x, q.y), cb);
-      v1 = cj(make_float2(q.z, q.w), cb);
+    if constexpr (AVEC) {
+      st.a[j] = *reinterpret_cast<const float4*>(a0 + (ok0 ? i0 : 0));
+    } else {
+      const float2 u0 = a0[ok0 ? i0 : 0];
+      const float2 u1 = a0[ok1 ? i1 : 0];
+      st.a[j] = make_float4(u0.x, u0.y, u1.x, u1.y);
     }
-    st.b = make_float4(v0.x, v0.y, v1.x, v1.y);
+    ok |= (ok0 ? 1u : 0u) << (2 * j);
+    ok |= (ok1 ? 1u : 0u) << (2 * j + 1);
   }
-}
-
-// Registers -> LDS.  A as [kBM][kAS] complex, B as [kKC][kBS] complex.
-__device__ __forceinline__ void store_stage(const CGemm& p, const Stage& st, float2* As, float2* Bs, int tid) {
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int pr = tid + kMT * j;
+    const int k = k0 + pr / 32, n = n0 + 2 * (pr % 32);
+    const bool okb = k < p.K && n < p.N;  // N and the column blocks are even: a pair never splits
+    const int64_t ib = okb ? (int64_t)k * p.ldb_k + col_off(n, p.b_ni, p.b_shi) : 0;
+    st.b[j] = *reinterpret_cast<const float4*>(B + p.b + ib);
+    ok |= (okb ? 1u : 0u) << (4 + j);
+  }
+  st.ok = ok;
+}
+
+// Operand values of a stage with the invalid elements zeroed and the conjugation
+// flags applied (this is where the loads are waited for).
+__device__ __forceinline__ float4 a_val(const CGemm& p, const Stage& st, int j) {
+  float4 v = st.a[j];
+  if (!(st.ok & (1u << (2 * j)))) v.x = v.y = 0.f;
+  if (!(st.ok & (1u << (2 * j + 1)))) v.z = v.w = 0.f;
+  if (p.flags & kConjA) {
+    v.y = -v.y;
+    v.w = -v.w;
+  }
+  return v;
+}
+
+__device__ __forceinline__ float4 b_val(const CGemm& p, const Stage& st, int j) {
+  float4 v = st.b[j];
+  if (!(st.ok & (1u << (4 + j)))) v = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (p.flags & kConjB) {
+    v.y = -v.y;
+    v.w = -v.w;
+  }
+  return v;
+}
+
+// ------------------------------------------------------------------- FP32 variant
+struct LdsF32 {
+  float2 a[2][kBM * kAS];
+  float2 b[2][kKC * kBS];
+};
+
+__device__ __forceinline__ void store_f32(const CGemm& p, const Stage& st, LdsF32& L, int buf, int tid) {
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int pr = tid + kMT * j;
+    const float4 v = a_val(p, st, j);
     if (p.lda_k == 1) {
       const int m = pr / 8, k = 2 * (pr % 8);
-      *reinterpret_cast<float4*>(As + m * kAS + k) = st.a[j];
+      *reinterpret_cast<float4*>(&L.a[buf][m * kAS + k]) = v;
     } else {
       const int k = pr / 32, m = 2 * (pr % 32);
-      As[m * kAS + k] = make_float2(st.a[j].x, st.a[j].y);
-      As[(m + 1) * kAS + k] = make_float2(st.a[j].z, st.a[j].w);
+      L.a[buf][m * kAS + k] = make_float2(v.x, v.y);
+      L.a[buf][(m + 1) * kAS + k] = make_float2(v.z, v.w);
     }
   }
-  const int k = tid / 16, n = 2 * (tid % 16);
-  *reinterpret_cast<float4*>(Bs + k * kBS + n) = st.b;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int pr = tid + kMT * j;
+    const int k = pr / 32, n = 2 * (pr % 32);
+    *reinterpret_cast<float4*>(&L.b[buf][k * kBS + n]) = b_val(p, st, j);
+  }
 }
 
-// ------------------------------------------------------------------- compute
-
-// One K step on FP32 MFMA.  Lane (mi, kb) of wavefront w: rows 16w + mi; the real K
-// index covered by instruction (h, s) is 16h + 4kb + s (a permutation of the step's
-// 32 real indices, applied identically to A and B).
-__device__ __forceinline__ void mma_step_f32(const float2* As, const float2* Bs, int w, int lane,
-                                             floatx4 (&acc)[4]) {
+// Lane (mi, kb) of wavefront w: rows 16w + mi.  The real K index of instruction
+// (h, s) is 16h + 4kb + s (a permutation of the step's 32 real indices, applied
+// identically to A and B); B column lane mi covers real column 16t + mi.
+__device__ __forceinline__ void mma_f32(const LdsF32& L, int buf, int w, int lane, floatx4 (&acc)[kNT]) {
   const int mi = lane % 16, kb = lane / 16;
-  const int q = mi & 1;  // as a B column lane: real column parity (0: Re, 1: Im)
+  const bool q = mi & 1;  // real column parity (0: Re C, 1: Im C)
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const float4 a = *reinterpret_cast<const float4*>(As + (16 * w + mi) * kAS + 8 * h + 2 * kb);
+    const float4 a = *reinterpret_cast<const float4*>(&L.a[buf][(16 * w + mi) * kAS + 8 * h + 2 * kb]);
     const float av[4] = {a.x, a.y, a.z, a.w};
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int nc = 8 * t + mi / 2;
-      const float2 b0 = Bs[(8 * h + 2 * kb) * kBS + nc];
-      const float2 b1 = Bs[(8 * h + 2 * kb + 1) * kBS + nc];
-      // expanded B rows 2k (Re A) and 2k + 1 (Im A) at real column 2n + q
-      const float bv[4] = {q ? b0.y : b0.x, q ? b0.x : -b0.y, q ? b1.y : b1.x, q ? b1.x : -b1.y};
+    for (int t0 = 0; t0 < kNT; t0 += kNT / 2) {  // two halves: four independent accumulators each
+      float bv[kNT / 2][4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bv[s], acc[t], 0, 0, 0);
+      for (int u = 0; u < kNT / 2; ++u) {
+        const int nc = 8 * (t0 + u) + mi / 2;
+        const float2 b0 = L.b[buf][(8 * h + 2 * kb) * kBS + nc];
+        const float2 b1 = L.b[buf][(8 * h + 2 * kb + 1) * kBS + nc];
+        // expanded B rows 2k (Re A) and 2k + 1 (Im A) at real column 2n + q
+        bv[u][0] = q ? b0.y : b0.x;
+        bv[u][1] = q ? b0.x : -b0.y;
+        bv[u][2] = q ? b1.y : b1.x;
+        bv[u][3] = q ? b1.x : -b1.y;
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int u = 0; u < kNT / 2; ++u)
+          acc[t0 + u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bv[u][s], acc[t0 + u], 0, 0, 0);
     }
   }
 }
 
-// One K step on BF16 MFMA with operands split into NP pieces (2 or 3).  Lane (mi, kb)
-// supplies the real K indices 8kb .. 8kb + 7 of the 32-wide instruction.
+// ------------------------------------------------------------------- BF16 variants
+// LDS holds the operands pre-split: A as [piece][row][32 real K] and the expanded B
+// as [piece][real column][32 real K], bf16, so every lane reads its 8 K values of a
+// piece with one 16-byte load.
 template <int NP>
-__device__ __forceinline__ void split_bf16(float v, __bf16 (&pc)[NP]) {
+struct LdsBf16 {
+  __bf16 a[2][NP][kBM * kKR];
+  __bf16 b[2][NP][2 * kBN * kKR];
+};
+
+template <int NP>
+__device__ __forceinline__ void split(float v, __bf16 (&pc)[NP]) {
   pc[0] = (__bf16)v;
   float r = v - (float)pc[0];
   pc[1] = (__bf16)r;
@@ -169,117 +228,199 @@ __device__ __forceinline__ void split_bf16(float v, __bf16 (&pc)[NP]) {
   }
 }
 
+// Splits two consecutive real values and writes each piece as one bf16 pair.
 template <int NP>
-__device__ __forceinline__ void mma_step_bf16(const float2* As, const float2* Bs, int w, int lane,
-                                              floatx4 (&acc)[4]) {
-  const int mi = lane % 16, kb = lane / 16;
-  const int q = mi & 1;
-  bf16x8 ap[NP];
-  {
-    const float4 a0 = *reinterpret_cast<const float4*>(As + (16 * w + mi) * kAS + 4 * kb);
-    const float4 a1 = *reinterpret_cast<const float4*>(As + (16 * w + mi) * kAS + 4 * kb + 2);
-    const float av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+__device__ __forceinline__ void put2(__bf16* base, int stride_piece, float v0, float v1) {
+  __bf16 p0[NP], p1[NP];
+  split<NP>(v0, p0);
+  split<NP>(v1, p1);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      __bf16 pc[NP];
-      split_bf16<NP>(av[e], pc);
+  for (int u = 0; u < NP; ++u) {
+    bf16x2 w;
+    w[0] = p0[u];
+    w[1] = p1[u];
+    *reinterpret_cast<bf16x2*>(base + u * stride_piece) = w;
+  }
+}
+
+template <int NP>
+__device__ __forceinline__ void store_bf16(const CGemm& p, const Stage& st, LdsBf16<NP>& L, int buf, int tid) {
+  constexpr int sa = kBM * kKR, sb = 2 * kBN * kKR;
 #pragma unroll
-      for (int u = 0; u < NP; ++u) ap[u][e] = pc[u];
+  for (int j = 0; j < 2; ++j) {
+    const int pr = tid + kMT * j;
+    const float4 v = a_val(p, st, j);
+    if (p.lda_k == 1) {  // row m, real K 4(pr % 8) .. + 3
+      const int m = pr / 8, kr = 4 * (pr % 8);
+      __bf16* dst = &L.a[buf][0][m * kKR + kr];
+      put2<NP>(dst, sa, v.x, v.y);
+      put2<NP>(dst + 2, sa, v.z, v.w);
+    } else {  // rows m, m + 1, real K 2k, 2k + 1
+      const int k = pr / 32, m = 2 * (pr % 32);
+      put2<NP>(&L.a[buf][0][m * kKR + 2 * k], sa, v.x, v.y);
+      put2<NP>(&L.a[buf][0][(m + 1) * kKR + 2 * k], sa, v.z, v.w);
     }
   }
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int nc = 8 * t + mi / 2;
-    bf16x8 bp[NP];
+  for (int j = 0; j < 2; ++j) {
+    const int pr = tid + kMT * j;
+    const int k = pr / 32, n = 2 * (pr % 32);
+    const float4 v = b_val(p, st, j);
+    // complex b at column n': real column 2n' holds (Re b, -Im b) at real K (2k, 2k+1),
+    // real column 2n' + 1 holds (Im b, Re b)
+    put2<NP>(&L.b[buf][0][(2 * n) * kKR + 2 * k], sb, v.x, -v.y);
+    put2<NP>(&L.b[buf][0][(2 * n + 1) * kKR + 2 * k], sb, v.y, v.x);
+    put2<NP>(&L.b[buf][0][(2 * n + 2) * kKR + 2 * k], sb, v.z, -v.w);
+    put2<NP>(&L.b[buf][0][(2 * n + 3) * kKR + 2 * k], sb, v.w, v.z);
+  }
+}
+
+template <int NP>
+__device__ __forceinline__ void mma_bf16(const LdsBf16<NP>& L, int buf, int w, int lane, floatx4 (&acc)[kNT]) {
+  const int mi = lane % 16, kb = lane / 16;
+  bf16x8 ap[NP];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const float2 b = Bs[(4 * kb + e) * kBS + nc];
-      // expanded B rows 2k (Re A) and 2k + 1 (Im A) at real column 2n + q
-      const float v0 = q ? b.y : b.x, v1 = q ? b.x : -b.y;
-      __bf16 p0[NP], p1[NP];
-      split_bf16<NP>(v0, p0);
-      split_bf16<NP>(v1, p1);
+  for (int u = 0; u < NP; ++u) ap[u] = *reinterpret_cast<const bf16x8*>(&L.a[buf][u][(16 * w + mi) * kKR + 8 * kb]);
 #pragma unroll
-      for (int u = 0; u < NP; ++u) {
-        bp[u][2 * e] = p0[u];
-        bp[u][2 * e + 1] = p1[u];
+  for (int t = 0; t < kNT; t += 2) {
+    bf16x8 b0[NP], b1[NP];
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      b0[u] = *reinterpret_cast<const bf16x8*>(&L.b[buf][u][(16 * t + mi) * kKR + 8 * kb]);
+      b1[u] = *reinterpret_cast<const bf16x8*>(&L.b[buf][u][(16 * (t + 1) + mi) * kKR + 8 * kb]);
+    }
+    // smallest terms first; two independent accumulators interleaved
+    if constexpr (NP == 3) {
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[2], b0[0], acc[t], 0, 0, 0);
+      acc[t + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[2], b1[0], acc[t + 1], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[1], b0[1], acc[t], 0, 0, 0);
+      acc[t + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[1], b1[1], acc[t + 1], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[0], b0[2], acc[t], 0, 0, 0);
+      acc[t + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[0], b1[2], acc[t + 1], 0, 0, 0);
+    }
+    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[1], b0[0], acc[t], 0, 0, 0);
+    acc[t + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[1], b1[0], acc[t + 1], 0, 0, 0);
+    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[0], b0[1], acc[t], 0, 0, 0);
+    acc[t + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[0], b1[1], acc[t + 1], 0, 0, 0);
+    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[0], b0[0], acc[t], 0, 0, 0);
+    acc[t + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[0], b1[0], acc[t + 1], 0, 0, 0);
+  }
+}
+
+// ------------------------------------------------------------------- epilogue
+// Lane (ni, g) holds real rows 4g + i (i = 0..3) of real column 16t + ni.  Lanes ni
+// and ni ^ 1 hold the real and imaginary parts of one complex column: after one
+// exchange the even lane owns rows 4g, 4g + 1 and the odd lane rows 4g + 2, 4g + 3 as
+// complex values.
+__device__ __forceinline__ void epilogue(const CGemm& p, float2* Cp, int m0, int n0, int w, int lane,
+                                         const floatx4 (&acc)[kNT]) {
+  const int ni = lane % 16, g = lane / 16;
+  const bool odd = ni & 1;
+  const bool conj_out = p.flags & kConjC, atomic = p.flags & kAtomicC;
+#pragma unroll
+  for (int t = 0; t < kNT; ++t) {
+    const float s0 = odd ? acc[t][0] : acc[t][2];
+    const float s1 = odd ? acc[t][1] : acc[t][3];
+    const float r0 = __shfl_xor(s0, 1);
+    const float r1 = __shfl_xor(s1, 1);
+    // even lane: (acc0, r0), (acc1, r1) for rows 4g, 4g + 1; odd: (r0, acc2), (r1, acc3)
+    float2 c0 = odd ? make_float2(r0, acc[t][2]) : make_float2(acc[t][0], r0);
+    float2 c1 = odd ? make_float2(r1, acc[t][3]) : make_float2(acc[t][1], r1);
+    if (conj_out) {
+      c0.y = -c0.y;
+      c1.y = -c1.y;
+    }
+    const int n = n0 + 8 * t + ni / 2;
+    if (n >= p.N) continue;
+    const int64_t coff = p.c + col_off(n, p.c_ni, p.c_shi);
+    const int mb = m0 + 16 * w + 4 * g + (odd ? 2 : 0);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int m = mb + i;
+      if (m >= p.M) continue;
+      float2* dst = Cp + coff + (int64_t)m * p.ldc_m;
+      const float2 c = i ? c1 : c0;
+      if (atomic) {
+        atomicAdd(&dst->x, c.x);
+        atomicAdd(&dst->y, c.y);
+      } else {
+        *dst = c;
       }
     }
-    // smallest terms first
-    if constexpr (NP == 3) {
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[2], bp[0], acc[t], 0, 0, 0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[1], bp[1], acc[t], 0, 0, 0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[0], bp[2], acc[t], 0, 0, 0);
-    }
-    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[1], bp[0], acc[t], 0, 0, 0);
-    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[0], bp[1], acc[t], 0, 0, 0);
-    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[0], bp[0], acc[t], 0, 0, 0);
   }
 }
 
 // ------------------------------------------------------------------- kernel
 
-__device__ __forceinline__ float2* base_ptr(const CGemmBases& b, int i) {
-  // i is uniform across the workgroup: a select chain, no indexed private array
-  void* p = i == 0 ? b.p[0] : i == 1 ? b.p[1] : i == 2 ? b.p[2] : i == 3 ? b.p[3] : i == 4 ? b.p[4] : b.p[5];
-  return static_cast<float2*>(p);
+template <int VARIANT>
+struct LdsOf {
+  using type = LdsBf16<VARIANT + 1>;
+};
+template <>
+struct LdsOf<0> {
+  using type = LdsF32;
+};
+
+template <int VARIANT>
+__device__ __forceinline__ void store_stage(const CGemm& p, const Stage& st, typename LdsOf<VARIANT>::type& L, int buf,
+                                            int tid) {
+  if constexpr (VARIANT == 0)
+    store_f32(p, st, L, buf, tid);
+  else
+    store_bf16<VARIANT + 1>(p, st, L, buf, tid);
+}
+
+template <int VARIANT, bool AVEC>
+__device__ __forceinline__ void run_tile(const CGemm& p, const CTile& tl, const float2* A, const float2* B, float2* Cp,
+                                         typename LdsOf<VARIANT>::type& L) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int nsteps = (p.K + kKC - 1) / kKC;
+  const int nblk = (tl.n1 - tl.n0 + kBN - 1) / kBN;
+  const int total = nblk * nsteps;
+
+  floatx4 acc[kNT];
+#pragma unroll
+  for (int t = 0; t < kNT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  Stage st;
+  load_stage<AVEC>(p, A, B, tl.m0, tl.n0, 0, tid, st);
+  store_stage<VARIANT>(p, st, L, 0, tid);
+  __syncthreads();
+  for (int it = 0; it < total; ++it) {
+    const int cur = it & 1;
+    const int blk = it / nsteps, s = it - blk * nsteps;
+    if (it + 1 < total) {
+      const int nb = (it + 1) / nsteps, ns = (it + 1) - nb * nsteps;
+      load_stage<AVEC>(p, A, B, tl.m0, tl.n0 + nb * kBN, ns * kKC, tid, st);
+    }
+    if constexpr (VARIANT == 0)
+      mma_f32(L, cur, w, lane, acc);
+    else
+      mma_bf16<VARIANT + 1>(L, cur, w, lane, acc);
+    if (s == nsteps - 1) {
+      epilogue(p, Cp, tl.m0, tl.n0 + blk * kBN, w, lane, acc);
+#pragma unroll
+      for (int t = 0; t < kNT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    if (it + 1 < total) store_stage<VARIANT>(p, st, L, cur ^ 1, tid);
+    __syncthreads();
+  }
 }
 
 template <int VARIANT>
 __global__ __launch_bounds__(kMT) void cgemm_kernel(const CGemm* __restrict__ probs, const CTile* __restrict__ tiles,
                                                     CGemmBases bases) {
-  __shared__ __align__(16) float2 As[2][kBM * kAS];
-  __shared__ __align__(16) float2 Bs[2][kKC * kBS];
+  using Lds = typename LdsOf<VARIANT>::type;
+  __shared__ __align__(16) Lds L;
   const CTile tl = tiles[blockIdx.x];
   const CGemm p = probs[tl.prob];
   const float2* A = base_ptr(bases, p.abase);
   const float2* B = base_ptr(bases, p.bbase);
   float2* Cp = base_ptr(bases, p.cbase);
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int nsteps = (p.K + kKC - 1) / kKC;
-
-  for (int n0 = tl.n0; n0 < tl.n1; n0 += kBN) {
-    floatx4 acc[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-    Stage st;
-    load_stage(p, A, B, tl.m0, n0, 0, tid, st);
-    __syncthreads();  // previous column block finished reading LDS
-    store_stage(p, st, As[0], Bs[0], tid);
-    __syncthreads();
-    for (int s = 0; s < nsteps; ++s) {
-      const int cur = s & 1;
-      if (s + 1 < nsteps) load_stage(p, A, B, tl.m0, n0, (s + 1) * kKC, tid, st);
-      if constexpr (VARIANT == 0)
-        mma_step_f32(As[cur], Bs[cur], w, lane, acc);
-      else
-        mma_step_bf16<VARIANT + 1>(As[cur], Bs[cur], w, lane, acc);
-      if (s + 1 < nsteps) store_stage(p, st, As[cur ^ 1], Bs[cur ^ 1], tid);
-      __syncthreads();
-    }
-    // epilogue: lane (ni, g) holds real rows 4g + i, real column 16t + ni
-    const int ni = lane % 16, g = lane / 16;
-    const int q = ni & 1;
-    const bool conj_out = p.flags & kConjC, atomic = p.flags & kAtomicC;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int n = n0 + 8 * t + ni / 2;
-      if (n >= p.N) continue;
-      const int64_t coff = p.c + col_off(n, p.c_ni, p.c_shi);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int m = tl.m0 + 16 * w + 4 * g + i;
-        if (m >= p.M) continue;
-        float v = acc[t][i];
-        if (conj_out && q) v = -v;
-        float* dst = reinterpret_cast<float*>(Cp + coff + (int64_t)m * p.ldc_m) + q;
-        if (atomic)
-          atomicAdd(dst, v);
-        else
-          *dst = v;
-      }
-    }
-  }
+  // 16-byte A loads need an even complex offset for every pair
+  if (!((p.a | (p.lda_k == 1 ? p.lda_m : p.lda_k)) & 1))
+    run_tile<VARIANT, true>(p, tl, A, B, Cp, L);
+  else
+    run_tile<VARIANT, false>(p, tl, A, B, Cp, L);
 }
 
 template <typename C>

@@ -28,7 +28,7 @@ namespace tuckfmm {
 
 namespace {
 
-constexpr int kTileM = 64, kTileN = 32, kStepK = 16;  // tile shape of the grouped GEMM kernel
+constexpr int kTileM = 64, kTileN = 64, kStepK = 16;  // tile shape of the grouped GEMM kernel
 
 int64_t up32(int64_t n) { return (n + 31) / 32 * 32; }  // complex elements, 256-byte blocks
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
@@ -106,7 +106,7 @@ struct TileCost {
   int64_t cost;
 };
 
-// Work tiles of one product: 64-row blocks x groups of 32-column blocks.  A tile runs
+// Work tiles of one product: 64-row blocks x groups of 64-column blocks.  A tile runs
 // about tile_steps K steps; products with few column blocks keep them all in one tile
 // so their (large) A operand is read once.
 void tiles_of(const CGemm& g, int prob, int tile_steps, std::vector<TileCost>& out) {
