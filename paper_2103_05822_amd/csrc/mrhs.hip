@@ -20,8 +20,8 @@
 // values (32 real).  Four wavefronts, each owning 16 rows x 128 real columns = eight
 // 16 x 16 MFMA accumulators.  A workgroup walks its column blocks and K steps as one
 // flat pipeline: the global loads of step s + 1 are in flight while step s runs on the
-// matrix cores from LDS (double buffered); conjugation, B expansion and the bf16
-// split happen when a step is written to LDS.
+// matrix cores from LDS; conjugation, B expansion and the bf16 split happen when a
+// step is written to LDS (single buffered).
 //
 // Arithmetic variants (factors are stored as complex64 in every variant):
 //   0  FP32    v_mfma_f32_16x16x4_f32 on the FP32 operands;
@@ -44,7 +44,6 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kMT = 256;           // threads
 constexpr int kBM = 64;            // rows per tile
@@ -52,9 +51,8 @@ constexpr int kBN = 64;            // complex columns per block
 constexpr int kKC = 16;            // complex K per step
 constexpr int kKR = 2 * kKC;       // real K per step
 constexpr int kNT = 2 * kBN / 16;  // 16-column accumulators per wavefront (8)
-// FP32 LDS strides (complex): padding keeps 16-byte alignment and spreads banks
+// FP32 A LDS row stride (complex): padding keeps 16-byte alignment and spreads banks
 constexpr int kAS = kKC + 2;
-constexpr int kBS = kBN + 2;
 
 __device__ __forceinline__ int64_t col_off(int n, int ni, int shi) { return (int64_t)(n / ni) * shi + n % ni; }
 
@@ -65,158 +63,188 @@ __device__ __forceinline__ float2* base_ptr(const CGemmBases& b, int i) {
 }
 
 // ------------------------------------------------------------------ global loads
-// One K step of raw operands in registers: two complex pairs of A and two of B per
-// thread, plus validity bits.  Every load is unconditional (an invalid element reads
-// the operand's first element instead) and nothing consumes the loaded values before
-// the step is written to LDS, so the loads stay in flight while the previous step
-// runs on the matrix cores.  AVEC (uniform per product): A pairs are loaded as one
-// 16-byte access; the second element of a pair at the K (or M) tail then lies in the
-// zero padding of the factor row (rows are padded to an even length), and is masked.
+// Thread t owns four consecutive complex K values of one A row and of one B column:
+//   A  K-contiguous: row t / 4, K quad t % 4;   M-contiguous: row t % 64, K quad t / 64
+//   B  column t % 64, K quad t / 64
+// so that a step's piece of an operand is written to LDS as whole 16-byte chunks.
+// Each thread keeps a pointer to its quad that advances by one step per K step; an
+// element outside the product (row beyond M, column beyond N, K beyond the last
+// step's tail) is read from a clamp address inside the operand instead and zeroed
+// when the step is written to LDS.  Nothing consumes the loaded values before that
+// point, so the loads stay in flight while the previous step runs on the matrix cores.
 struct Stage {
-  float4 a[2];
-  float4 b[2];
-  uint32_t ok;  // bits 0-3: A halves (pair j: bits 2j, 2j+1); bits 4-5: B pairs
+  float2 a[4];
+  float2 b[4];
+  int na, nb;  // number of valid elements (a prefix of the quad)
 };
 
+// Per-thread operand walkers.
+struct Walk {
+  const float2* clampa;  // first element of A
+  const float2* a0;      // the thread's quad at K step 0 (clampa if the row is invalid)
+  const float2* a;       // the quad at the current K step
+  int64_t astep;         // pointer advance per K step (0 for an invalid row)
+  int aes;               // element stride inside the quad
+  int aq;                // K quad index (0..3)
+  bool arow;             // row valid
+  const float2* clampb;
+  const float2* b;
+  int64_t bstep;
+  int bes;
+  int bq;
+  bool bcol;
+};
+
+__device__ __forceinline__ void walk_init(const CGemm& p, const float2* A, const float2* B, int m0, int tid, Walk& w) {
+  const bool kc = p.lda_k == 1;
+  const int am = m0 + (kc ? tid / 4 : tid % 64);
+  w.aq = kc ? tid % 4 : tid / 64;
+  w.arow = am < p.M;
+  w.clampa = A + p.a;
+  w.aes = kc ? 1 : p.lda_k;
+  w.a0 = w.arow ? w.clampa + (kc ? (int64_t)am * p.lda_m + 4 * w.aq : am + (int64_t)(4 * w.aq) * p.lda_k) : w.clampa;
+  w.a = w.a0;
+  w.astep = w.arow ? (kc ? (int64_t)kKC : (int64_t)kKC * p.lda_k) : 0;
+  w.clampb = B + p.b;
+  w.bq = tid / 64;
+  w.bes = p.ldb_k;
+}
+
+// Points the B walker at column block n0 (K step 0).
+__device__ __forceinline__ void walk_block(const CGemm& p, int n0, int tid, Walk& w) {
+  const int n = n0 + tid % 64;
+  w.bcol = n < p.N;
+  w.b = w.bcol ? w.clampb + col_off(n, p.b_ni, p.b_shi) + (int64_t)(4 * w.bq) * p.ldb_k : w.clampb;
+  w.bstep = w.bcol ? (int64_t)kKC * p.ldb_k : 0;
+  w.a = w.a0;
+}
+
+// AVEC (uniform per product; K-contiguous A with even offset and row stride): A is
+// read as two 16-byte pairs.  A pair whose first element is valid is read whole; at
+// an odd K its second element is the row's zero padding (factor rows are padded to
+// an even length) and is masked.
 template <bool AVEC>
-__device__ __forceinline__ void load_stage(const CGemm& p, const float2* A, const float2* B, int m0, int n0, int k0,
-                                           int tid, Stage& st) {
-  uint32_t ok = 0;
-  const float2* a0 = A + p.a;
+__device__ __forceinline__ void load_stage(const CGemm& p, int k0, Walk& w, Stage& st) {
+  const int na = w.arow ? min(4, max(0, p.K - k0 - 4 * w.aq)) : 0;
+  const int nb = w.bcol ? min(4, max(0, p.K - k0 - 4 * w.bq)) : 0;
+  const float2* pa = na > 0 ? w.a : w.clampa;
+  if constexpr (AVEC) {
+    const float4 u = *reinterpret_cast<const float4*>(pa);
+    const float4 v = *reinterpret_cast<const float4*>(pa + (na > 2 ? 2 : 0));
+    st.a[0] = make_float2(u.x, u.y);
+    st.a[1] = make_float2(u.z, u.w);
+    st.a[2] = make_float2(v.x, v.y);
+    st.a[3] = make_float2(v.z, v.w);
+  } else {
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int pr = tid + kMT * j;  // pair index 0..511
-    bool ok0, ok1;
-    int64_t i0, i1;
-    if (p.lda_k == 1) {  // K contiguous: pair = (m, k), (m, k + 1)
-      const int m = m0 + pr / 8, k = k0 + 2 * (pr % 8);
-      ok0 = m < p.M && k < p.K;
-      ok1 = m < p.M && k + 1 < p.K;
-      i0 = (int64_t)m * p.lda_m + k;
-      i1 = i0 + 1;
-    } else {  // M contiguous: pair = (m, k), (m + 1, k)
-      const int k = k0 + pr / 32, m = m0 + 2 * (pr % 32);
-      ok0 = k < p.K && m < p.M;
-      ok1 = k < p.K && m + 1 < p.M;
-      i0 = m + (int64_t)k * p.lda_k;
-      i1 = i0 + 1;
-    }
-    if constexpr (AVEC) {
-      st.a[j] = *reinterpret_cast<const float4*>(a0 + (ok0 ? i0 : 0));
-    } else {
-      const float2 u0 = a0[ok0 ? i0 : 0];
-      const float2 u1 = a0[ok1 ? i1 : 0];
-      st.a[j] = make_float4(u0.x, u0.y, u1.x, u1.y);
-    }
-    ok |= (ok0 ? 1u : 0u) << (2 * j);
-    ok |= (ok1 ? 1u : 0u) << (2 * j + 1);
+    for (int e = 0; e < 4; ++e) st.a[e] = pa[e < na ? e * w.aes : 0];
   }
+  const float2* pb = nb > 0 ? w.b : w.clampb;
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int pr = tid + kMT * j;
-    const int k = k0 + pr / 32, n = n0 + 2 * (pr % 32);
-    const bool okb = k < p.K && n < p.N;  // N and the column blocks are even: a pair never splits
-    const int64_t ib = okb ? (int64_t)k * p.ldb_k + col_off(n, p.b_ni, p.b_shi) : 0;
-    st.b[j] = *reinterpret_cast<const float4*>(B + p.b + ib);
-    ok |= (okb ? 1u : 0u) << (4 + j);
-  }
-  st.ok = ok;
+  for (int e = 0; e < 4; ++e) st.b[e] = pb[e < nb ? e * w.bes : 0];
+  st.na = na;
+  st.nb = nb;
+  w.a += w.astep;
+  w.b += w.bstep;
 }
 
-// Operand values of a stage with the invalid elements zeroed and the conjugation
-// flags applied (this is where the loads are waited for).
-__device__ __forceinline__ float4 a_val(const CGemm& p, const Stage& st, int j) {
-  float4 v = st.a[j];
-  if (!(st.ok & (1u << (2 * j)))) v.x = v.y = 0.f;
-  if (!(st.ok & (1u << (2 * j + 1)))) v.z = v.w = 0.f;
-  if (p.flags & kConjA) {
-    v.y = -v.y;
-    v.w = -v.w;
-  }
+// Element e of the stage's A (B) values with invalid elements zeroed and the
+// conjugation flag applied -- the point where the loads are waited for.
+__device__ __forceinline__ float2 a_val(const CGemm& p, const Stage& st, int e) {
+  float2 v = e < st.na ? st.a[e] : make_float2(0.f, 0.f);
+  if (p.flags & kConjA) v.y = -v.y;
   return v;
 }
 
-__device__ __forceinline__ float4 b_val(const CGemm& p, const Stage& st, int j) {
-  float4 v = st.b[j];
-  if (!(st.ok & (1u << (4 + j)))) v = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (p.flags & kConjB) {
-    v.y = -v.y;
-    v.w = -v.w;
-  }
+__device__ __forceinline__ float2 b_val(const CGemm& p, const Stage& st, int e) {
+  float2 v = e < st.nb ? st.b[e] : make_float2(0.f, 0.f);
+  if (p.flags & kConjB) v.y = -v.y;
   return v;
+}
+
+// Row / K quad of the thread's A values in the tile (see walk_init).
+__device__ __forceinline__ void a_slot(const CGemm& p, int tid, int& m, int& kq) {
+  if (p.lda_k == 1) {
+    m = tid / 4;
+    kq = tid % 4;
+  } else {
+    m = tid % 64;
+    kq = tid / 64;
+  }
 }
 
 // ------------------------------------------------------------------- FP32 variant
+// LDS: A complex [row][K]; B already expanded, [K][complex column][q] with q = 0 the
+// pair (Re b, -Im b) and q = 1 the pair (Im b, Re b): the expanded-B values a lane
+// with column parity q needs for real rows 2k and 2k + 1.
+constexpr int kXS = 2 * kBN + 4;  // expanded-B row stride (float2)
+
 struct LdsF32 {
-  float2 a[2][kBM * kAS];
-  float2 b[2][kKC * kBS];
+  float2 a[kBM * kAS];
+  float2 b[kKC * kXS];
 };
 
-__device__ __forceinline__ void store_f32(const CGemm& p, const Stage& st, LdsF32& L, int buf, int tid) {
+__device__ __forceinline__ void store_f32(const CGemm& p, const Stage& st, LdsF32& L, int tid) {
+  int m, kq;
+  a_slot(p, tid, m, kq);
+  float2* da = &L.a[m * kAS + 4 * kq];
+  const float2 a0 = a_val(p, st, 0), a1 = a_val(p, st, 1), a2 = a_val(p, st, 2), a3 = a_val(p, st, 3);
+  *reinterpret_cast<float4*>(da) = make_float4(a0.x, a0.y, a1.x, a1.y);
+  *reinterpret_cast<float4*>(da + 2) = make_float4(a2.x, a2.y, a3.x, a3.y);
+  const int nn = tid % 64, kb = 4 * (tid / 64);
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int pr = tid + kMT * j;
-    const float4 v = a_val(p, st, j);
-    if (p.lda_k == 1) {
-      const int m = pr / 8, k = 2 * (pr % 8);
-      *reinterpret_cast<float4*>(&L.a[buf][m * kAS + k]) = v;
-    } else {
-      const int k = pr / 32, m = 2 * (pr % 32);
-      L.a[buf][m * kAS + k] = make_float2(v.x, v.y);
-      L.a[buf][(m + 1) * kAS + k] = make_float2(v.z, v.w);
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int pr = tid + kMT * j;
-    const int k = pr / 32, n = 2 * (pr % 32);
-    *reinterpret_cast<float4*>(&L.b[buf][k * kBS + n]) = b_val(p, st, j);
+  for (int e = 0; e < 4; ++e) {
+    const float2 v = b_val(p, st, e);
+    *reinterpret_cast<float4*>(&L.b[(kb + e) * kXS + 2 * nn]) = make_float4(v.x, -v.y, v.y, v.x);
   }
 }
 
 // Lane (mi, kb) of wavefront w: rows 16w + mi.  The real K index of instruction
 // (h, s) is 16h + 4kb + s (a permutation of the step's 32 real indices, applied
-// identically to A and B); B column lane mi covers real column 16t + mi.
-__device__ __forceinline__ void mma_f32(const LdsF32& L, int buf, int w, int lane, floatx4 (&acc)[kNT]) {
+// identically to A and B); B column lane mi covers real column 16t + mi.  (The MFMA
+// sequence is straight-line code: a branch around it would make the compiler move
+// the accumulators between register files.)
+__device__ __forceinline__ void mma_f32(const LdsF32& L, int w, int lane, floatx4 (&acc)[kNT]) {
   const int mi = lane % 16, kb = lane / 16;
-  const bool q = mi & 1;  // real column parity (0: Re C, 1: Im C)
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const float4 a = *reinterpret_cast<const float4*>(&L.a[buf][(16 * w + mi) * kAS + 8 * h + 2 * kb]);
+    const float4 a = *reinterpret_cast<const float4*>(&L.a[(16 * w + mi) * kAS + 8 * h + 2 * kb]);
     const float av[4] = {a.x, a.y, a.z, a.w};
 #pragma unroll
     for (int t0 = 0; t0 < kNT; t0 += kNT / 2) {  // two halves: four independent accumulators each
-      float bv[kNT / 2][4];
+      float2 b0[kNT / 2], b1[kNT / 2];
 #pragma unroll
       for (int u = 0; u < kNT / 2; ++u) {
-        const int nc = 8 * (t0 + u) + mi / 2;
-        const float2 b0 = L.b[buf][(8 * h + 2 * kb) * kBS + nc];
-        const float2 b1 = L.b[buf][(8 * h + 2 * kb + 1) * kBS + nc];
-        // expanded B rows 2k (Re A) and 2k + 1 (Im A) at real column 2n + q
-        bv[u][0] = q ? b0.y : b0.x;
-        bv[u][1] = q ? b0.x : -b0.y;
-        bv[u][2] = q ? b1.y : b1.x;
-        bv[u][3] = q ? b1.x : -b1.y;
+        const int col = 16 * (t0 + u) + mi;  // = 2 (complex column) + q
+        b0[u] = L.b[(8 * h + 2 * kb) * kXS + col];
+        b1[u] = L.b[(8 * h + 2 * kb + 1) * kXS + col];
       }
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+      for (int u = 0; u < kNT / 2; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0], b0[u].x, acc[t0 + u], 0, 0, 0);
 #pragma unroll
-        for (int u = 0; u < kNT / 2; ++u)
-          acc[t0 + u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bv[u][s], acc[t0 + u], 0, 0, 0);
+      for (int u = 0; u < kNT / 2; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[1], b0[u].y, acc[t0 + u], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < kNT / 2; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2], b1[u].x, acc[t0 + u], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < kNT / 2; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[3], b1[u].y, acc[t0 + u], 0, 0, 0);
     }
   }
 }
 
 // ------------------------------------------------------------------- BF16 variants
-// LDS holds the operands pre-split: A as [piece][row][32 real K] and the expanded B
-// as [piece][real column][32 real K], bf16, so every lane reads its 8 K values of a
-// piece with one 16-byte load.
+// LDS holds the operands pre-split: A as [piece][row][32 real K] and
+// the expanded B as [piece][real column][32 real K], bf16, rows padded to 80 bytes
+// (conflict-free 16-byte accesses), so every lane reads its 8 K values of a piece
+// with one 16-byte load.
+constexpr int kPR = kKR + 8;  // bf16 row stride
+
 template <int NP>
 struct LdsBf16 {
-  __bf16 a[2][NP][kBM * kKR];
-  __bf16 b[2][NP][2 * kBN * kKR];
+  __bf16 a[NP][kBM * kPR];
+  __bf16 b[NP][2 * kBN * kPR];
 };
 
+// bf16 pieces of v: v ~ pc[0] + pc[1] (+ pc[2]), each the rounding of what is left.
 template <int NP>
 __device__ __forceinline__ void split(float v, __bf16 (&pc)[NP]) {
   pc[0] = (__bf16)v;
@@ -228,82 +256,86 @@ __device__ __forceinline__ void split(float v, __bf16 (&pc)[NP]) {
   }
 }
 
-// Splits two consecutive real values and writes each piece as one bf16 pair.
-template <int NP>
-__device__ __forceinline__ void put2(__bf16* base, int stride_piece, float v0, float v1) {
-  __bf16 p0[NP], p1[NP];
-  split<NP>(v0, p0);
-  split<NP>(v1, p1);
-#pragma unroll
-  for (int u = 0; u < NP; ++u) {
-    bf16x2 w;
-    w[0] = p0[u];
-    w[1] = p1[u];
-    *reinterpret_cast<bf16x2*>(base + u * stride_piece) = w;
-  }
-}
+__device__ __forceinline__ __bf16 bneg(__bf16 x) { return -x; }
 
 template <int NP>
-__device__ __forceinline__ void store_bf16(const CGemm& p, const Stage& st, LdsBf16<NP>& L, int buf, int tid) {
-  constexpr int sa = kBM * kKR, sb = 2 * kBN * kKR;
+__device__ __forceinline__ void store_bf16(const CGemm& p, const Stage& st, LdsBf16<NP>& L, int tid) {
+  {
+    int m, kq;
+    a_slot(p, tid, m, kq);
+    bf16x8 out[NP];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int pr = tid + kMT * j;
-    const float4 v = a_val(p, st, j);
-    if (p.lda_k == 1) {  // row m, real K 4(pr % 8) .. + 3
-      const int m = pr / 8, kr = 4 * (pr % 8);
-      __bf16* dst = &L.a[buf][0][m * kKR + kr];
-      put2<NP>(dst, sa, v.x, v.y);
-      put2<NP>(dst + 2, sa, v.z, v.w);
-    } else {  // rows m, m + 1, real K 2k, 2k + 1
-      const int k = pr / 32, m = 2 * (pr % 32);
-      put2<NP>(&L.a[buf][0][m * kKR + 2 * k], sa, v.x, v.y);
-      put2<NP>(&L.a[buf][0][(m + 1) * kKR + 2 * k], sa, v.z, v.w);
+    for (int e = 0; e < 4; ++e) {
+      const float2 v = a_val(p, st, e);
+      __bf16 re[NP], im[NP];
+      split<NP>(v.x, re);
+      split<NP>(v.y, im);
+#pragma unroll
+      for (int u = 0; u < NP; ++u) {
+        out[u][2 * e] = re[u];
+        out[u][2 * e + 1] = im[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NP; ++u) *reinterpret_cast<bf16x8*>(&L.a[u][m * kPR + 8 * kq]) = out[u];
+  }
+  {
+    // complex b at column n: real column 2n holds (Re b, -Im b) at real K (2k, 2k + 1),
+    // real column 2n + 1 holds (Im b, Re b).  split(-v) = -split(v) (rounding to
+    // nearest is symmetric), so the pieces are split once and negated.
+    const int nn = tid % 64, kq = tid / 64;
+    bf16x8 c0[NP], c1[NP];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float2 v = b_val(p, st, e);
+      __bf16 re[NP], im[NP];
+      split<NP>(v.x, re);
+      split<NP>(v.y, im);
+#pragma unroll
+      for (int u = 0; u < NP; ++u) {
+        c0[u][2 * e] = re[u];
+        c0[u][2 * e + 1] = bneg(im[u]);
+        c1[u][2 * e] = im[u];
+        c1[u][2 * e + 1] = re[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      *reinterpret_cast<bf16x8*>(&L.b[u][(2 * nn) * kPR + 8 * kq]) = c0[u];
+      *reinterpret_cast<bf16x8*>(&L.b[u][(2 * nn + 1) * kPR + 8 * kq]) = c1[u];
     }
   }
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int pr = tid + kMT * j;
-    const int k = pr / 32, n = 2 * (pr % 32);
-    const float4 v = b_val(p, st, j);
-    // complex b at column n': real column 2n' holds (Re b, -Im b) at real K (2k, 2k+1),
-    // real column 2n' + 1 holds (Im b, Re b)
-    put2<NP>(&L.b[buf][0][(2 * n) * kKR + 2 * k], sb, v.x, -v.y);
-    put2<NP>(&L.b[buf][0][(2 * n + 1) * kKR + 2 * k], sb, v.y, v.x);
-    put2<NP>(&L.b[buf][0][(2 * n + 2) * kKR + 2 * k], sb, v.z, -v.w);
-    put2<NP>(&L.b[buf][0][(2 * n + 3) * kKR + 2 * k], sb, v.w, v.z);
-  }
 }
 
 template <int NP>
-__device__ __forceinline__ void mma_bf16(const LdsBf16<NP>& L, int buf, int w, int lane, floatx4 (&acc)[kNT]) {
+__device__ __forceinline__ void mma_pair(const bf16x8 (&ap)[NP], const bf16x8 (&bp)[NP], floatx4& acc) {
+  // smallest terms first
+  if constexpr (NP == 3) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[2], bp[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[1], bp[1], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[0], bp[2], acc, 0, 0, 0);
+  }
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[1], bp[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[0], bp[1], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[0], bp[0], acc, 0, 0, 0);
+}
+
+template <int NP>
+__device__ __forceinline__ void mma_bf16(const LdsBf16<NP>& L, int w, int lane, floatx4 (&acc)[kNT]) {
   const int mi = lane % 16, kb = lane / 16;
   bf16x8 ap[NP];
 #pragma unroll
-  for (int u = 0; u < NP; ++u) ap[u] = *reinterpret_cast<const bf16x8*>(&L.a[buf][u][(16 * w + mi) * kKR + 8 * kb]);
+  for (int u = 0; u < NP; ++u) ap[u] = *reinterpret_cast<const bf16x8*>(&L.a[u][(16 * w + mi) * kPR + 8 * kb]);
 #pragma unroll
   for (int t = 0; t < kNT; t += 2) {
     bf16x8 b0[NP], b1[NP];
 #pragma unroll
     for (int u = 0; u < NP; ++u) {
-      b0[u] = *reinterpret_cast<const bf16x8*>(&L.b[buf][u][(16 * t + mi) * kKR + 8 * kb]);
-      b1[u] = *reinterpret_cast<const bf16x8*>(&L.b[buf][u][(16 * (t + 1) + mi) * kKR + 8 * kb]);
+      b0[u] = *reinterpret_cast<const bf16x8*>(&L.b[u][(16 * t + mi) * kPR + 8 * kb]);
+      b1[u] = *reinterpret_cast<const bf16x8*>(&L.b[u][(16 * (t + 1) + mi) * kPR + 8 * kb]);
     }
-    // smallest terms first; two independent accumulators interleaved
-    if constexpr (NP == 3) {
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[2], b0[0], acc[t], 0, 0, 0);
-      acc[t + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[2], b1[0], acc[t + 1], 0, 0, 0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[1], b0[1], acc[t], 0, 0, 0);
-      acc[t + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[1], b1[1], acc[t + 1], 0, 0, 0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[0], b0[2], acc[t], 0, 0, 0);
-      acc[t + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[0], b1[2], acc[t + 1], 0, 0, 0);
-    }
-    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[1], b0[0], acc[t], 0, 0, 0);
-    acc[t + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[1], b1[0], acc[t + 1], 0, 0, 0);
-    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[0], b0[1], acc[t], 0, 0, 0);
-    acc[t + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[0], b1[1], acc[t + 1], 0, 0, 0);
-    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[0], b0[0], acc[t], 0, 0, 0);
-    acc[t + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[0], b1[0], acc[t + 1], 0, 0, 0);
+    mma_pair<NP>(ap, b0, acc[t]);
+    mma_pair<NP>(ap, b1, acc[t + 1]);
   }
 }
 
@@ -362,47 +394,68 @@ struct LdsOf<0> {
 };
 
 template <int VARIANT>
-__device__ __forceinline__ void store_stage(const CGemm& p, const Stage& st, typename LdsOf<VARIANT>::type& L, int buf,
-                                            int tid) {
+__device__ __forceinline__ void store_stage(const CGemm& p, const Stage& st, typename LdsOf<VARIANT>::type& L, int tid) {
   if constexpr (VARIANT == 0)
-    store_f32(p, st, L, buf, tid);
+    store_f32(p, st, L, tid);
   else
-    store_bf16<VARIANT + 1>(p, st, L, buf, tid);
+    store_bf16<VARIANT + 1>(p, st, L, tid);
 }
 
+template <int VARIANT>
+__device__ __forceinline__ void mma_stage(const typename LdsOf<VARIANT>::type& L, int w, int lane,
+                                          floatx4 (&acc)[kNT]) {
+  if constexpr (VARIANT == 0)
+    mma_f32(L, w, lane, acc);
+  else
+    mma_bf16<VARIANT + 1>(L, w, lane, acc);
+}
+
+// One tile: column blocks n0 = tl.n0, tl.n0 + 64, ... below tl.n1, each a full K
+// sweep, walked as one pipeline over (block, K step).  LDS is single buffered: the
+// loads of the next step are issued before the current step's matrix-core work and
+// written to LDS after it.
 template <int VARIANT, bool AVEC>
 __device__ __forceinline__ void run_tile(const CGemm& p, const CTile& tl, const float2* A, const float2* B, float2* Cp,
                                          typename LdsOf<VARIANT>::type& L) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int nsteps = (p.K + kKC - 1) / kKC;
-  const int nblk = (tl.n1 - tl.n0 + kBN - 1) / kBN;
-  const int total = nblk * nsteps;
 
   floatx4 acc[kNT];
 #pragma unroll
   for (int t = 0; t < kNT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  Walk wk;
+  walk_init(p, A, B, tl.m0, tid, wk);
+  walk_block(p, tl.n0, tid, wk);
   Stage st;
-  load_stage<AVEC>(p, A, B, tl.m0, tl.n0, 0, tid, st);
-  store_stage<VARIANT>(p, st, L, 0, tid);
+  load_stage<AVEC>(p, 0, wk, st);
+  store_stage<VARIANT>(p, st, L, tid);
   __syncthreads();
-  for (int it = 0; it < total; ++it) {
-    const int cur = it & 1;
-    const int blk = it / nsteps, s = it - blk * nsteps;
-    if (it + 1 < total) {
-      const int nb = (it + 1) / nsteps, ns = (it + 1) - nb * nsteps;
-      load_stage<AVEC>(p, A, B, tl.m0, tl.n0 + nb * kBN, ns * kKC, tid, st);
+  for (int n0 = tl.n0;;) {
+    // K sweep of one column block; the epilogue stays outside this loop so that the
+    // accumulators never cross a branch inside it
+    for (int s = 0; s < nsteps; ++s) {
+      int nn0 = n0, ns = s + 1;
+      if (ns == nsteps) {
+        ns = 0;
+        nn0 += kBN;
+      }
+      const bool more = nn0 < tl.n1;
+      if (more) {
+        if (ns == 0) walk_block(p, nn0, tid, wk);
+        load_stage<AVEC>(p, ns * kKC, wk, st);
+      }
+      mma_stage<VARIANT>(L, w, lane, acc);
+      if (more) {
+        __syncthreads();  // every wavefront is done reading the step
+        store_stage<VARIANT>(p, st, L, tid);
+        __syncthreads();
+      }
     }
-    if constexpr (VARIANT == 0)
-      mma_f32(L, cur, w, lane, acc);
-    else
-      mma_bf16<VARIANT + 1>(L, cur, w, lane, acc);
-    if (s == nsteps - 1) {
-      epilogue(p, Cp, tl.m0, tl.n0 + blk * kBN, w, lane, acc);
+    epilogue(p, Cp, tl.m0, n0, w, lane, acc);
+    n0 += kBN;
+    if (n0 >= tl.n1) break;
 #pragma unroll
-      for (int t = 0; t < kNT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-    }
-    if (it + 1 < total) store_stage<VARIANT>(p, st, L, cur ^ 1, tid);
-    __syncthreads();
+    for (int t = 0; t < kNT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
   }
 }
 
@@ -416,8 +469,8 @@ __global__ __launch_bounds__(kMT) void cgemm_kernel(const CGemm* __restrict__ pr
   const float2* A = base_ptr(bases, p.abase);
   const float2* B = base_ptr(bases, p.bbase);
   float2* Cp = base_ptr(bases, p.cbase);
-  // 16-byte A loads need an even complex offset for every pair
-  if (!((p.a | (p.lda_k == 1 ? p.lda_m : p.lda_k)) & 1))
+  // 16-byte A loads: K-contiguous A with an even offset and row stride
+  if (p.lda_k == 1 && !((p.a | p.lda_m) & 1))
     run_tile<VARIANT, true>(p, tl, A, B, Cp, L);
   else
     run_tile<VARIANT, false>(p, tl, A, B, Cp, L);
