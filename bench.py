@@ -29,6 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 1 << 30
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_sphere30.md")
 
 
 def log(*a):
@@ -40,11 +42,20 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="sphere30", choices=["sphere30", "sphere30g29", "sphere6", "small"])
+    p.add_argument("--workload", default="sphere30",
+                   choices=["sphere30", "sphere30g29", "sphere6", "small", "sphere20b0.5", "sphere20b1", "sphere20b2",
+                            "sphere20b4", "sphere45"])
     p.add_argument("--sample-groups", type=int, default=6, help="groups checked against the oracle")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU timing")
     p.add_argument("--no-oracle", action="store_true", help="skip accuracy sampling and the CPU baseline")
     p.add_argument("--no-dense", action="store_true", help="Tucker stages only (profiling runs)")
+    p.add_argument("--nrhs", type=int, default=None,
+                   help="right-hand sides of the multi-RHS section (default: the workload's, else 64; 0: skip)")
+    p.add_argument("--mrhs-precs", default="c64,bf16x2,bf16x3",
+                   help="precisions of the multi-RHS section (c128, c64, bf16x2, bf16x3)")
+    p.add_argument("--setup-chunk", type=int, default=128,
+                   help="groups per far-field fill + compress chunk when the dense tensor is not kept")
+    p.add_argument("--mrhs-steps", type=int, default=10, help="timed passes per multi-RHS precision")
     p.add_argument("--save-factors", default=None, help="write the compressed factors to this .npz")
     p.add_argument("--load-factors", default=None, help="read the factors from this .npz instead of compressing")
     return p.parse_args()
@@ -52,7 +63,11 @@ def parse():
 
 def workload(name):
     from synth import workloads as W
-    return {"sphere30": W.SPHERE30, "sphere30g29": W.SPHERE30_G29, "sphere6": W.SPHERE6, "small": W.SMALL}[name]
+    table = {"sphere30": W.SPHERE30, "sphere30g29": W.SPHERE30_G29, "sphere6": W.SPHERE6, "small": W.SMALL,
+             "sphere45": W.SPHERE45}
+    for box, wl in W.SPHERE20.items():
+        table["sphere20b%g" % box] = wl
+    return table[name]
 
 
 def tucker_stage_bytes(ranks, offsets, n_theta, n_phi, es):
@@ -63,6 +78,40 @@ def tucker_stage_bytes(ranks, offsets, n_theta, n_phi, es):
     fac = (nb[:, None] * rb + n_theta * rt + n_phi * rp + rt * rp * rb).sum()
     io = int(offsets[-1]) + 2 * (offsets.size - 1) * n_theta * n_phi
     return int(es * (fac + io)), int(es * fac)
+
+
+def tucker_stage_flops(ranks, offsets, n_theta, n_phi, nrhs):
+    """Algorithmic real flops of one Tucker stage for nrhs right-hand sides: 8 per
+    complex multiply-add, the beta and core contractions plus the cheaper order of the
+    two angular ones."""
+    nb = np.diff(offsets)[:, None]
+    rt, rp, rb = ranks[..., 0].astype(np.int64), ranks[..., 1].astype(np.int64), ranks[..., 2].astype(np.int64)
+    ang = np.minimum(n_theta * rp * (rt + n_phi), rt * n_phi * (rp + n_theta))
+    return int(8 * nrhs * (nb * rb + rt * rp * rb + ang).sum())
+
+
+def kernel_source_sha(name):
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2103_05822_amd", "csrc", name), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, source):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary:
+    FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by the ratio of known bytes to
+    the counter's reading for the calibration copy.  None when the summary is missing
+    or was taken from another version of the kernel's source file."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = {}
+    for ln in open(TRAFFIC_FILE):
+        if ln.startswith("traffic:"):
+            kv = dict(t.split("=", 1) for t in ln.split()[1:])
+            rec[kv["kernel"]] = kv
+    r = rec.get(kernel)
+    if r is None or r.get("src_sha") != kernel_source_sha(source):
+        return None
+    return int(float(r["hbm_bytes"]))
 
 
 def dense_stage_bytes(offsets, n_theta, n_phi, es):
@@ -117,21 +166,39 @@ def main():
     lay = T.fmm_geometry_layout(geom)
     N, G, nd = lay.n_basis, lay.n_groups, lay.n_dir
     log("geometry: N=%d groups=%d grid=%dx%d" % (N, G, w.n_theta, w.n_phi))
-    dense = torch.empty((N, 2, w.n_theta, w.n_phi), dtype=torch.complex128, device="cuda")
-    T.fmm_farfield_fill(geom, 0, G, dense)
-    torch.cuda.synchronize()
+    if args.workload == "sphere45":
+        args.no_dense = True   # the dense far-fields of this workload are never materialised
+    if args.nrhs is None:
+        args.nrhs = w.nrhs if w.nrhs > 1 else 64
     t0 = time.time()
+    dense = None
+    if not args.no_dense:
+        dense = torch.empty((N, 2, w.n_theta, w.n_phi), dtype=torch.complex128, device="cuda")
+        T.fmm_farfield_fill(geom, 0, G, dense)
+        torch.cuda.synchronize()
     if args.load_factors:
         h = load_factors(T, lay, args.load_factors)
         log("factors loaded from %s (%.1f s)" % (args.load_factors, time.time() - t0))
     else:
+        # group chunks: progress shows during long setups; without a dense tensor every
+        # chunk's far-fields are filled into one reusable buffer and compressed (streaming)
         h = None
-        chunk = 128
-        for g0 in range(0, G, chunk):   # group chunks, so progress shows during long setups
+        chunk = args.setup_chunk
+        buf = None
+        if dense is None:
+            rows = max(int(lay.offsets[min(G, g0 + chunk)] - lay.offsets[g0]) for g0 in range(0, G, chunk))
+            buf = torch.empty((rows, 2, w.n_theta, w.n_phi), dtype=torch.complex128, device="cuda")
+        for g0 in range(0, G, chunk):
             cnt = min(chunk, G - g0)
             rows0 = int(lay.offsets[g0])
-            h = T.fmm_farfield_compress(lay, dense[rows0:], g0, cnt, w.gamma, handle=h)
+            if dense is None:
+                T.fmm_farfield_fill(geom, g0, cnt, buf)
+                src = buf
+            else:
+                src = dense[rows0:]
+            h = T.fmm_farfield_compress(lay, src, g0, cnt, w.gamma, handle=h)
             log("compress: groups %d..%d done (%.1f s)" % (g0, g0 + cnt - 1, time.time() - t0))
+        src = buf = None   # a view of `dense` would keep it alive
     t_compress = time.time() - t0
     ranks = T.fmm_tucker_ranks(h, G)
     if args.save_factors:
@@ -202,17 +269,18 @@ def main():
         ms[name] = float(np.mean([a.elapsed_time(b) for a, b in evs]))
     log("stage ms: %s" % {k: round(v, 4) for k, v in ms.items()})
 
-    # practical-bandwidth reference: a plain 2 GiB device-to-device copy
-    csrc = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")
+    # practical-bandwidth reference and HBM-counter calibration: a plain elementwise
+    # copy (dst = src * 1) of 1 GiB, 1 GiB read + 1 GiB written per launch
+    csrc = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     cdst = torch.empty_like(csrc)
-    cdst.copy_(csrc)
+    torch.mul(csrc, 1.0, out=cdst)
     cev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
     for a, b in cev:
         a.record()
-        cdst.copy_(csrc)
+        torch.mul(csrc, 1.0, out=cdst)
         b.record()
     torch.cuda.synchronize()
-    copy_gbs = 2 * csrc.numel() / (min(a.elapsed_time(b) for a, b in cev) * 1e-3) / 1e9
+    copy_gbs = 2 * COPY_BYTES / (min(a.elapsed_time(b) for a, b in cev) * 1e-3) / 1e9
     del csrc, cdst
 
     b_t32, fac32 = tucker_stage_bytes(ranks, lay.offsets, w.n_theta, w.n_phi, 8)
@@ -244,7 +312,8 @@ def main():
         "stage_GBps": {k: round(v, 1) for k, v in gbs.items()},
         "roofline": {"bound": "hbm", "kernel": "tucker_pass_kernel<float> (+ V zeroing)", "achieved": round(gbs[dom], 1),
                      "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(gbs[dom] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(gbs[dom] / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("tucker_pass_kernel<float>", "tucker.hip"),
                      "bytes_per_launch": per_stage_bytes[dom]},
         "copy_GBps": round(copy_gbs, 1),
         "memory_MB": {"tucker_factors_f32": round(fac32 / 2 ** 20, 1),
@@ -263,13 +332,20 @@ def main():
                                       "disagg": round(ms["dense_disagg_f64"] / ms["tucker_disagg_f32"], 2),
                                       "pass": round(dense_ms / tucker_ms, 2)}
 
+    # ------------------------------------------------------------ multi-RHS section
+    mr_out = {}
+    if args.nrhs > 0:
+        dense = None
+        torch.cuda.empty_cache()
+        result["multi_rhs"], mr_out = multi_rhs(args, T, torch, synth, h, lay, ranks, w)
+
     # ------------------------------------------------ accuracy + CPU baseline (oracle)
     if not args.no_oracle:
         F32h, V32h = F32.cpu().numpy(), V32.cpu().numpy()
         F64h = V64h = None
         if not args.no_dense:
             F64h, V64h = F64.cpu().numpy(), V64.cpu().numpy()
-        result.update(oracle_checks(args, w, verts, tris, lay, x, gin, F32h, V32h, F64h, V64h))
+        result.update(oracle_checks(args, w, verts, tris, lay, x, gin, F32h, V32h, F64h, V64h, mr_out))
 
     T.fmm_dense_destroy(dplan)
     T.fmm_tucker_destroy(h)
@@ -277,7 +353,73 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def oracle_checks(args, w, verts, tris, lay, x, gin, F32h, V32h, F64h, V64h):
+MRHS_PRECS = {"c128": 0, "c64": 1, "bf16x2": 2, "bf16x3": 3}
+
+
+def multi_rhs(args, T, torch, synth, h, lay, ranks, w):
+    """Multi-RHS pass (aggregation of x [N][R] + disaggregation of G [G][2][N_dir][R])
+    per precision: autotuned, captured in a graph, replayed.  Returns the report and the
+    sampled outputs for the oracle check."""
+    R = args.nrhs
+    N, G, nd = lay.n_basis, lay.n_groups, lay.n_dir
+    xs = synth.complex_normal(synth.rng(w.seeds.get("x", 0) + 100), (N, R))
+    gs = synth.complex_normal(synth.rng(w.seeds.get("g", 1) + 100), (G, 2, nd, R))
+    dev = {}
+    rep = {"nrhs": R, "precisions": {}}
+    outs = {"x": xs, "g": gs}
+    s = torch.cuda.Stream()
+    for name in [p for p in args.mrhs_precs.split(",") if p]:
+        prec = MRHS_PRECS[name]
+        dt = torch.complex128 if prec == 0 else torch.complex64
+        if dt not in dev:
+            dev.clear()   # one dtype's buffers at a time
+            torch.cuda.empty_cache()
+            dev[dt] = (torch.from_numpy(xs).to("cuda", dt), torch.from_numpy(gs).to("cuda", dt),
+                       torch.empty((G, 2, nd, R), dtype=dt, device="cuda"),
+                       torch.empty((N, R), dtype=dt, device="cuda"))
+        xd, gd, F, V = dev[dt]
+        es = 16 if prec == 0 else 8
+        b_stage, fac = tucker_stage_bytes(ranks, lay.offsets, w.n_theta, w.n_phi, es)
+        pass_bytes = 2 * (fac + R * (b_stage - fac))
+        pass_flops = 2 * tucker_stage_flops(ranks, lay.offsets, w.n_theta, w.n_phi, R)
+        _, nbytes = T.fmm_tucker_storage_bytes(h, prec)
+        ar = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        T.fmm_tucker_upload(h, prec, ar)
+        tuned = T.fmm_tucker_tune(h, prec, R, xd, F, gd, V)
+        with torch.cuda.stream(s):
+            T.fmm_graph_capture(h, prec, R, xd, F, gd, V, s)
+        torch.cuda.synchronize()
+        for _ in range(2):
+            T.fmm_graph_launch(h, s)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.mrhs_steps)]
+        for a, b in evs:
+            a.record(s)
+            T.fmm_graph_launch(h, s)
+            b.record(s)
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in evs]))
+        tf = pass_flops / (ms * 1e-3) / 1e12
+        gbs = pass_bytes / (ms * 1e-3) / 1e9
+        r = {"pass_ms": round(ms, 4), "ms_per_rhs": round(ms / R, 5), "pass_bytes": pass_bytes,
+             "pass_flops": pass_flops, "GBps": round(gbs, 1), "TFLOPs": round(tf, 2),
+             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "tuned": tuned}
+        if prec == 0:
+            r["fp64_frac"] = round(tf / 78.6, 4)
+        elif prec == 1:
+            r["mfma_frac_fp32"] = round(tf / 157.3, 4)
+        else:
+            issued = {2: 3, 3: 6}[prec]
+            r["mfma_issued_TFLOPs_bf16"] = round(tf * issued, 1)
+            r["mfma_frac_bf16"] = round(tf * issued / 2500.0, 4)
+        rep["precisions"][name] = r
+        log("multi-RHS %s R=%d: %.3f ms/pass, %.1f GB/s, %.1f TFLOP/s, tuned %s" % (name, R, ms, gbs, tf, tuned))
+        outs[name] = (F.cpu().numpy(), V.cpu().numpy())
+        del ar
+    return rep, outs
+
+
+def oracle_checks(args, w, verts, tris, lay, x, gin, F32h, V32h, F64h, V64h, mr_out=None):
     """End-to-end error of the GPU outputs against the oracle's dense FP64 products on
     sampled groups, and the oracle's own throughput on the same sample."""
     from oracle import geometry as geo
@@ -314,6 +456,20 @@ def oracle_checks(args, w, verts, tris, lay, x, gin, F32h, V32h, F64h, V64h):
         ref = ref_f if k.endswith("_agg") else ref_v
         out["rel_err_vs_oracle"][k] = float(pr.rel_err(np.concatenate([np.ravel(a) for a in got[k]]),
                                                         np.concatenate([np.ravel(a) for a in ref])))
+    if mr_out:
+        xs, gs = mr_out["x"], mr_out["g"]
+        rf, rv = [], []
+        for g in sample:
+            lo, hi = int(P.offsets[g]), int(P.offsets[g + 1])
+            rf.append(np.ravel(pr.dense_aggregate(blocks[g], xs[lo:hi])))
+            rv.append(np.ravel(pr.dense_disaggregate(blocks[g], gs[g])))
+        rf, rv = np.concatenate(rf), np.concatenate(rv)
+        for name in [k for k in mr_out if k not in ("x", "g")]:
+            Fm, Vm = mr_out[name]
+            gf = np.concatenate([np.ravel(Fm[g]) for g in sample])
+            gv = np.concatenate([np.ravel(Vm[int(P.offsets[g]):int(P.offsets[g + 1])]) for g in sample])
+            out["rel_err_vs_oracle"]["mrhs_%s_agg" % name] = float(pr.rel_err(gf, rf))
+            out["rel_err_vs_oracle"]["mrhs_%s_disagg" % name] = float(pr.rel_err(gv, rv))
     out["rel_err_sample_groups"] = [int(g) for g in sample]
     log("errors vs oracle: %s" % out["rel_err_vs_oracle"])
 

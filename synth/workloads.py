@@ -1,7 +1,7 @@
 """Workload parameters of the synthetic stand-ins for the paper's sphere examples.
 
 Lengths are in wavelengths (lambda = 1, wavenumber k = 2 pi).  The angular grids
-are written out as integers; ``tests/test_oracle_grid.py`` checks them against the
+are written out as integers; ``tests/test_oracle_geometry.py`` checks them against the
 sampling rule of Section II.A as the oracle implements it (n_theta = L + 1,
 n_phi = 2 L + 1, L from the box's enclosing radius and the FMM accuracy).
 
