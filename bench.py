@@ -96,11 +96,12 @@ def kernel_source_sha(name):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(kernel, source):
+def measured_traffic(kernel, source, workload_name):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary:
     FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by the ratio of known bytes to
-    the counter's reading for the calibration copy.  None when the summary is missing
-    or was taken from another version of the kernel's source file."""
+    the counter's reading for the calibration copy.  None when the summary is missing,
+    covers another workload, or was taken from another version of the kernel's source
+    file."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     rec = {}
@@ -109,7 +110,7 @@ def measured_traffic(kernel, source):
             kv = dict(t.split("=", 1) for t in ln.split()[1:])
             rec[kv["kernel"]] = kv
     r = rec.get(kernel)
-    if r is None or r.get("src_sha") != kernel_source_sha(source):
+    if r is None or r.get("src_sha") != kernel_source_sha(source) or r.get("workload") != workload_name:
         return None
     return int(float(r["hbm_bytes"]))
 
@@ -313,7 +314,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "tucker_pass_kernel<float> (+ V zeroing)", "achieved": round(gbs[dom], 1),
                      "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(gbs[dom] / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("tucker_pass_kernel<float>", "tucker.hip"),
+                     "traffic": measured_traffic("tucker_pass_kernel<float>", "tucker.hip", w.name),
                      "bytes_per_launch": per_stage_bytes[dom]},
         "copy_GBps": round(copy_gbs, 1),
         "memory_MB": {"tucker_factors_f32": round(fac32 / 2 ** 20, 1),
