@@ -213,8 +213,8 @@ def main():
         T.fmm_tucker_upload(h, prec, arenas[prec])
     dplan = T.fmm_dense_create(lay)
 
-    x = synth.complex_normal(synth.rng(w.seeds["x"]), N)
-    gin = synth.complex_normal(synth.rng(w.seeds["g"]), (G, 2, nd))
+    x = synth.complex_normal(synth.rng(w.seeds.get("x", 0)), N)
+    gin = synth.complex_normal(synth.rng(w.seeds.get("g", 1)), (G, 2, nd))
     x32 = torch.from_numpy(x).to("cuda", torch.complex64)
     g32 = torch.from_numpy(gin).to("cuda", torch.complex64)
     x64 = torch.from_numpy(x).to("cuda")
