@@ -53,6 +53,8 @@ def parse():
                    help="right-hand sides of the multi-RHS section (default: the workload's, else 64; 0: skip)")
     p.add_argument("--mrhs-precs", default="c64,bf16x2,bf16x3",
                    help="precisions of the multi-RHS section (c128, c64, bf16x2, bf16x3)")
+    p.add_argument("--no-tune", action="store_true",
+                   help="multi-RHS section: default kernel choice instead of the autotuner (profiling runs)")
     p.add_argument("--setup-chunk", type=int, default=128,
                    help="groups per far-field fill + compress chunk when the dense tensor is not kept")
     p.add_argument("--mrhs-steps", type=int, default=10, help="timed passes per multi-RHS precision")
@@ -386,7 +388,7 @@ def multi_rhs(args, T, torch, synth, h, lay, ranks, w):
         _, nbytes = T.fmm_tucker_storage_bytes(h, prec)
         ar = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         T.fmm_tucker_upload(h, prec, ar)
-        tuned = T.fmm_tucker_tune(h, prec, R, xd, F, gd, V)
+        tuned = None if args.no_tune else T.fmm_tucker_tune(h, prec, R, xd, F, gd, V)
         with torch.cuda.stream(s):
             T.fmm_graph_capture(h, prec, R, xd, F, gd, V, s)
         torch.cuda.synchronize()

@@ -104,6 +104,7 @@ void item_products(const TuckItem& it, const Layout& L, int R, int r0, int rc, c
 struct TileCost {
   CTile t;
   int64_t cost;
+  int64_t bundle;  // tiles of one product and column range: they share the B operand
 };
 
 // Work tiles of one product: 64-row blocks x groups of 64-column blocks.  A tile runs
@@ -115,18 +116,75 @@ void tiles_of(const CGemm& g, int prob, int tile_steps, std::vector<TileCost>& o
   const int nblk = (g.N + kTileN - 1) / kTileN;
   const int ks = std::max(1, (g.K + kStepK - 1) / kStepK);
   int cpt = nblk <= 4 ? nblk : std::max(1, std::min(nblk, (tile_steps + ks - 1) / ks));
-  for (int m = 0; m < mt; ++m)
-    for (int b = 0; b < nblk; b += cpt) {
-      const int nb = std::min(cpt, nblk - b);
+  for (int b = 0; b < nblk; b += cpt) {
+    const int nb = std::min(cpt, nblk - b);
+    const int64_t bundle = ((int64_t)prob << 20) | b;
+    for (int m = 0; m < mt; ++m) {
       TileCost tc;
       tc.t = CTile{prob, m * kTileM, b * kTileN, std::min(g.N, (b + nb) * kTileN)};
       tc.cost = (int64_t)nb * (ks + 2);
+      tc.bundle = bundle;
       out.push_back(tc);
     }
+  }
 }
 
-void sort_lpt(std::vector<TileCost>& v) {
-  std::stable_sort(v.begin(), v.end(), [](const TileCost& a, const TileCost& b) { return a.cost > b.cost; });
+// Launch order of a tile list.  Workgroups are dispatched to the eight XCDs of the
+// chip round-robin by index, and each XCD has its own L2.  Tiles that share a B
+// operand (a bundle) are kept on one XCD: bundles, longest first, go to the least
+// loaded of eight queues, and the list interleaves the queues so that position p
+// lands on XCD p mod 8.  Each XCD then runs its bundles in longest-first order.
+constexpr int kXcds = 8;
+
+void order_tiles(std::vector<TileCost>& v) {
+  if (v.empty()) return;
+  std::vector<size_t> idx(v.size());
+  std::iota(idx.begin(), idx.end(), 0);
+  // bundles in first-appearance order with their total cost
+  std::vector<int64_t> keys;
+  std::vector<int64_t> cost;
+  std::vector<std::vector<size_t>> members;
+  {
+    std::vector<size_t> by(idx);
+    std::stable_sort(by.begin(), by.end(), [&](size_t a, size_t b) { return v[a].bundle < v[b].bundle; });
+    for (size_t i : by) {
+      if (keys.empty() || keys.back() != v[i].bundle) {
+        keys.push_back(v[i].bundle);
+        cost.push_back(0);
+        members.emplace_back();
+      }
+      cost.back() += v[i].cost;
+      members.back().push_back(i);
+    }
+  }
+  std::vector<size_t> border(keys.size());
+  std::iota(border.begin(), border.end(), 0);
+  std::stable_sort(border.begin(), border.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+  std::vector<std::vector<size_t>> q(kXcds);
+  std::vector<int64_t> load(kXcds, 0);
+  for (size_t bi : border) {
+    const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    for (size_t i : members[bi]) q[x].push_back(i);
+    load[x] += cost[bi];
+  }
+  std::vector<TileCost> out;
+  out.reserve(v.size());
+  std::vector<size_t> head(kXcds, 0);
+  while (out.size() < v.size()) {
+    for (int x = 0; x < kXcds && out.size() < v.size(); ++x) {
+      int src = x;
+      if (head[src] == q[src].size()) {  // queue empty: take from the longest remaining one
+        size_t best = 0;
+        for (int y = 0; y < kXcds; ++y)
+          if (q[y].size() - head[y] > best) {
+            best = q[y].size() - head[y];
+            src = y;
+          }
+      }
+      out.push_back(v[q[src][head[src]++]]);
+    }
+  }
+  v.swap(out);
 }
 
 }  // namespace
@@ -182,9 +240,9 @@ void mrhs_build_host(const std::vector<TuckItem>& items, const Layout& L, int nr
       }
       std::vector<TileCost> tp(ta);
       tp.insert(tp.end(), td.begin(), td.end());
-      sort_lpt(ta);
-      sort_lpt(td);
-      sort_lpt(tp);
+      order_tiles(ta);
+      order_tiles(td);
+      order_tiles(tp);
       const std::vector<TileCost>* src[3] = {&ta, &td, &tp};
       for (int k = 0; k < 3; ++k) {
         h.lists[k][j].resize(src[k]->size());
