@@ -57,7 +57,7 @@ class fmm_layout(ctypes.Structure):
 
 class fmm_tune_result(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("tile_steps", ctypes.c_int32), ("rhs_chunk", ctypes.c_int32),
-                ("ms", ctypes.c_float)]
+                ("threads", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
 _vp = ctypes.c_void_p
@@ -293,11 +293,12 @@ def fmm_graph_launch(h, stream=None):
 
 
 def fmm_tucker_tune(h, prec, nrhs, x, F, G, V, stream=None):
-    """Returns a dict with the chosen path, tile_steps, rhs_chunk and ms per pass."""
+    """Returns a dict with the chosen path, tile_steps, rhs_chunk, threads and ms per pass."""
     r = fmm_tune_result()
     _check(_lib.fmm_tucker_tune(h, int(prec), int(nrhs), _ptr(x), _ptr(F), _ptr(G), _ptr(V), _stream(stream),
                                 ctypes.byref(r)))
-    return {"path": r.path, "tile_steps": r.tile_steps, "rhs_chunk": r.rhs_chunk, "ms": r.ms}
+    return {"path": r.path, "tile_steps": r.tile_steps, "rhs_chunk": r.rhs_chunk, "threads": r.threads,
+            "ms": r.ms}
 
 
 def fmm_tucker_destroy(h):

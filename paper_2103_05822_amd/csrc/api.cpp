@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <thread>
@@ -225,10 +226,14 @@ struct Route {
   bool mfma = false;  // matrix-core products (else the streaming kernels)
   int variant = 0;    // grouped GEMM arithmetic: 0 FP32, 1 BF16x2, 2 BF16x3
   int tile_steps = 0, rhs_chunk = 0;
+  int threads = 512;  // streaming kernels' workgroup size
 };
 
 fmm_status route_of(const PrecSlot& s, fmm_prec prec, int nrhs, Route* r) {
   *r = Route{};
+  r->threads = s.threads;
+  for (const TuneChoice& t : s.tuned)
+    if (t.nrhs == nrhs && t.path == 0 && t.threads) r->threads = t.threads;
   if (prec == FMM_C128) return FMM_OK;
   if (prec_is_split(prec)) {
     if (nrhs % 2) return fail(FMM_ERR_UNSUPPORTED, "the bf16 split precisions need an even nrhs");
@@ -263,14 +268,14 @@ fmm_status run_stage(fmm_tucker_t h, PrecSlot& s, fmm_prec prec, int nrhs, int s
   }
   if (prec == FMM_C128) {
     if ((st = lds_check(tucker_lds_bytes<double>(s.plan.mx))) != FMM_OK) return st;
-    if (stage == 0) TFMM_HIP(launch_tucker_agg<double>(s.plan, L.n_theta, L.n_phi, nrhs, x, F, hs));
-    if (stage == 1) TFMM_HIP(launch_tucker_disagg<double>(s.plan, L.n_theta, L.n_phi, nrhs, G, V, hs));
-    if (stage == 2) TFMM_HIP(launch_tucker_pass<double>(s.plan, L.n_theta, L.n_phi, nrhs, x, F, G, V, hs));
+    if (stage == 0) TFMM_HIP(launch_tucker_agg<double>(s.plan, r.threads, L.n_theta, L.n_phi, nrhs, x, F, hs));
+    if (stage == 1) TFMM_HIP(launch_tucker_disagg<double>(s.plan, r.threads, L.n_theta, L.n_phi, nrhs, G, V, hs));
+    if (stage == 2) TFMM_HIP(launch_tucker_pass<double>(s.plan, r.threads, L.n_theta, L.n_phi, nrhs, x, F, G, V, hs));
   } else {
     if ((st = lds_check(tucker_lds_bytes<float>(s.plan.mx))) != FMM_OK) return st;
-    if (stage == 0) TFMM_HIP(launch_tucker_agg<float>(s.plan, L.n_theta, L.n_phi, nrhs, x, F, hs));
-    if (stage == 1) TFMM_HIP(launch_tucker_disagg<float>(s.plan, L.n_theta, L.n_phi, nrhs, G, V, hs));
-    if (stage == 2) TFMM_HIP(launch_tucker_pass<float>(s.plan, L.n_theta, L.n_phi, nrhs, x, F, G, V, hs));
+    if (stage == 0) TFMM_HIP(launch_tucker_agg<float>(s.plan, r.threads, L.n_theta, L.n_phi, nrhs, x, F, hs));
+    if (stage == 1) TFMM_HIP(launch_tucker_disagg<float>(s.plan, r.threads, L.n_theta, L.n_phi, nrhs, G, V, hs));
+    if (stage == 2) TFMM_HIP(launch_tucker_pass<float>(s.plan, r.threads, L.n_theta, L.n_phi, nrhs, x, F, G, V, hs));
   }
   return FMM_OK;
 }
@@ -450,6 +455,19 @@ extern "C" fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* are
   mrhs_release(sl);
   sl.tuned.clear();
   sl.items = P.items;
+  {
+    // workgroup size of the streaming kernels from the mean streamed elements per item:
+    // small items leave most of a large workgroup idle
+    double c = 0.0;
+    for (const TuckItem& it : P.items) c += item_cost(it);
+    c /= std::max<size_t>(1, P.items.size());
+    // (measured on MI355X: mean 12k and 50k elements run best at 128, 258k at 256)
+    sl.threads = c >= 1.5e6 ? 512 : (c >= 1e5 ? 256 : 128);
+    if (const char* env = std::getenv("TUCKFMM_STREAM_THREADS")) {
+      const int v = std::atoi(env);
+      if (v == 128 || v == 256 || v == 512) sl.threads = v;
+    }
+  }
   sl.ready = true;
   sl.arena = static_cast<char*>(arena);
   sl.bytes = bytes;
@@ -552,13 +570,14 @@ extern "C" fmm_status fmm_tucker_tune(fmm_tucker_t h, fmm_prec prec, int32_t nrh
   // candidates: the streaming kernels (FP64, FP32) and the matrix-core products with
   // several tile sizes and right-hand-side chunks (even nrhs)
   std::vector<TuneChoice> cand;
-  if (!prec_is_split(prec)) cand.push_back(TuneChoice{nrhs, 0, 0, 0});
+  if (!prec_is_split(prec))
+    for (int nt : {128, 256, 512}) cand.push_back(TuneChoice{nrhs, 0, 0, 0, nt});
   if (prec != FMM_C128 && nrhs % 2 == 0) {
     std::vector<int> chunks{std::min<int>(nrhs, kMrhsDefaultChunk)};
     if (nrhs > 2 * kMrhsDefaultChunk) chunks.push_back(2 * kMrhsDefaultChunk);
     if (nrhs >= kMrhsDefaultChunk) chunks.push_back(kMrhsDefaultChunk / 2);
     for (int ts : {8, 16, 32})
-      for (int rc : chunks) cand.push_back(TuneChoice{nrhs, 1, ts, rc});
+      for (int rc : chunks) cand.push_back(TuneChoice{nrhs, 1, ts, rc, 0});
   }
   if (cand.empty()) return fail(FMM_ERR_UNSUPPORTED, "no kernels for precision %d with nrhs %d", (int)prec, nrhs);
   // keep only the tables that existed before and the winner's
@@ -617,6 +636,7 @@ extern "C" fmm_status fmm_tucker_tune(fmm_tucker_t h, fmm_prec prec, int32_t nrh
     out->path = win.path;
     out->tile_steps = win.tile_steps;
     out->rhs_chunk = win.path == 1 ? std::min(win.rhs_chunk, nrhs) : 0;
+    out->threads = win.path == 0 ? win.threads : 0;
     out->ms = best;
   }
   return FMM_OK;

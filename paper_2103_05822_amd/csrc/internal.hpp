@@ -72,9 +72,10 @@ struct MrhsPlan {
   std::vector<MrhsChunk> chunks;
 };
 
-// Tuned choice for one nrhs: path 0 = streaming kernels, 1 = matrix-core products.
+// Tuned choice for one nrhs: path 0 = streaming kernels (workgroup size `threads`),
+// 1 = matrix-core products.
 struct TuneChoice {
-  int nrhs = 0, path = 0, tile_steps = 0, rhs_chunk = 0;
+  int nrhs = 0, path = 0, tile_steps = 0, rhs_chunk = 0, threads = 0;
 };
 
 struct PrecSlot {
@@ -84,6 +85,7 @@ struct PrecSlot {
   int device = -1;
   TuckPlan plan;          // device pointers into the arena
   std::vector<TuckItem> items;      // host copy of the item table
+  int threads = 512;                // default workgroup size of the streaming kernels
   std::list<MrhsPlan> mrhs;         // built on first use per (nrhs, knobs); stable addresses
   std::vector<TuneChoice> tuned;
 };

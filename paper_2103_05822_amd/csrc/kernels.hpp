@@ -6,16 +6,17 @@
 
 namespace tuckfmm {
 
-// Tucker aggregation / disaggregation / whole pass over an uploaded plan.
+// Tucker aggregation / disaggregation / whole pass over an uploaded plan, one
+// workgroup of `threads` (128, 256 or 512) per item and right-hand side.
 template <typename T>
-hipError_t launch_tucker_agg(const TuckPlan& pl, int n_theta, int n_phi, int nrhs, const void* x, void* F,
-                             hipStream_t s);
+hipError_t launch_tucker_agg(const TuckPlan& pl, int threads, int n_theta, int n_phi, int nrhs, const void* x,
+                             void* F, hipStream_t s);
 template <typename T>
-hipError_t launch_tucker_disagg(const TuckPlan& pl, int n_theta, int n_phi, int nrhs, const void* G, void* V,
-                                hipStream_t s);
+hipError_t launch_tucker_disagg(const TuckPlan& pl, int threads, int n_theta, int n_phi, int nrhs, const void* G,
+                                void* V, hipStream_t s);
 template <typename T>
-hipError_t launch_tucker_pass(const TuckPlan& pl, int n_theta, int n_phi, int nrhs, const void* x, void* F,
-                              const void* G, void* V, hipStream_t s);
+hipError_t launch_tucker_pass(const TuckPlan& pl, int threads, int n_theta, int n_phi, int nrhs, const void* x,
+                              void* F, const void* G, void* V, hipStream_t s);
 // Largest dynamic LDS request of the Tucker kernels.
 template <typename T>
 size_t tucker_lds_bytes(const TuckMax& mx);

@@ -34,8 +34,8 @@ namespace tuckfmm {
 
 namespace {
 
-constexpr int kThreads = 512;
-constexpr int kWaves = kThreads / 64;
+// Workgroup size NT (128, 256 or 512 threads, NT / 64 wavefronts) is a template
+// parameter of every phase: one workgroup per item.
 constexpr int kColPacks = 2;  // column packs per thread per chunk in the axpy stages
 
 // LDS regions (complex elements).
@@ -123,9 +123,9 @@ __device__ __forceinline__ void wave_rowdots(const typename Tr<T>::c* rows, int 
   }
 }
 
-// acc[j] (column packs base + tid + kThreads j) += sum_b rows[b][.] * coef[b];
+// acc[j] (column packs base + tid + NT j) += sum_b rows[b][.] * coef[b];
 // four rows per iteration.
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void block_colaxpy(const typename Tr<T>::c* rows, int ld, int nrows,
                                               const typename Tr<T>::c* coef, int npk, int base, int tid,
                                               typename Tr<T>::pack (&acc)[kColPacks]) {
@@ -134,7 +134,7 @@ __device__ __forceinline__ void block_colaxpy(const typename Tr<T>::c* rows, int
   const int p0 = base + tid;
   bool in[kColPacks];
 #pragma unroll
-  for (int j = 0; j < kColPacks; ++j) in[j] = p0 + kThreads * j < npk;
+  for (int j = 0; j < kColPacks; ++j) in[j] = p0 + NT * j < npk;
   int b = 0;
   for (; b + 3 < nrows; b += 4) {
     P u[4][kColPacks];
@@ -142,7 +142,7 @@ __device__ __forceinline__ void block_colaxpy(const typename Tr<T>::c* rows, int
     for (int i = 0; i < 4; ++i) {
       const P* r = reinterpret_cast<const P*>(rows + (int64_t)(b + i) * ld);
 #pragma unroll
-      for (int j = 0; j < kColPacks; ++j) u[i][j] = in[j] ? r[p0 + kThreads * j] : pzero<P>();
+      for (int j = 0; j < kColPacks; ++j) u[i][j] = in[j] ? r[p0 + NT * j] : pzero<P>();
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -156,7 +156,7 @@ __device__ __forceinline__ void block_colaxpy(const typename Tr<T>::c* rows, int
     const C c = coef[b];
 #pragma unroll
     for (int j = 0; j < kColPacks; ++j)
-      if (in[j]) paxpy(acc[j], r[p0 + kThreads * j], c);
+      if (in[j]) paxpy(acc[j], r[p0 + NT * j], c);
   }
 }
 
@@ -164,10 +164,10 @@ __device__ __forceinline__ void block_colaxpy(const typename Tr<T>::c* rows, int
 // computed by the whole workgroup in tiles of four rows per thread, n across
 // threads, so that a(m, k) is a broadcast load shared by the four accumulators and
 // b(k, n) a coalesced load.
-template <typename C, class FA, class FB, class FO>
+template <typename C, int NT, class FA, class FB, class FO>
 __device__ __forceinline__ void tile_product(int M, int N, int K, FA a, FB b, FO out, int tid) {
   const int tasks = (M + 3) / 4 * N;
-  for (int task = tid; task < tasks; task += kThreads) {
+  for (int task = tid; task < tasks; task += NT) {
     const int m0 = task / N * 4, n = task - task / N * N;
     C acc[4];
 #pragma unroll
@@ -216,7 +216,7 @@ __device__ __forceinline__ void atomic_add_c(double2* p, double2 v) {
 
 // Streaming phase: y = U^beta^T x (row-dots), then t = core^T y (column axpy) written
 // as packs to `t_out` in LDS.  t[q], q = theta' r_phi + phi'.
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void agg_stream(const typename Tr<T>::c* __restrict__ fac, const TuckItem& it,
                                            const Lds<T>& L, unsigned char* smem, int nrhs, int r,
                                            const typename Tr<T>::c* __restrict__ x, typename Tr<T>::c* t_out) {
@@ -230,24 +230,24 @@ __device__ __forceinline__ void agg_stream(const typename Tr<T>::c* __restrict__
   const int nbp = round_up(nb, E);
 
   // x of the group into LDS (zero padded to whole packs)
-  for (int n = tid; n < nbp; n += kThreads) xs[n] = n < nb ? x[(it.row0 + n) * nrhs + r] : czero<C>();
+  for (int n = tid; n < nbp; n += NT) xs[n] = n < nb ? x[(it.row0 + n) * nrhs + r] : czero<C>();
   __syncthreads();
 
   // y = U^beta^T x
-  wave_rowdots<T>(fac + it.off_ubt, it.ld_ub, wave, rb, kWaves, reinterpret_cast<const P*>(xs), nbp / E, ys,
+  wave_rowdots<T>(fac + it.off_ubt, it.ld_ub, wave, rb, (NT / 64), reinterpret_cast<const P*>(xs), nbp / E, ys,
                   lane);
   __syncthreads();
 
   // t = core^T y; t_out may alias x, which is no longer read
   const int qpk = round_up(Q, E) / E;
-  for (int base = 0; base < qpk; base += kThreads * kColPacks) {
+  for (int base = 0; base < qpk; base += NT * kColPacks) {
     P acc[kColPacks];
 #pragma unroll
     for (int j = 0; j < kColPacks; ++j) acc[j] = pzero<P>();
-    block_colaxpy<T>(fac + it.off_core, it.ld_c, rb, ys, qpk, base, tid, acc);
+    block_colaxpy<T, NT>(fac + it.off_core, it.ld_c, rb, ys, qpk, base, tid, acc);
 #pragma unroll
     for (int j = 0; j < kColPacks; ++j) {
-      const int p = base + tid + kThreads * j;
+      const int p = base + tid + NT * j;
       if (p < qpk) reinterpret_cast<P*>(t_out)[p] = acc[j];
     }
   }
@@ -255,7 +255,7 @@ __device__ __forceinline__ void agg_stream(const typename Tr<T>::c* __restrict__
 
 // Angular phase: F = U^theta t U^phi^T from t in LDS (`ts`); the intermediate uses
 // LDS region r2.
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void agg_angular(const typename Tr<T>::c* __restrict__ fac, const TuckItem& it,
                                             const Lds<T>& L, unsigned char* smem, const typename Tr<T>::c* ts,
                                             int n_theta, int n_phi, int nrhs, int r,
@@ -270,23 +270,23 @@ __device__ __forceinline__ void agg_angular(const typename Tr<T>::c* __restrict_
   C* Fo = F + ((int64_t)(it.group * 2 + it.alpha) * ndir) * nrhs + r;
   if (it.theta_first) {
     // t3[i][c] = sum_a U^theta[i][a] t[a][c]           (n_theta x r_phi)
-    tile_product<C>(
+    tile_product<C, NT>(
         n_theta, rp, rt, [&](int i, int a) { return ut[i * rt + a]; }, [&](int a, int c) { return ts[a * rp + c]; },
         [&](int i, int c, C v) { t3[i * rp + c] = v; }, tid);
     __syncthreads();
     // F[i][j] = sum_c t3[i][c] U^phi[j][c]
-    tile_product<C>(
+    tile_product<C, NT>(
         n_theta, n_phi, rp, [&](int i, int c) { return t3[i * rp + c]; },
         [&](int c, int j) { return upt[c * n_phi + j]; },
         [&](int i, int j, C v) { Fo[(int64_t)(i * n_phi + j) * nrhs] = v; }, tid);
   } else {
     // t3[a][j] = sum_c t[a][c] U^phi[j][c]             (r_theta x n_phi)
-    tile_product<C>(
+    tile_product<C, NT>(
         rt, n_phi, rp, [&](int a, int c) { return ts[a * rp + c]; }, [&](int c, int j) { return upt[c * n_phi + j]; },
         [&](int a, int j, C v) { t3[a * n_phi + j] = v; }, tid);
     __syncthreads();
     // F[i][j] = sum_a U^theta[i][a] t3[a][j]
-    tile_product<C>(
+    tile_product<C, NT>(
         n_theta, n_phi, rt, [&](int i, int a) { return ut[i * rt + a]; },
         [&](int a, int j) { return t3[a * n_phi + j]; },
         [&](int i, int j, C v) { Fo[(int64_t)(i * n_phi + j) * nrhs] = v; }, tid);
@@ -297,7 +297,7 @@ __device__ __forceinline__ void agg_angular(const typename Tr<T>::c* __restrict_
 
 // Angular phase: S = U^theta^T conj(G) U^phi, written with its pack padding to
 // `S2` in LDS.  With zero_v the item also clears its rows of V.
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void dis_angular(const typename Tr<T>::c* __restrict__ fac, const TuckItem& it,
                                             const Lds<T>& L, unsigned char* smem, int n_theta, int n_phi,
                                             int nrhs, int r, const typename Tr<T>::c* __restrict__ Gin,
@@ -312,36 +312,36 @@ __device__ __forceinline__ void dis_angular(const typename Tr<T>::c* __restrict_
   const C* up = fac + it.off_up;  // [n_phi][rp]
   const C* Gi = Gin + ((int64_t)(it.group * 2 + it.alpha) * ndir) * nrhs + r;
   if (zero_v)
-    for (int n = tid; n < it.nb; n += kThreads) V[(it.row0 + n) * nrhs + r] = czero<C>();
+    for (int n = tid; n < it.nb; n += NT) V[(it.row0 + n) * nrhs + r] = czero<C>();
   // the angular order mirrors the aggregation choice
   if (!it.theta_first) {
     // s1[a][j] = sum_i U^theta[i][a] conj(G[i][j])     (r_theta x n_phi)
-    tile_product<C>(
+    tile_product<C, NT>(
         rt, n_phi, n_theta, [&](int a, int i) { return ut[i * rt + a]; },
         [&](int i, int j) { return conjc(Gi[(int64_t)(i * n_phi + j) * nrhs]); },
         [&](int a, int j, C v) { s1[a * n_phi + j] = v; }, tid);
     __syncthreads();
     // S[a][c] = sum_j s1[a][j] U^phi[j][c]
-    tile_product<C>(
+    tile_product<C, NT>(
         rt, rp, n_phi, [&](int a, int j) { return s1[a * n_phi + j]; }, [&](int j, int c) { return up[j * rp + c]; },
         [&](int a, int c, C v) { S2[a * rp + c] = v; }, tid);
   } else {
     // s1[i][c] = sum_j conj(G[i][j]) U^phi[j][c]       (n_theta x r_phi)
-    tile_product<C>(
+    tile_product<C, NT>(
         n_theta, rp, n_phi, [&](int i, int j) { return conjc(Gi[(int64_t)(i * n_phi + j) * nrhs]); },
         [&](int j, int c) { return up[j * rp + c]; }, [&](int i, int c, C v) { s1[i * rp + c] = v; }, tid);
     __syncthreads();
     // S[a][c] = sum_i U^theta[i][a] s1[i][c]
-    tile_product<C>(
+    tile_product<C, NT>(
         rt, rp, n_theta, [&](int a, int i) { return ut[i * rt + a]; }, [&](int i, int c) { return s1[i * rp + c]; },
         [&](int a, int c, C v) { S2[a * rp + c] = v; }, tid);
   }
-  for (int o = Q + tid; o < round_up(Q, E); o += kThreads) S2[o] = czero<C>();  // pack padding
+  for (int o = Q + tid; o < round_up(Q, E); o += NT) S2[o] = czero<C>();  // pack padding
 }
 
 // Streaming phase: s = core S (row-dots) with S in LDS region s2, then
 // V[n] += conj(sum_b U^beta[n][b] s[b]) (column axpy, atomic adds).
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void dis_stream(const typename Tr<T>::c* __restrict__ fac, const TuckItem& it,
                                            const Lds<T>& L, unsigned char* smem, int nrhs, int r,
                                            typename Tr<T>::c* __restrict__ V) {
@@ -353,21 +353,21 @@ __device__ __forceinline__ void dis_stream(const typename Tr<T>::c* __restrict__
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rb = it.rb, Q = it.rt * it.rp;
   // s[b] = sum_q core[b][q] S[q]
-  wave_rowdots<T>(fac + it.off_core, it.ld_c, wave, rb, kWaves, reinterpret_cast<const P*>(S2),
+  wave_rowdots<T>(fac + it.off_core, it.ld_c, wave, rb, (NT / 64), reinterpret_cast<const P*>(S2),
                   round_up(Q, E) / E, s3, lane);
   __syncthreads();
   // V[n] += conj(sum_b U^beta[n][b] s[b])
   const int nb = it.nb;
   const int npk = round_up(nb, E) / E;
   C* Vo = V + it.row0 * nrhs + r;
-  for (int base = 0; base < npk; base += kThreads * kColPacks) {
+  for (int base = 0; base < npk; base += NT * kColPacks) {
     P acc[kColPacks];
 #pragma unroll
     for (int j = 0; j < kColPacks; ++j) acc[j] = pzero<P>();
-    block_colaxpy<T>(fac + it.off_ubt, it.ld_ub, rb, s3, npk, base, tid, acc);
+    block_colaxpy<T, NT>(fac + it.off_ubt, it.ld_ub, rb, s3, npk, base, tid, acc);
 #pragma unroll
     for (int j = 0; j < kColPacks; ++j) {
-      const int p = base + tid + kThreads * j;
+      const int p = base + tid + NT * j;
       if (p < npk) {
         const C* vals = reinterpret_cast<const C*>(&acc[j]);
 #pragma unroll
@@ -382,8 +382,8 @@ __device__ __forceinline__ void dis_stream(const typename Tr<T>::c* __restrict__
 
 // ---------------------------------------------------------------------- kernels
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void tucker_agg_kernel(const typename Tr<T>::c* __restrict__ fac,
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void tucker_agg_kernel(const typename Tr<T>::c* __restrict__ fac,
                                                               const TuckItem* __restrict__ items,
                                                               const int32_t* __restrict__ order, TuckMax mx,
                                                               int n_theta, int n_phi, int nrhs,
@@ -394,13 +394,13 @@ __global__ __launch_bounds__(kThreads) void tucker_agg_kernel(const typename Tr<
   const TuckItem it = items[order[blockIdx.x]];
   const Lds<T> L(mx);
   C* ts = reinterpret_cast<C*>(smem);  // t over x
-  agg_stream<T>(fac, it, L, smem, nrhs, blockIdx.y, x, ts);
+  agg_stream<T, NT>(fac, it, L, smem, nrhs, blockIdx.y, x, ts);
   __syncthreads();
-  agg_angular<T>(fac, it, L, smem, ts, n_theta, n_phi, nrhs, blockIdx.y, F);
+  agg_angular<T, NT>(fac, it, L, smem, ts, n_theta, n_phi, nrhs, blockIdx.y, F);
 }
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void tucker_dis_kernel(const typename Tr<T>::c* __restrict__ fac,
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void tucker_dis_kernel(const typename Tr<T>::c* __restrict__ fac,
                                                               const TuckItem* __restrict__ items,
                                                               const int32_t* __restrict__ order, TuckMax mx,
                                                               int n_theta, int n_phi, int nrhs,
@@ -410,17 +410,17 @@ __global__ __launch_bounds__(kThreads) void tucker_dis_kernel(const typename Tr<
   extern __shared__ __align__(16) unsigned char smem[];
   const TuckItem it = items[order[blockIdx.x]];
   const Lds<T> L(mx);
-  dis_angular<T>(fac, it, L, smem, n_theta, n_phi, nrhs, blockIdx.y, G, reinterpret_cast<C*>(smem) + L.s1, false, V);
+  dis_angular<T, NT>(fac, it, L, smem, n_theta, n_phi, nrhs, blockIdx.y, G, reinterpret_cast<C*>(smem) + L.s1, false, V);
   __syncthreads();
-  dis_stream<T>(fac, it, L, smem, nrhs, blockIdx.y, V);
+  dis_stream<T, NT>(fac, it, L, smem, nrhs, blockIdx.y, V);
 }
 
 // One launch for a whole aggregation + disaggregation pass: work-list entry e is
 // aggregation item e if e >= 0 and disaggregation item ~e otherwise.  Both stages'
 // items interleave in one longest-first list, so small items of either stage fill
 // the end of the launch.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void tucker_pass_kernel(const typename Tr<T>::c* __restrict__ fac,
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void tucker_pass_kernel(const typename Tr<T>::c* __restrict__ fac,
                                                                const TuckItem* __restrict__ items,
                                                                const int32_t* __restrict__ list, TuckMax mx,
                                                                int n_theta, int n_phi, int nrhs,
@@ -436,14 +436,14 @@ __global__ __launch_bounds__(kThreads) void tucker_pass_kernel(const typename Tr
   if (e >= 0) {
     const TuckItem it = items[e];
     C* ts = reinterpret_cast<C*>(smem);  // t over x
-    agg_stream<T>(fac, it, L, smem, nrhs, r, x, ts);
+    agg_stream<T, NT>(fac, it, L, smem, nrhs, r, x, ts);
     __syncthreads();
-    agg_angular<T>(fac, it, L, smem, ts, n_theta, n_phi, nrhs, r, F);
+    agg_angular<T, NT>(fac, it, L, smem, ts, n_theta, n_phi, nrhs, r, F);
   } else {
     const TuckItem it = items[~e];
-    dis_angular<T>(fac, it, L, smem, n_theta, n_phi, nrhs, r, G, reinterpret_cast<C*>(smem) + L.s1, false, V);
+    dis_angular<T, NT>(fac, it, L, smem, n_theta, n_phi, nrhs, r, G, reinterpret_cast<C*>(smem) + L.s1, false, V);
     __syncthreads();
-    dis_stream<T>(fac, it, L, smem, nrhs, r, V);
+    dis_stream<T, NT>(fac, it, L, smem, nrhs, r, V);
   }
 }
 
@@ -467,50 +467,81 @@ size_t tucker_lds_bytes(const TuckMax& mx) {
   return Lds<T>(mx).bytes();
 }
 
+// Workgroup sizes a launch may take.
+#define TFMM_NT_SWITCH(threads, ...) \
+  switch (threads) {                  \
+    case 128: {                       \
+      constexpr int NT = 128;         \
+      __VA_ARGS__;                    \
+      break;                          \
+    }                                 \
+    case 256: {                       \
+      constexpr int NT = 256;         \
+      __VA_ARGS__;                    \
+      break;                          \
+    }                                 \
+    case 512: {                       \
+      constexpr int NT = 512;         \
+      __VA_ARGS__;                    \
+      break;                          \
+    }                                 \
+    default:                          \
+      return hipErrorInvalidValue;    \
+  }
+
 template <typename T>
-hipError_t launch_tucker_agg(const TuckPlan& pl, int n_theta, int n_phi, int nrhs, const void* x, void* F,
-                             hipStream_t s) {
+hipError_t launch_tucker_agg(const TuckPlan& pl, int threads, int n_theta, int n_phi, int nrhs, const void* x,
+                             void* F, hipStream_t s) {
   using C = typename Tr<T>::c;
   if (pl.n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(tucker_agg_kernel<T>, dim3(pl.n_items, nrhs), dim3(kThreads), Lds<T>(pl.mx).agg_bytes(), s,
-                     static_cast<const C*>(pl.factors), pl.items, pl.order, pl.mx, n_theta, n_phi, nrhs,
-                     static_cast<const C*>(x), static_cast<C*>(F));
+  TFMM_NT_SWITCH(threads,
+                 hipLaunchKernelGGL((tucker_agg_kernel<T, NT>), dim3(pl.n_items, nrhs), dim3(NT),
+                                    Lds<T>(pl.mx).agg_bytes(), s, static_cast<const C*>(pl.factors), pl.items,
+                                    pl.order, pl.mx, n_theta, n_phi, nrhs, static_cast<const C*>(x),
+                                    static_cast<C*>(F)))
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_tucker_disagg(const TuckPlan& pl, int n_theta, int n_phi, int nrhs, const void* G, void* V,
-                                hipStream_t s) {
+hipError_t launch_tucker_disagg(const TuckPlan& pl, int threads, int n_theta, int n_phi, int nrhs, const void* G,
+                                void* V, hipStream_t s) {
   using C = typename Tr<T>::c;
+  if (threads != 128 && threads != 256 && threads != 512) return hipErrorInvalidValue;
   hipError_t e = zero(static_cast<C*>(V), pl.n_basis * nrhs, s);
   if (e != hipSuccess || pl.n_items == 0) return e;
-  hipLaunchKernelGGL(tucker_dis_kernel<T>, dim3(pl.n_items, nrhs), dim3(kThreads), Lds<T>(pl.mx).dis_bytes(), s,
-                     static_cast<const C*>(pl.factors), pl.items, pl.order, pl.mx, n_theta, n_phi, nrhs,
-                     static_cast<const C*>(G), static_cast<C*>(V));
+  TFMM_NT_SWITCH(threads,
+                 hipLaunchKernelGGL((tucker_dis_kernel<T, NT>), dim3(pl.n_items, nrhs), dim3(NT),
+                                    Lds<T>(pl.mx).dis_bytes(), s, static_cast<const C*>(pl.factors), pl.items,
+                                    pl.order, pl.mx, n_theta, n_phi, nrhs, static_cast<const C*>(G),
+                                    static_cast<C*>(V)))
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_tucker_pass(const TuckPlan& pl, int n_theta, int n_phi, int nrhs, const void* x, void* F,
-                              const void* G, void* V, hipStream_t s) {
+hipError_t launch_tucker_pass(const TuckPlan& pl, int threads, int n_theta, int n_phi, int nrhs, const void* x,
+                              void* F, const void* G, void* V, hipStream_t s) {
   using C = typename Tr<T>::c;
+  if (threads != 128 && threads != 256 && threads != 512) return hipErrorInvalidValue;
   hipError_t e = zero(static_cast<C*>(V), pl.n_basis * nrhs, s);
   if (e != hipSuccess || pl.n_items == 0) return e;
-  hipLaunchKernelGGL(tucker_pass_kernel<T>, dim3(2 * pl.n_items, nrhs), dim3(kThreads), Lds<T>(pl.mx).bytes(), s,
-                     static_cast<const C*>(pl.factors), pl.items, pl.pass_list, pl.mx, n_theta, n_phi, nrhs,
-                     static_cast<const C*>(x), static_cast<C*>(F), static_cast<const C*>(G), static_cast<C*>(V));
+  TFMM_NT_SWITCH(threads,
+                 hipLaunchKernelGGL((tucker_pass_kernel<T, NT>), dim3(2 * pl.n_items, nrhs), dim3(NT),
+                                    Lds<T>(pl.mx).bytes(), s, static_cast<const C*>(pl.factors), pl.items,
+                                    pl.pass_list, pl.mx, n_theta, n_phi, nrhs, static_cast<const C*>(x),
+                                    static_cast<C*>(F), static_cast<const C*>(G), static_cast<C*>(V)))
   return hipGetLastError();
 }
 
 template size_t tucker_lds_bytes<float>(const TuckMax&);
 template size_t tucker_lds_bytes<double>(const TuckMax&);
-template hipError_t launch_tucker_agg<float>(const TuckPlan&, int, int, int, const void*, void*, hipStream_t);
-template hipError_t launch_tucker_agg<double>(const TuckPlan&, int, int, int, const void*, void*, hipStream_t);
-template hipError_t launch_tucker_disagg<float>(const TuckPlan&, int, int, int, const void*, void*, hipStream_t);
-template hipError_t launch_tucker_disagg<double>(const TuckPlan&, int, int, int, const void*, void*, hipStream_t);
-template hipError_t launch_tucker_pass<float>(const TuckPlan&, int, int, int, const void*, void*, const void*, void*,
-                                              hipStream_t);
-template hipError_t launch_tucker_pass<double>(const TuckPlan&, int, int, int, const void*, void*, const void*,
+template hipError_t launch_tucker_agg<float>(const TuckPlan&, int, int, int, int, const void*, void*, hipStream_t);
+template hipError_t launch_tucker_agg<double>(const TuckPlan&, int, int, int, int, const void*, void*, hipStream_t);
+template hipError_t launch_tucker_disagg<float>(const TuckPlan&, int, int, int, int, const void*, void*, hipStream_t);
+template hipError_t launch_tucker_disagg<double>(const TuckPlan&, int, int, int, int, const void*, void*,
+                                                 hipStream_t);
+template hipError_t launch_tucker_pass<float>(const TuckPlan&, int, int, int, int, const void*, void*, const void*,
+                                              void*, hipStream_t);
+template hipError_t launch_tucker_pass<double>(const TuckPlan&, int, int, int, int, const void*, void*, const void*,
                                                void*, hipStream_t);
 
 }  // namespace tuckfmm

@@ -312,3 +312,35 @@ def test_compress_end_to_end(gamma):
             # ranks agree with the oracle's HOSVD up to ties at the threshold
             c_ref, _, _ = H.hosvd(H.tensorize(blk, a), gamma)
             assert np.all(np.abs(np.array(core.shape) - np.array(c_ref.shape)) <= 1), (core.shape, c_ref.shape)
+
+
+@pytest.mark.parametrize("threads", [128, 256, 512])
+@pytest.mark.parametrize("prec", [T.FMM_C128, T.FMM_C64], ids=["c128", "c64"])
+def test_tucker_workgroup_sizes(prec, threads, monkeypatch):
+    """Every workgroup size of the streaming kernels (forced at upload) matches the
+    oracle, for separate stages and the merged pass."""
+    monkeypatch.setenv("TUCKFMM_STREAM_THREADS", str(threads))
+    lay = ragged_layout(9, 17)
+    banner("tucker workgroup size %d prec=%d" % (threads, prec))
+    tuck = random_tucker(lay, 60 + threads)
+    rng = synth.rng(11)
+    x = synth.complex_normal(rng, lay.n_basis)
+    gin = synth.complex_normal(rng, (lay.n_groups, 2, lay.n_dir))
+    f_ref, v_ref = oracle_tucker(lay, tuck, x, gin)
+    h = make_handle(lay, tuck)
+    try:
+        _, nbytes = T.fmm_tucker_storage_bytes(h, prec)
+        ar = arena(nbytes)
+        T.fmm_tucker_upload(h, prec, ar)
+        xd, gd = dev(x, CDT[prec]), dev(gin, CDT[prec])
+        F = dev(np.zeros(f_ref.shape, CDT[prec]))
+        V = dev(np.zeros(v_ref.shape, CDT[prec]))
+        T.fmm_tucker_pass(h, prec, 1, xd, F, gd, V)
+        Fp, Vp = host(F), host(V)
+        tol = TOL[prec]
+        assert l2_rel(Fp, f_ref) < tol and l2_rel(Vp, v_ref) < tol
+        T.fmm_tucker_aggregate(h, prec, 1, xd, F)
+        T.fmm_tucker_disaggregate(h, prec, 1, gd, V)
+        assert np.array_equal(host(F), Fp) and np.array_equal(host(V), Vp)
+    finally:
+        T.fmm_tucker_destroy(h)
