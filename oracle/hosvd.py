@@ -67,11 +67,47 @@ def hosvd(a, gamma):
     return core, tuple(factors), sigmas
 
 
+def truncated_svd(a, gamma):
+    """The paper's comparison method (Section I; Section II.C, the truncated SVD of
+    the aggregation matrix): only the basis mode is compressed.
+
+    The aggregation matrix of one group and polarisation, A (N_dir x n_beta), is the
+    transpose of the mode-3 unfolding of the tensor ``a``.  With U^beta the leading
+    r_beta left singular vectors of that unfolding, A ~ W U^beta^T with
+    W = A conj(U^beta) (N_dir x r_beta).  Reading (the paper gives no rule for the
+    SVD rank): the smallest r_beta whose discarded tail satisfies
+    sqrt(sum_{i >= r} s_i^2) <= gamma ||A||_F, so that ||A - W U^beta^T||_F <= gamma ||A||_F.
+
+    Returns ``W [N_dir, r_beta], U_b [n_beta, r_beta], s`` (s: all singular values).
+    """
+    amat = unfold(a, 2)                               # [n_beta, N_dir]
+    u, s, _ = np.linalg.svd(amat, full_matrices=False)
+    r = truncation_rank(s, gamma * np.linalg.norm(a))
+    ub = u[:, :r]
+    w = amat.T @ ub.conj()                            # A conj(U^beta), [N_dir, r_beta]
+    return w, ub, s
+
+
+def svd_memory(n_beta, n_dir, r_beta, elem_bytes=16):
+    """Stored bytes of the truncated-SVD method: U^beta and W."""
+    return elem_bytes * (n_beta * r_beta + n_dir * r_beta)
+
+
 def reconstruct(core, factors):
     """A_hat = C x_1 U^theta x_2 U^phi x_3 U^beta (eq. (6))."""
     out = core
     for mode in range(3):
         out = mode_product(out, factors[mode], mode)
+    return out
+
+
+def compress_all_svd(dense, offsets, gamma):
+    """Truncated SVD of every (group, polarisation): a list over groups of
+    ``[(W, U_b) for alpha in (0, 1)]``."""
+    out = []
+    for g in range(offsets.size - 1):
+        blk = dense[offsets[g]:offsets[g + 1]]
+        out.append([truncated_svd(tensorize(blk, alpha), gamma)[:2] for alpha in range(2)])
     return out
 
 

@@ -109,6 +109,16 @@ def tucker_disaggregate_one(core, factors, g):
     return out[:, 0] if vec else out
 
 
+def svd_aggregate_one(w, ub, x):
+    """Truncated-SVD aggregation: F = W (U^beta^T x)."""
+    return w @ (ub.T @ x)
+
+
+def svd_disaggregate_one(w, ub, g):
+    """Truncated-SVD disaggregation: (W U^beta^T)* g = conj(U^beta) (W^H g)."""
+    return ub.conj() @ (w.conj().T @ g)
+
+
 def tucker_aggregate(tucker_group, x):
     """Both polarisations: ``tucker_group = [(core, factors)] * 2``.  [2, N_dir(, R)]."""
     return np.stack([tucker_aggregate_one(c, f, x) for c, f in tucker_group])
@@ -123,13 +133,16 @@ def tucker_disaggregate(tucker_group, g):
 # ------------------------------------------------------- whole-problem helpers
 
 def aggregate_all(kind, data, offsets, x):
-    """Aggregation over all groups; ``kind`` is 'dense' (data = [N,2,n_t,n_p]) or
-    'tucker' (data = list of per-group Tucker pairs).  Returns [G, 2, N_dir(, R)]."""
+    """Aggregation over all groups; ``kind`` is 'dense' (data = [N,2,n_t,n_p]),
+    'tucker' (data = list of per-group Tucker pairs) or 'svd' (data = list of
+    per-group (W, U^beta) pairs).  Returns [G, 2, N_dir(, R)]."""
     out = []
     for g in range(offsets.size - 1):
         xs = x[offsets[g]:offsets[g + 1]]
         if kind == "dense":
             out.append(dense_aggregate(data[offsets[g]:offsets[g + 1]], xs))
+        elif kind == "svd":
+            out.append(np.stack([svd_aggregate_one(w, ub, xs) for w, ub in data[g]]))
         else:
             out.append(tucker_aggregate(data[g], xs))
     return np.stack(out)
@@ -142,6 +155,8 @@ def disaggregate_all(kind, data, offsets, gin):
     for g in range(offsets.size - 1):
         if kind == "dense":
             out.append(dense_disaggregate(data[offsets[g]:offsets[g + 1]], gin[g]))
+        elif kind == "svd":
+            out.append(sum(svd_disaggregate_one(w, ub, gin[g][alpha]) for alpha, (w, ub) in enumerate(data[g])))
         else:
             out.append(tucker_disaggregate(data[g], gin[g]))
     return np.concatenate(out, axis=0)

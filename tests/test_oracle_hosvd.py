@@ -117,3 +117,55 @@ def test_sphere_ranks_near_table_iv(golden_dir):
     got = core.shape
     assert abs(got[0] - rt) <= 0.2 * rt and abs(got[1] - rp) <= 0.2 * rp
     assert abs(got[2] - rb) <= 0.25 * rb, got
+
+
+# ---------------------------------------------------------------- truncated SVD
+
+def test_svd_full_rank_is_exact(small):
+    P, D = small
+    blk = D[P.offsets[2]:P.offsets[3]]
+    a = H.tensorize(blk, 1)
+    w, ub, s = H.truncated_svd(a, 0.0)
+    amat = blk[:, 1].reshape(blk.shape[0], -1).T          # [N_dir, n_beta]
+    assert ub.shape[1] == min(amat.shape)
+    assert np.linalg.norm(w @ ub.T - amat) <= 1e-12 * np.linalg.norm(amat)
+
+
+@pytest.mark.parametrize("gamma", [1e-2, 1e-4, 1e-6])
+def test_svd_is_the_best_approximation_of_its_rank(small, gamma):
+    """Eckart-Young: the error of W U^beta^T equals the discarded singular-value tail,
+    it meets the gamma bound, and one rank less would not."""
+    P, D = small
+    blk = D[P.offsets[5]:P.offsets[6]]
+    a = H.tensorize(blk, 0)
+    amat = blk[:, 0].reshape(blk.shape[0], -1).T
+    w, ub, s = H.truncated_svd(a, gamma)
+    r = ub.shape[1]
+    err = np.linalg.norm(w @ ub.T - amat)
+    tail = np.sqrt(np.sum(s[r:] ** 2))
+    assert abs(err - tail) <= 1e-10 * np.linalg.norm(amat)
+    assert err <= gamma * np.linalg.norm(amat) * (1 + 1e-12)
+    if r > 1:
+        assert np.sqrt(np.sum(s[r - 1:] ** 2)) > gamma * np.linalg.norm(amat)
+    # orthonormal basis factor
+    assert np.allclose(ub.conj().T @ ub, np.eye(r), atol=1e-12)
+
+
+def test_svd_memory_ratio_near_table_iii(golden_dir):
+    """On a typical 2-lambda group of the 30-lambda sphere the SVD method stores about
+    twice what Tucker stores at gamma = 1e-6, as in Table III.  A sanity band: the
+    paper's totals are over its own mesh."""
+    ref = json.load(open(os.path.join(golden_dir, "paper_sphere_svd_vs_tucker.json")))
+    paper_ratio = ref["svd_mb"]["1e-6"] / ref["tucker_mb"]["1e-6"]
+    w = W.SPHERE30
+    v, t = synth.icosphere(w.freq, w.radius)
+    P = geo.Problem(v, t, w.origin, w.box, w.boxes_per_axis, w.n_theta, w.n_phi)
+    nb = P.group_sizes()
+    g = int(np.argmin(np.abs(nb - 909)))
+    a = H.tensorize(ff.farfield_group(P, g), 0)
+    core, (ut, up, ubt), _ = H.hosvd(a, 1e-6)
+    wm, ubs, _ = H.truncated_svd(a, 1e-6)
+    tucker = core.size + ut.size + up.size + ubt.size
+    svd = H.svd_memory(a.shape[2], a.shape[0] * a.shape[1], ubs.shape[1], 1)
+    ratio = svd / tucker
+    assert 0.7 * paper_ratio <= ratio <= 1.4 * paper_ratio, (ratio, paper_ratio)

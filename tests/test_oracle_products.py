@@ -131,3 +131,29 @@ def test_identity_angular_factors_reduce_to_svd_method(small):
     amat = blk[:, 0].reshape(blk.shape[0], -1).T                 # [N_dir, nb]
     svd_prod = (amat @ ub.conj()) @ (ub.T @ x)
     assert pr.rel_err(pr.tucker_aggregate_one(core, fac, x), svd_prod) < 1e-13
+
+
+def test_svd_products_match_the_explicit_operator(small):
+    """SVD-method aggregation / disaggregation equal the explicit W U^beta^T and its
+    conjugate transpose, satisfy the adjoint identity, and agree with the dense
+    products within gamma."""
+    P, D = small
+    gamma = 1e-4
+    data = H.compress_all_svd(D, P.offsets, gamma)
+    rng = synth.rng(21)
+    x = synth.complex_normal(rng, P.n_basis)
+    gin = synth.complex_normal(rng, (P.n_groups, 2, P.n_dir))
+    f = pr.aggregate_all("svd", data, P.offsets, x)
+    v = pr.disaggregate_all("svd", data, P.offsets, gin)
+    for g in range(P.n_groups):
+        lo, hi = P.offsets[g], P.offsets[g + 1]
+        for alpha in range(2):
+            w, ub = data[g][alpha]
+            op = w @ ub.T
+            assert pr.rel_err(f[g, alpha], op @ x[lo:hi]) < 1e-13
+    # adjoint identity over the whole problem
+    lhs = np.vdot(gin, f)
+    rhs = np.vdot(v, x)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    assert pr.rel_err(f, pr.aggregate_all("dense", D, P.offsets, x)) < 10 * gamma
+    assert pr.rel_err(v, pr.disaggregate_all("dense", D, P.offsets, gin)) < 10 * gamma
