@@ -168,6 +168,20 @@ fmm_status fmm_tucker_create(const fmm_layout* layout, fmm_tucker_t* out);
 fmm_status fmm_farfield_compress(const fmm_layout* layout, const void* farfield, int32_t first_group,
                                  int32_t count, double gamma, void* stream, fmm_tucker_t* inout);
 
+/* Setup of the paper's comparison method, the truncated SVD (Section I; Section II.C,
+ * last paragraph): only the basis mode is compressed.  Per (group, polarisation),
+ * U^beta (n_beta x r_beta) holds the leading left singular vectors of the basis-mode
+ * unfolding, with the smallest r_beta such that sqrt(sum_{i>=r} s_i^2) <= gamma ||A||_F,
+ * and W = A conj(U^beta) (N_dir x r_beta), so that A ~ W U^beta^T.  The handle stores
+ * it as a Tucker tensor with identity angular factors (r_theta = n_theta,
+ * r_phi = n_phi, core[i_theta][i_phi][b] = W[i][b]); the compute calls then apply
+ * F = W (U^beta^T x) and V = conj(U^beta) (W^H G) with no angular products, and the
+ * storage measure counts U^beta and W only.  Arguments, streaming by group ranges and
+ * errors as fmm_farfield_compress; FP64 throughout.  fmm_tucker_set_group with exact
+ * identity angular factors gives the same representation. */
+fmm_status fmm_farfield_compress_svd(const fmm_layout* layout, const void* farfield, int32_t first_group,
+                                     int32_t count, double gamma, void* stream, fmm_tucker_t* inout);
+
 /* Set the factors of one (group, polarisation) from host complex128 arrays in the
  * paper's shapes (see the conventions above).  1 <= r_theta <= n_theta,
  * 1 <= r_phi <= n_phi, 1 <= r_beta <= n_beta.  Copies the data. */

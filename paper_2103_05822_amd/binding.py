@@ -20,7 +20,8 @@ __all__ = [
     "FMM_OK", "FMM_C128", "FMM_C64", "FMM_BF16X2", "FMM_BF16X3", "FmmError", "Layout", "exported_symbols",
     "fmm_last_error", "fmm_version", "fmm_device_count",
     "fmm_geometry_build", "fmm_geometry_info", "fmm_geometry_tables", "fmm_geometry_layout", "fmm_farfield_fill",
-    "fmm_geometry_destroy", "fmm_tucker_create", "fmm_farfield_compress", "fmm_tucker_set_group",
+    "fmm_geometry_destroy", "fmm_tucker_create", "fmm_farfield_compress", "fmm_farfield_compress_svd",
+    "fmm_tucker_set_group",
     "fmm_tucker_ranks", "fmm_tucker_export", "fmm_tucker_storage_bytes", "fmm_tucker_upload",
     "fmm_tucker_aggregate", "fmm_tucker_disaggregate", "fmm_tucker_pass", "fmm_graph_capture", "fmm_graph_launch",
     "fmm_tucker_tune", "fmm_tucker_destroy", "fmm_dense_create", "fmm_dense_aggregate", "fmm_dense_disaggregate",
@@ -79,6 +80,8 @@ _SIGS = {
     "fmm_geometry_destroy": (None, [_vp]),
     "fmm_tucker_create": (_st, [ctypes.POINTER(fmm_layout), ctypes.POINTER(_vp)]),
     "fmm_farfield_compress": (_st, [ctypes.POINTER(fmm_layout), _vp, _i32, _i32, _f64, _vp, ctypes.POINTER(_vp)]),
+    "fmm_farfield_compress_svd": (_st, [ctypes.POINTER(fmm_layout), _vp, _i32, _i32, _f64, _vp,
+                                        ctypes.POINTER(_vp)]),
     "fmm_tucker_set_group": (_st, [_vp, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp]),
     "fmm_tucker_ranks": (_st, [_vp, _vp]),
     "fmm_tucker_export": (_st, [_vp, _i32, _i32, _vp, _vp, _vp, _vp]),
@@ -233,6 +236,13 @@ def fmm_farfield_compress(layout, farfield, first_group, count, gamma, handle=No
     h = _vp(handle)
     _check(_lib.fmm_farfield_compress(ctypes.byref(layout.c), _ptr(farfield), int(first_group), int(count),
                                       float(gamma), _stream(stream), ctypes.byref(h)))
+    return h.value
+
+
+def fmm_farfield_compress_svd(layout, farfield, first_group, count, gamma, handle=None, stream=None):
+    h = _vp(handle)
+    _check(_lib.fmm_farfield_compress_svd(ctypes.byref(layout.c), _ptr(farfield), int(first_group), int(count),
+                                          float(gamma), _stream(stream), ctypes.byref(h)))
     return h.value
 
 

@@ -123,20 +123,25 @@ fmm_status plan_arena(const fmm_tucker_s* h, fmm_prec prec, ArenaPlan* P) {
       const double c_theta = (double)L.n_theta * it.rp * (it.rt + L.n_phi);
       const double c_phi = (double)it.rt * L.n_phi * (it.rp + L.n_theta);
       it.theta_first = c_theta <= c_phi ? 1 : 0;
+      it.ident = tf.ident ? 1 : 0;
       it.off_ubt = (int64_t)(block((size_t)it.rb * it.ld_ub) / es);
       it.off_core = (int64_t)(block((size_t)it.rb * it.ld_c) / es);
-      it.off_ut = (int64_t)(block((size_t)L.n_theta * it.rt) / es);
-      it.off_up = (int64_t)(block((size_t)L.n_phi * it.rp) / es);
-      it.off_upt = (int64_t)(block((size_t)L.n_phi * it.rp) / es);
+      if (!it.ident) {  // identity angular factors are not stored
+        it.off_ut = (int64_t)(block((size_t)L.n_theta * it.rt) / es);
+        it.off_up = (int64_t)(block((size_t)L.n_phi * it.rp) / es);
+        it.off_upt = (int64_t)(block((size_t)L.n_phi * it.rp) / es);
+      }
       P->items[2 * g + a] = it;
       mx.nb = std::max(mx.nb, it.nb);
       mx.rt = std::max(mx.rt, it.rt);
       mx.rp = std::max(mx.rp, it.rp);
       mx.rb = std::max(mx.rb, it.rb);
       mx.q = std::max(mx.q, it.rt * it.rp);
-      mx.t3 = std::max(mx.t3, it.theta_first ? L.n_theta * it.rp : it.rt * L.n_phi);
-      P->factor_bytes_paper += es * ((size_t)it.rt * it.rp * it.rb + (size_t)L.n_theta * it.rt +
-                                     (size_t)L.n_phi * it.rp + (size_t)it.nb * it.rb);
+      if (!it.ident) mx.t3 = std::max(mx.t3, it.theta_first ? L.n_theta * it.rp : it.rt * L.n_phi);
+      P->factor_bytes_paper +=
+          it.ident ? es * ((size_t)it.rt * it.rp * it.rb + (size_t)it.nb * it.rb)   // W and U^beta
+                   : es * ((size_t)it.rt * it.rp * it.rb + (size_t)L.n_theta * it.rt + (size_t)L.n_phi * it.rp +
+                           (size_t)it.nb * it.rb);
     }
   }
   P->mx = mx;
@@ -182,6 +187,7 @@ void pack_tensor(const Layout& L, const TensorFactors& tf, const TuckItem& it, S
     for (int c = 0; c < it.rp; ++c)
       for (int b = 0; b < it.rb; ++b)
         put<S>(core + 2 * ((size_t)b * it.ld_c + a * it.rp + c), tf.core[((size_t)a * it.rp + c) * it.rb + b]);
+  if (it.ident) return;
   S* ut = fac + 2 * it.off_ut;
   for (size_t i = 0; i < (size_t)nt * it.rt; ++i) put<S>(ut + 2 * i, tf.ut[i]);
   S* up = fac + 2 * it.off_up;
@@ -351,6 +357,14 @@ extern "C" fmm_status fmm_tucker_set_group(fmm_tucker_t h, int32_t group, int32_
     for (const cd& z : *v)
       if (!std::isfinite(z.real()) || !std::isfinite(z.imag()))
         return fail(FMM_ERR_NUMERIC, "non-finite factor entry in group %d polarisation %d", group, alpha);
+  // identity angular factors (the truncated-SVD method): no angular products
+  auto is_eye = [](const std::vector<cd>& m, int n) {
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j)
+        if (m[(size_t)i * n + j] != cd(i == j ? 1.0 : 0.0, 0.0)) return false;
+    return true;
+  };
+  tf.ident = r_theta == L.n_theta && r_phi == L.n_phi && is_eye(tf.ut, r_theta) && is_eye(tf.up, r_phi);
   h->t[2 * (size_t)group + alpha] = std::move(tf);
   drop_graph(h);
   for (auto& s : h->slot) {  // uploads are stale now

@@ -1,5 +1,6 @@
 // Setup: truncated HOSVD of the dense far-field tensors (Section II.B, eq. (6)),
-// FP64 on the device.
+// FP64 on the device; and the truncated SVD of the basis mode alone, the paper's
+// comparison method.
 //
 // For each (group, polarisation) tensor A (n_theta x n_phi x n_beta):
 //   1. the Gram matrices of the three mode unfoldings: the basis mode with rocBLAS
@@ -93,13 +94,87 @@ struct Job {
   int n_tensors;
   int nb_max;
   double gamma;
+  bool svd;  // truncated SVD of the basis mode only (the paper's comparison method)
   fmm_tucker_s* handle;
 };
 
 std::string hip_msg(const char* what, hipError_t e) { return std::string(what) + ": " + hipGetErrorString(e); }
 
+// Truncated SVD of tensor t (basis mode only): U^beta from the basis-mode Gram matrix,
+// rank rule sqrt(sum_{i>=r} s_i^2) <= gamma ||A||_F, W = A conj(U^beta) (N_dir x r_beta).
+// Stored as a Tucker item with identity angular factors and core W.
+std::string decompose_svd(const Job& J, Worker& w, int t) {
+  const Layout& L = *J.L;
+  const int g = J.first_group + t / 2, alpha = t % 2;
+  const int nt = L.n_theta, np = L.n_phi, nd = L.ndir();
+  const int nb = L.nb(g);
+  const int64_t row0 = L.offsets[g] - J.base_row;
+  using Z = rocblas_double_complex;
+  Z* slab = static_cast<Z*>(w.buf[0]);
+  Z* gb = static_cast<Z*>(w.buf[1]);
+  double* lb = static_cast<double*>(w.buf[4]);
+  Z* vb = static_cast<Z*>(w.buf[6]);
+  Z* y = static_cast<Z*>(w.buf[7]);
+  double* ework = lb + J.nb_max + nt + np;
+  rocblas_int* info = reinterpret_cast<rocblas_int*>(ework + J.nb_max + nt + np);
+
+  hipError_t he = launch_gather_slab(J.farfield, row0, nb, alpha, nt, np, slab, nullptr, w.s);
+  if (he != hipSuccess) return hip_msg("gather kernel", he);
+  const double one = 1.0, zero = 0.0;
+  rocblas_status bs = rocblas_zherk(w.h, rocblas_fill_upper, rocblas_operation_conjugate_transpose, nb, nd, &one,
+                                    slab, nd, &zero, gb, nb);
+  if (bs != rocblas_status_success) return std::string("zherk: ") + rocblas_status_to_string(bs);
+  bs = rocsolver_zheevd(w.h, rocblas_evect_original, rocblas_fill_upper, nb, gb, nb, lb, ework, info);
+  if (bs != rocblas_status_success) return std::string("zheevd: ") + rocblas_status_to_string(bs);
+  std::vector<double> lam_h(nb);
+  rocblas_int info_h = 0;
+  if ((he = hipMemcpyAsync(lam_h.data(), lb, sizeof(double) * nb, hipMemcpyDeviceToHost, w.s)) != hipSuccess ||
+      (he = hipMemcpyAsync(&info_h, info, sizeof(info_h), hipMemcpyDeviceToHost, w.s)) != hipSuccess ||
+      (he = hipStreamSynchronize(w.s)) != hipSuccess)
+    return hip_msg("eigenvalue copy", he);
+  if (info_h != 0) return "NUMERIC:eigensolver did not converge";
+  std::vector<double> eb(nb);
+  double norm2 = 0.0;
+  for (int i = 0; i < nb; ++i) {
+    eb[i] = lam_h[nb - 1 - i];
+    if (!std::isfinite(eb[i])) return "NUMERIC:non-finite far-field values";
+    norm2 += std::max(eb[i], 0.0);
+  }
+  const int rb = truncation_rank(eb, J.gamma * J.gamma * norm2);
+  if ((he = launch_select_cols_rev(gb, nb, rb, vb, w.s)) != hipSuccess) return hip_msg("column select kernel", he);
+  const Z cone = {1.0, 0.0}, czero = {0.0, 0.0};
+  // W (nd x rb) = A conj(U^beta): as in the HOSVD, the Gram eigenvectors are conj(U^beta)
+  bs = rocblas_zgemm(w.h, rocblas_operation_none, rocblas_operation_none, nd, rb, nb, &cone, slab, nd, vb, nb,
+                     &czero, y, nd);
+  if (bs != rocblas_status_success) return std::string("W projection: ") + rocblas_status_to_string(bs);
+  std::vector<cd> vb_h((size_t)nb * rb), w_h((size_t)nd * rb);
+  const size_t cz = sizeof(Z);
+  if ((he = hipMemcpyAsync(vb_h.data(), vb, cz * vb_h.size(), hipMemcpyDeviceToHost, w.s)) != hipSuccess ||
+      (he = hipMemcpyAsync(w_h.data(), y, cz * w_h.size(), hipMemcpyDeviceToHost, w.s)) != hipSuccess ||
+      (he = hipStreamSynchronize(w.s)) != hipSuccess)
+    return hip_msg("factor copy", he);
+  TensorFactors tf;
+  tf.rt = nt;
+  tf.rp = np;
+  tf.rb = rb;
+  tf.ident = true;
+  tf.ub.resize((size_t)nb * rb);
+  for (int n = 0; n < nb; ++n)
+    for (int b = 0; b < rb; ++b) tf.ub[(size_t)n * rb + b] = std::conj(vb_h[(size_t)b * nb + n]);
+  tf.ut.assign((size_t)nt * nt, cd(0.0, 0.0));
+  for (int i = 0; i < nt; ++i) tf.ut[(size_t)i * nt + i] = cd(1.0, 0.0);
+  tf.up.assign((size_t)np * np, cd(0.0, 0.0));
+  for (int j = 0; j < np; ++j) tf.up[(size_t)j * np + j] = cd(1.0, 0.0);
+  tf.core.resize((size_t)nd * rb);  // [theta][phi][rb]: direction i = theta * n_phi + phi
+  for (int i = 0; i < nd; ++i)
+    for (int b = 0; b < rb; ++b) tf.core[(size_t)i * rb + b] = w_h[(size_t)b * nd + i];
+  J.handle->t[2 * (size_t)g + alpha] = std::move(tf);
+  return std::string();
+}
+
 // Decompose tensor t of the job on worker w.  Returns an empty string on success.
 std::string decompose(const Job& J, Worker& w, int t) {
+  if (J.svd) return decompose_svd(J, w, t);
   const Layout& L = *J.L;
   const int g = J.first_group + t / 2, alpha = t % 2;
   const int nt = L.n_theta, np = L.n_phi, nd = L.ndir();
@@ -242,9 +317,9 @@ std::string setup_worker(Worker& w, const Job& J, int device) {
 
 }  // namespace
 
-extern "C" fmm_status fmm_farfield_compress(const fmm_layout* layout, const void* farfield, int32_t first_group,
-                                            int32_t count, double gamma, void* stream, fmm_tucker_t* inout) {
-  clear_error();
+namespace {
+fmm_status compress_impl(const fmm_layout* layout, const void* farfield, int32_t first_group, int32_t count,
+                         double gamma, void* stream, fmm_tucker_t* inout, bool svd) {
   if (!inout) return fail(FMM_ERR_ARG, "inout is NULL");
   if (!(gamma >= 0.0 && gamma < 1.0)) return fail(FMM_ERR_ARG, "gamma must be in [0, 1)");
   Layout L;
@@ -287,6 +362,7 @@ extern "C" fmm_status fmm_farfield_compress(const fmm_layout* layout, const void
   J.nb_max = 0;
   for (int g = first_group; g < first_group + count; ++g) J.nb_max = std::max(J.nb_max, L.nb(g));
   J.gamma = gamma;
+  J.svd = svd;
   J.handle = *inout;
 
   Shared sh;
@@ -324,4 +400,17 @@ extern "C" fmm_status fmm_farfield_compress(const fmm_layout* layout, const void
   }
   for (auto& s : (*inout)->slot) s.ready = false;
   return FMM_OK;
+}
+}  // namespace
+
+extern "C" fmm_status fmm_farfield_compress(const fmm_layout* layout, const void* farfield, int32_t first_group,
+                                            int32_t count, double gamma, void* stream, fmm_tucker_t* inout) {
+  clear_error();
+  return compress_impl(layout, farfield, first_group, count, gamma, stream, inout, false);
+}
+
+extern "C" fmm_status fmm_farfield_compress_svd(const fmm_layout* layout, const void* farfield, int32_t first_group,
+                                                int32_t count, double gamma, void* stream, fmm_tucker_t* inout) {
+  clear_error();
+  return compress_impl(layout, farfield, first_group, count, gamma, stream, inout, true);
 }

@@ -12,7 +12,9 @@ namespace tuckfmm {
 //   ut   : U^theta [n_theta][r_theta]
 //   up   : U^phi [n_phi][r_phi]
 //   upt  : U^phi transposed, [r_phi][n_phi]
-// Row padding elements are zero.
+// Row padding elements are zero.  An item with identity angular factors (the
+// truncated-SVD method: r_theta = n_theta, r_phi = n_phi, U^theta = U^phi = I) has
+// ident = 1, stores no angular factors, and its core is W (column q = direction).
 struct alignas(16) TuckItem {
   int64_t off_ubt;
   int64_t off_core;
@@ -24,7 +26,8 @@ struct alignas(16) TuckItem {
   int32_t ld_ub, ld_c;
   int32_t group, alpha;
   int32_t theta_first;  // 1: contract U^theta before U^phi in the angular stages
-  int32_t pad0, pad1, pad2;
+  int32_t ident;        // 1: identity angular factors (no angular products)
+  int32_t pad1, pad2;
 };
 static_assert(sizeof(TuckItem) == 96, "TuckItem layout");
 

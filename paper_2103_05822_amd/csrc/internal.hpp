@@ -43,6 +43,7 @@ fmm_status copy_layout(const fmm_layout* in, Layout* out);
 
 struct TensorFactors {
   int32_t rt = 0, rp = 0, rb = 0;
+  bool ident = false;    // U^theta and U^phi are identities (truncated-SVD method)
   std::vector<cd> core;  // paper shape [rt][rp][rb]
   std::vector<cd> ut;    // [n_theta][rt]
   std::vector<cd> up;    // [n_phi][rp]

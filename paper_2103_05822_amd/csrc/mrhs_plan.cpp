@@ -69,6 +69,18 @@ void item_products(const TuckItem& it, const Layout& L, int R, int r0, int rc, c
   // aggregation
   out[0] = make_gemm(it.rb, rc, it.nb, it.off_ubt, F_, it.ld_ub, 1, xo, kBaseX, R, rc, 0, sa[0], S_, rc, rc, 0, 0);
   out[1] = make_gemm(Q, rc, it.rb, it.off_core, F_, 1, it.ld_c, sa[0], S_, rc, rc, 0, sa[1], S_, rc, rc, 0, 0);
+  if (it.ident) {
+    // truncated-SVD item (identity angular factors): F = W Y directly, s3 = W^T-side
+    // product of conj(G); the angular products are empty (M = 0: no tiles)
+    out[1].c = fo;
+    out[1].cbase = kBaseF;
+    out[1].ldc_m = R;
+    out[2] = out[3] = out[4] = out[5] = CGemm{};
+    out[6] = make_gemm(it.rb, rc, Q, it.off_core, F_, it.ld_c, 1, fo, kBaseG, R, rc, 0, sd[0], S_, rc, rc, 0, kConjB);
+    out[7] = make_gemm(it.nb, rc, it.rb, it.off_ubt, F_, 1, it.ld_ub, sd[0], S_, rc, rc, 0, xo, kBaseV, R, rc, 0,
+                       kAtomicC | kConjC);
+    return;
+  }
   if (it.theta_first) {
     // T3 [c][i][r] = sum_a U^theta[i][a] T[a rp + c][r];  F[i][j][r] = sum_c U^phi[j][c] T3[c][i][r]
     out[2] = make_gemm(nt, it.rp * rc, it.rt, it.off_ut, F_, it.rt, 1, sa[1], S_, it.rp * rc, it.rp * rc, 0, sa[2],
@@ -210,7 +222,8 @@ void mrhs_build_host(const std::vector<TuckItem>& items, const Layout& L, int nr
     const TuckItem& it = items[i];
     const int64_t q = (int64_t)it.rt * it.rp;
     const int64_t t3 = it.theta_first ? (int64_t)L.n_theta * it.rp : (int64_t)it.rt * L.n_phi;
-    const int64_t sz[3] = {it.rb, q, t3};
+    // identity angular items keep only Y / s3 in scratch
+    const int64_t sz[3] = {it.rb, it.ident ? 0 : q, it.ident ? 0 : t3};
     for (int j = 0; j < 3; ++j) {
       sa[3 * i + j] = soff;
       soff += up32(sz[j] * rhs_chunk);

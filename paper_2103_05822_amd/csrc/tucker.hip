@@ -268,6 +268,10 @@ __device__ __forceinline__ void agg_angular(const typename Tr<T>::c* __restrict_
   const C* upt = fac + it.off_upt;  // [rp][n_phi]
   const int ndir = n_theta * n_phi;
   C* Fo = F + ((int64_t)(it.group * 2 + it.alpha) * ndir) * nrhs + r;
+  if (it.ident) {  // truncated-SVD item: t already holds the directions
+    for (int i = tid; i < ndir; i += NT) Fo[(int64_t)i * nrhs] = ts[i];
+    return;
+  }
   if (it.theta_first) {
     // t3[i][c] = sum_a U^theta[i][a] t[a][c]           (n_theta x r_phi)
     tile_product<C, NT>(
@@ -314,7 +318,9 @@ __device__ __forceinline__ void dis_angular(const typename Tr<T>::c* __restrict_
   if (zero_v)
     for (int n = tid; n < it.nb; n += NT) V[(it.row0 + n) * nrhs + r] = czero<C>();
   // the angular order mirrors the aggregation choice
-  if (!it.theta_first) {
+  if (it.ident) {  // truncated-SVD item: S2 is conj(G) itself
+    for (int q = tid; q < Q; q += NT) S2[q] = conjc(Gi[(int64_t)q * nrhs]);
+  } else if (!it.theta_first) {
     // s1[a][j] = sum_i U^theta[i][a] conj(G[i][j])     (r_theta x n_phi)
     tile_product<C, NT>(
         rt, n_phi, n_theta, [&](int a, int i) { return ut[i * rt + a]; },

@@ -261,3 +261,69 @@ def test_split_precisions_need_even_nrhs():
         assert e.value.status == -6
     finally:
         H.close()
+
+
+def random_svd_as_tucker(lay, seed, rank_mode="random"):
+    """Truncated-SVD factors (W, U_b) per (group, polarisation), returned as the oracle's
+    SVD pairs and as Tucker models with identity angular factors and core W reshaped
+    to [n_theta, n_phi, r_b]."""
+    rng = synth.rng(seed)
+    eye_t = np.eye(lay.n_theta, dtype=np.complex128)
+    eye_p = np.eye(lay.n_phi, dtype=np.complex128)
+    svd, tuck = [], []
+    for g in range(lay.n_groups):
+        nb = int(lay.offsets[g + 1] - lay.offsets[g])
+        sp, tp = [], []
+        for _ in range(2):
+            rb = nb if rank_mode == "full" else int(rng.integers(1, nb + 1))
+            wmat = synth.complex_normal(rng, (lay.n_dir, rb))
+            ub = synth.complex_normal(rng, (nb, rb)) / np.sqrt(nb)
+            sp.append((wmat, ub))
+            tp.append((wmat.reshape(lay.n_theta, lay.n_phi, rb), (eye_t, eye_p, ub)))
+        svd.append(sp)
+        tuck.append(tp)
+    return svd, tuck
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=PIDS)
+@pytest.mark.parametrize("rank_mode", ["random", "full"])
+@pytest.mark.parametrize("nrhs", [8, 66])
+def test_mrhs_svd_factors(prec, rank_mode, nrhs):
+    """The truncated-SVD form (identity angular factors) on the matrix cores: two
+    products per item, against the oracle's SVD aggregation and disaggregation."""
+    lay = ragged_layout()
+    banner("mrhs svd prec=%d ranks=%s nrhs=%d" % (prec, rank_mode, nrhs))
+    svd, tuck = random_svd_as_tucker(lay, 60 + nrhs, rank_mode)
+    x, gin = inputs(lay, nrhs, 8)
+    f_ref = pr.aggregate_all("svd", svd, lay.offsets, x)
+    v_ref = pr.disaggregate_all("svd", svd, lay.offsets, gin)
+    H = Handle(lay, tuck, prec)
+    try:
+        F = dev(np.zeros(f_ref.shape, C64))
+        V = dev(np.zeros(v_ref.shape, C64))
+        T.fmm_tucker_pass(H.h, prec, nrhs, dev(x, C64), F, dev(gin, C64), V)
+        check(prec, host(F), host(V), f_ref, v_ref)
+    finally:
+        H.close()
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=PIDS)
+def test_mrhs_svd_and_tucker_groups_in_one_pass(prec):
+    """SVD groups and general Tucker groups planned into the same launches."""
+    lay = ragged_layout()
+    nrhs = 8
+    banner("mrhs svd+tucker mixed prec=%d" % prec)
+    _, svd_t = random_svd_as_tucker(lay, 71)
+    gen = random_tucker(lay, 72)
+    tuck = [svd_t[g] if g % 2 == 1 else gen[g] for g in range(lay.n_groups)]
+    x, gin = inputs(lay, nrhs, 9)
+    f_ref = pr.aggregate_all("tucker", tuck, lay.offsets, x)
+    v_ref = pr.disaggregate_all("tucker", tuck, lay.offsets, gin)
+    H = Handle(lay, tuck, prec)
+    try:
+        F = dev(np.zeros(f_ref.shape, C64))
+        V = dev(np.zeros(v_ref.shape, C64))
+        T.fmm_tucker_pass(H.h, prec, nrhs, dev(x, C64), F, dev(gin, C64), V)
+        check(prec, host(F), host(V), f_ref, v_ref)
+    finally:
+        H.close()

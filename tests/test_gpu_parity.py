@@ -344,3 +344,156 @@ def test_tucker_workgroup_sizes(prec, threads, monkeypatch):
         assert np.array_equal(host(F), Fp) and np.array_equal(host(V), Vp)
     finally:
         T.fmm_tucker_destroy(h)
+
+
+# ------------------------------------------------------------ truncated SVD (comparison)
+
+def random_svd(lay, seed, rank_mode="random"):
+    """Per (group, polarisation) truncated-SVD factors ``(W [N_dir, r_b], U_b [nb, r_b])``."""
+    rng = synth.rng(seed)
+    out = []
+    for g in range(lay.n_groups):
+        nb = int(lay.offsets[g + 1] - lay.offsets[g])
+        pair = []
+        for a in range(2):
+            rb = nb if rank_mode == "full" else (1 if rank_mode == "one" else int(rng.integers(1, nb + 1)))
+            wmat = synth.complex_normal(rng, (lay.n_dir, rb))
+            ub = synth.complex_normal(rng, (nb, rb)) / np.sqrt(nb)
+            pair.append((wmat, ub))
+        out.append(pair)
+    return out
+
+
+def svd_as_tucker(lay, svd):
+    """The SVD model A = W U_b^T is the Tucker model with identity angular factors and
+    core C[i, j, b] = W[i n_phi + j, b] (the direction index runs theta-major)."""
+    eye_t = np.eye(lay.n_theta, dtype=np.complex128)
+    eye_p = np.eye(lay.n_phi, dtype=np.complex128)
+    return [[(wmat.reshape(lay.n_theta, lay.n_phi, -1), (eye_t, eye_p, ub)) for wmat, ub in pair]
+            for pair in svd]
+
+
+@pytest.mark.parametrize("prec", [T.FMM_C128, T.FMM_C64], ids=["c128", "c64"])
+@pytest.mark.parametrize("rank_mode", ["random", "full", "one"])
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_svd_factors_match_oracle(prec, rank_mode, nrhs):
+    """Identity angular factors select the SVD kernels' branch (no angular products);
+    the result is the oracle's SVD aggregation / disaggregation, and the stored bytes
+    are W and U_b only."""
+    lay = ragged_layout()
+    banner("svd ragged prec=%d ranks=%s nrhs=%d" % (prec, rank_mode, nrhs))
+    svd = random_svd(lay, 40 + nrhs, rank_mode)
+    rng = synth.rng(6)
+    shp = (nrhs,) if nrhs > 1 else ()
+    x = synth.complex_normal(rng, (lay.n_basis,) + shp)
+    gin = synth.complex_normal(rng, (lay.n_groups, 2, lay.n_dir) + shp)
+    tuck = svd_as_tucker(lay, svd)
+    h = make_handle(lay, tuck)
+    try:
+        ranks = T.fmm_tucker_ranks(h, lay.n_groups)
+        fbytes, _ = T.fmm_tucker_storage_bytes(h, prec)
+    finally:
+        T.fmm_tucker_destroy(h)
+    from oracle import hosvd as H
+    es = 16 if prec == T.FMM_C128 else 8
+    want = sum(H.svd_memory(ub.shape[0], lay.n_dir, ub.shape[1], es) for pair in svd for _, ub in pair)
+    assert fbytes == want
+    assert np.all(ranks[:, :, 0] == lay.n_theta) and np.all(ranks[:, :, 1] == lay.n_phi)
+    F, V = run_tucker(lay, tuck, prec, x, gin, nrhs)
+    f_ref = pr.aggregate_all("svd", svd, lay.offsets, x)
+    v_ref = pr.disaggregate_all("svd", svd, lay.offsets, gin)
+    tol = TOL[prec]
+    assert max_rel(F, f_ref) < tol and l2_rel(F, f_ref) < tol
+    assert max_rel(V, v_ref) < tol and l2_rel(V, v_ref) < tol
+
+
+@pytest.mark.parametrize("prec", [T.FMM_C128, T.FMM_C64], ids=["c128", "c64"])
+def test_svd_and_tucker_groups_in_one_pass(prec):
+    """Even groups in SVD form, odd groups in general Tucker form: one pass holds both
+    item kinds and each matches its own oracle product."""
+    lay = ragged_layout()
+    banner("svd+tucker mixed prec=%d" % prec)
+    svd = svd_as_tucker(lay, random_svd(lay, 51))
+    gen = random_tucker(lay, 52)
+    tuck = [svd[g] if g % 2 == 0 else gen[g] for g in range(lay.n_groups)]
+    rng = synth.rng(7)
+    x = synth.complex_normal(rng, lay.n_basis)
+    gin = synth.complex_normal(rng, (lay.n_groups, 2, lay.n_dir))
+    h = make_handle(lay, tuck)
+    try:
+        _, nbytes = T.fmm_tucker_storage_bytes(h, prec)
+        ar = arena(nbytes)
+        T.fmm_tucker_upload(h, prec, ar)
+        F = dev(np.zeros((lay.n_groups, 2, lay.n_dir), CDT[prec]))
+        V = dev(np.zeros(x.shape, CDT[prec]))
+        T.fmm_tucker_pass(h, prec, 1, dev(x, CDT[prec]), F, dev(gin, CDT[prec]), V)
+        F, V = host(F), host(V)
+    finally:
+        T.fmm_tucker_destroy(h)
+    f_ref, v_ref = oracle_tucker(lay, tuck, x, gin)
+    tol = TOL[prec]
+    assert max_rel(F, f_ref) < tol and l2_rel(F, f_ref) < tol
+    assert max_rel(V, v_ref) < tol and l2_rel(V, v_ref) < tol
+
+
+@pytest.mark.parametrize("gamma", [1e-6, 1e-4, 0.0])
+def test_compress_svd_end_to_end(gamma):
+    """GPU far-field -> GPU truncated SVD -> GPU products against the oracle's dense
+    products: the difference is bounded by gamma ||A||_F ||x|| per tensor; the basis
+    rank agrees with the oracle's truncated SVD and the product W U_b^T with the
+    oracle's (unique where the rank is)."""
+    w, v, t, P = small_problem()
+    D_ref = ff.farfield_all(P)
+    lay = T.Layout(w.n_theta, w.n_phi, P.offsets)
+    g = T.fmm_geometry_build(v, t, w.origin, w.box, w.boxes_per_axis, w.k, w.n_theta, w.n_phi)
+    h = None
+    try:
+        banner("compress svd small gamma=%g" % gamma)
+        D = dev(np.zeros(D_ref.shape, np.complex128))
+        T.fmm_farfield_fill(g, 0, P.n_groups, D)
+        h = T.fmm_farfield_compress_svd(lay, D, 0, P.n_groups, gamma)
+        ranks = T.fmm_tucker_ranks(h, P.n_groups)
+        rng = synth.rng(w.seeds["x"])
+        x = synth.complex_normal(rng, P.n_basis)
+        gin = synth.complex_normal(rng, (P.n_groups, 2, P.n_dir))
+        _, nbytes = T.fmm_tucker_storage_bytes(h, T.FMM_C128)
+        ar = arena(nbytes)
+        T.fmm_tucker_upload(h, T.FMM_C128, ar)
+        F = dev(np.zeros((P.n_groups, 2, P.n_dir), np.complex128))
+        V = dev(np.zeros(x.shape, np.complex128))
+        T.fmm_tucker_pass(h, T.FMM_C128, 1, dev(x), F, dev(gin), V)
+        F, V = host(F), host(V)
+        facs = [[T.fmm_tucker_export(h, gg, a, ranks[gg, a], w.n_theta, w.n_phi,
+                                     int(P.offsets[gg + 1] - P.offsets[gg])) for a in range(2)]
+                for gg in range(P.n_groups)]
+    finally:
+        if h:
+            T.fmm_tucker_destroy(h)
+        T.fmm_geometry_destroy(g)
+    from oracle import hosvd as H
+    assert np.all(ranks[:, :, 0] == w.n_theta) and np.all(ranks[:, :, 1] == w.n_phi)
+    v_dense = pr.disaggregate_all("dense", D_ref, P.offsets, gin)
+    for gg in range(P.n_groups):
+        lo, hi = P.offsets[gg], P.offsets[gg + 1]
+        blk = D_ref[lo:hi]
+        xs = x[lo:hi]
+        f_dense = pr.dense_aggregate(blk, xs)
+        vbound = 0.0
+        for a in range(2):
+            core, ut, up, ub = facs[gg][a]
+            assert np.array_equal(ut, np.eye(w.n_theta)) and np.array_equal(up, np.eye(w.n_phi))
+            assert np.allclose(ub.conj().T @ ub, np.eye(ub.shape[1]), atol=1e-12)
+            anorm = np.linalg.norm(blk[:, a])
+            bound = gamma * anorm * np.linalg.norm(xs)
+            err = np.linalg.norm(F[gg, a] - f_dense[a])
+            assert err <= bound * (1 + 1e-6) + 1e-12 * np.linalg.norm(f_dense[a]), (gg, a, err, bound)
+            vbound += gamma * anorm * np.linalg.norm(gin[gg, a])
+            w_ref, ub_ref, s = H.truncated_svd(H.tensorize(blk, a), gamma)
+            rb = ub.shape[1]
+            assert abs(rb - ub_ref.shape[1]) <= 1, (rb, ub_ref.shape[1])
+            if rb == ub_ref.shape[1] and (rb == s.size or s[rb - 1] - s[rb] > 1e-6 * s[0]):
+                wmat = core.reshape(P.n_dir, rb)
+                got, ref = wmat @ ub.T, w_ref @ ub_ref.T
+                assert np.linalg.norm(got - ref) <= 1e-9 * anorm, (gg, a)
+        err = np.linalg.norm(V[lo:hi] - v_dense[lo:hi])
+        assert err <= vbound * (1 + 1e-6) + 1e-12 * np.linalg.norm(v_dense[lo:hi]), (gg, err, vbound)
