@@ -58,6 +58,7 @@ def parse():
     p.add_argument("--setup-chunk", type=int, default=128,
                    help="groups per far-field fill + compress chunk when the dense tensor is not kept")
     p.add_argument("--mrhs-steps", type=int, default=10, help="timed passes per multi-RHS precision")
+    p.add_argument("--no-svd", action="store_true", help="skip the truncated-SVD comparison")
     p.add_argument("--save-factors", default=None, help="write the compressed factors to this .npz")
     p.add_argument("--load-factors", default=None, help="read the factors from this .npz instead of compressing")
     return p.parse_args()
@@ -115,6 +116,16 @@ def measured_traffic(kernel, source, workload_name):
     if r is None or r.get("src_sha") != kernel_source_sha(source) or r.get("workload") != workload_name:
         return None
     return int(float(r["hbm_bytes"]))
+
+
+def svd_stage_bytes(ranks, offsets, n_theta, n_phi, es):
+    """Algorithmic bytes of one truncated-SVD stage: W [N_dir, r_b] and U_b [n_beta, r_b]
+    of every tensor read once, plus the group vectors and patterns."""
+    nb = np.diff(offsets)
+    rb = ranks[..., 2].astype(np.int64)
+    fac = (nb[:, None] * rb + n_theta * n_phi * rb).sum()
+    io = int(offsets[-1]) + 2 * (offsets.size - 1) * n_theta * n_phi
+    return int(es * (fac + io)), int(es * fac)
 
 
 def dense_stage_bytes(offsets, n_theta, n_phi, es):
@@ -335,6 +346,12 @@ def main():
                                       "disagg": round(ms["dense_disagg_f64"] / ms["tucker_disagg_f32"], 2),
                                       "pass": round(dense_ms / tucker_ms, 2)}
 
+    # --------------------------------------------- truncated-SVD comparison (Table III)
+    svd_out = None
+    if not args.no_dense and not args.no_svd:
+        result["svd_comparison"], svd_out = svd_comparison(args, T, torch, lay, dense, w, x32, g32,
+                                                           tucker_ms, fac32)
+
     # ------------------------------------------------------------ multi-RHS section
     mr_out = {}
     if args.nrhs > 0:
@@ -348,7 +365,8 @@ def main():
         F64h = V64h = None
         if not args.no_dense:
             F64h, V64h = F64.cpu().numpy(), V64.cpu().numpy()
-        result.update(oracle_checks(args, w, verts, tris, lay, x, gin, F32h, V32h, F64h, V64h, mr_out))
+        result.update(oracle_checks(args, w, verts, tris, lay, x, gin, F32h, V32h, F64h, V64h, mr_out,
+                                    svd_out))
 
     T.fmm_dense_destroy(dplan)
     T.fmm_tucker_destroy(h)
@@ -357,6 +375,50 @@ def main():
 
 
 MRHS_PRECS = {"c128": 0, "c64": 1, "bf16x2": 2, "bf16x3": 3}
+
+
+def svd_comparison(args, T, torch, lay, dense, w, x32, g32, tucker_ms, tucker_fac_bytes):
+    """The comparison method: truncated SVD of every aggregation matrix at the same
+    gamma (basis mode only), FP32 storage, the same single-RHS pass.  Reports its
+    stored bytes and pass time beside the Tucker model's (Table III compares the two
+    by memory).  Returns the report and the outputs for the oracle check."""
+    G, nd = lay.n_groups, lay.n_dir
+    t0 = time.time()
+    hs = T.fmm_farfield_compress_svd(lay, dense, 0, G, w.gamma)
+    t_c = time.time() - t0
+    try:
+        rs = T.fmm_tucker_ranks(hs, G)
+        fbytes, nbytes = T.fmm_tucker_storage_bytes(hs, T.FMM_C64)
+        ar = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        T.fmm_tucker_upload(hs, T.FMM_C64, ar)
+        F = torch.empty((G, 2, nd), dtype=torch.complex64, device="cuda")
+        V = torch.empty(lay.n_basis, dtype=torch.complex64, device="cuda")
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            T.fmm_graph_capture(hs, T.FMM_C64, 1, x32, F, g32, V, s)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            T.fmm_graph_launch(hs, s)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+        for a, b in evs:
+            a.record(s)
+            T.fmm_graph_launch(hs, s)
+            b.record(s)
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        b_stage, fac = svd_stage_bytes(rs, lay.offsets, w.n_theta, w.n_phi, 8)
+        assert fac == fbytes, (fac, fbytes)
+        gbs = 2 * b_stage / (ms * 1e-3) / 1e9
+        rep = {"compress_s": round(t_c, 2), "r_beta_mean": round(float(rs[..., 2].mean()), 2),
+               "factors_MB_f32": round(fbytes / 2 ** 20, 1),
+               "tucker_factors_MB_f32": round(tucker_fac_bytes / 2 ** 20, 1),
+               "memory_ratio_svd_over_tucker": round(fbytes / tucker_fac_bytes, 3),
+               "pass_ms": round(ms, 4), "pass_GBps": round(gbs, 1),
+               "time_ratio_svd_over_tucker": round(ms / tucker_ms, 3)}
+        log("svd comparison: %s" % rep)
+        return rep, (F.cpu().numpy(), V.cpu().numpy())
+    finally:
+        T.fmm_tucker_destroy(hs)
 
 
 def multi_rhs(args, T, torch, synth, h, lay, ranks, w):
@@ -422,7 +484,7 @@ def multi_rhs(args, T, torch, synth, h, lay, ranks, w):
     return rep, outs
 
 
-def oracle_checks(args, w, verts, tris, lay, x, gin, F32h, V32h, F64h, V64h, mr_out=None):
+def oracle_checks(args, w, verts, tris, lay, x, gin, F32h, V32h, F64h, V64h, mr_out=None, svd_out=None):
     """End-to-end error of the GPU outputs against the oracle's dense FP64 products on
     sampled groups, and the oracle's own throughput on the same sample."""
     from oracle import geometry as geo
@@ -438,7 +500,8 @@ def oracle_checks(args, w, verts, tris, lay, x, gin, F32h, V32h, F64h, V64h, mr_
     # sample across the size distribution: largest group plus seeded draws
     sample = sorted(set([int(np.argmax(nb))] + list(rng.choice(P.n_groups, size=args.sample_groups - 1,
                                                                    replace=False))))
-    errs = {"tucker_f32_agg": [], "tucker_f32_disagg": [], "dense_f64_agg": [], "dense_f64_disagg": []}
+    errs = {"tucker_f32_agg": [], "tucker_f32_disagg": [], "dense_f64_agg": [], "dense_f64_disagg": [],
+            "svd_f32_agg": [], "svd_f32_disagg": []}
     ref_f, ref_v, got = [], [], {k: [] for k in errs}
     blocks = {}
     for g in sample:
@@ -452,6 +515,9 @@ def oracle_checks(args, w, verts, tris, lay, x, gin, F32h, V32h, F64h, V64h, mr_
         if F64h is not None:
             got["dense_f64_agg"].append(F64h[g])
             got["dense_f64_disagg"].append(V64h[lo:hi])
+        if svd_out is not None:
+            got["svd_f32_agg"].append(svd_out[0][g])
+            got["svd_f32_disagg"].append(svd_out[1][lo:hi])
     out = {"rel_err_vs_oracle": {}}
     for k in errs:
         if not got[k]:
