@@ -136,6 +136,12 @@ fmm_status fmm_geometry_tables(fmm_geometry_t geom, int64_t* offsets, int64_t* p
 /* A layout view of the geometry (offsets pointer owned by the geometry). */
 fmm_status fmm_geometry_layout(fmm_geometry_t geom, fmm_layout* out);
 
+/* The box grid of the FMM-FFT partition (Section II.A): *boxes_per_axis = K (the grid
+ * is K x K x K) and box_of_group host int64 [n_groups] = the linear index
+ * (ix * K + iy) * K + iz of each group's box (either pointer may be NULL).  These are
+ * the arguments fmm_tucker_set_box_grid takes. */
+fmm_status fmm_geometry_boxes(fmm_geometry_t geom, int32_t* boxes_per_axis, int64_t* box_of_group);
+
 /* Dense far-fields P^{alpha,+} of eq. (4) for groups first_group ..
  * first_group+count-1, on the device, FP64:
  *   farfield device complex128 [rows][2][n_theta][n_phi], rows = the groups' basis
@@ -189,6 +195,24 @@ fmm_status fmm_tucker_set_group(fmm_tucker_t h, int32_t group, int32_t alpha, in
                                 int32_t r_phi, int32_t r_beta, const double* core, const double* u_theta,
                                 const double* u_phi, const double* u_beta);
 
+/* Box-grid layout of the spectra (eq. (3) and (5), Section II.A): the outgoing
+ * spectra F^alpha_u of eq. (3) are tensors of K_x x K_y x K_z x N_dir entries per
+ * polarisation, zero on empty boxes, and the incoming spectra G^alpha_u of eq. (5) are
+ * read from the same positions.  After this call every aggregation, disaggregation,
+ * pass and graph capture of the handle takes
+ *   F, G device [2][K_x][K_y][K_z][N_dir][nrhs]   (alpha, then the box's linear index
+ *                                                  (v_x K_y + v_y) K_z + v_z)
+ * instead of [n_groups][2][N_dir][nrhs].  Group g's fibre F^alpha_g sits at box
+ * box_of_group[g] (host int64 [n_groups], distinct values in [0, K_x K_y K_z)).  The
+ * aggregation writes every entry of F: the fibres of the groups, and zero on the
+ * empty boxes (an extra fill of (K - n_groups) 2 N_dir nrhs values).  The
+ * disaggregation reads only the groups' boxes; entries of G at empty boxes are never
+ * read.  kx = ky = kz = 0 with box_of_group = NULL returns to the group-compact layout.
+ * Errors: FMM_ERR_ARG (sizes < 1, a box out of range or holding two groups),
+ * FMM_ERR_SHAPE (fewer boxes than groups), FMM_ERR_SIZE (more than 2^30 boxes).  Like
+ * fmm_tucker_set_group it makes earlier uploads stale: upload again before computing. */
+fmm_status fmm_tucker_set_box_grid(fmm_tucker_t h, int32_t kx, int32_t ky, int32_t kz, const int64_t* box_of_group);
+
 /* Ranks of every tensor: host int32 [n_groups][2][3] = (r_theta, r_phi, r_beta). */
 fmm_status fmm_tucker_ranks(fmm_tucker_t h, int32_t* ranks);
 
@@ -210,14 +234,16 @@ fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* arena, size_t 
 
 /* Aggregation in Tucker format (Section II.C, Fig. 2(b)) for every group and both
  * polarisations: F^alpha_g = A_hat^alpha_g x_g, A_hat the Tucker model of eq. (6).
- *   x device [N][nrhs], F device [n_groups][2][N_dir][nrhs]; complex128 for
+ *   x device [N][nrhs], F device [n_groups][2][N_dir][nrhs] (on a box grid:
+ *   [2][K_x][K_y][K_z][N_dir][nrhs], see fmm_tucker_set_box_grid); complex128 for
  *   FMM_C128, complex64 otherwise.  Requires a prior upload of `prec`. */
 fmm_status fmm_tucker_aggregate(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F,
                                 void* stream);
 
 /* Disaggregation in Tucker format (Section II.C, Fig. 3(b)), summed over the two
  * polarisations as in eq. (5): V_g = sum_alpha (A_hat^alpha_g)* G^alpha_g, with *
- * the conjugate transpose.  G device [n_groups][2][N_dir][nrhs], V device [N][nrhs]. */
+ * the conjugate transpose.  G device [n_groups][2][N_dir][nrhs] (on a box grid:
+ * [2][K_x][K_y][K_z][N_dir][nrhs]), V device [N][nrhs]. */
 fmm_status fmm_tucker_disaggregate(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* G, void* V,
                                    void* stream);
 

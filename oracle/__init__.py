@@ -17,7 +17,8 @@ speed.  Each function cites the passage of the paper it follows:
 * :mod:`oracle.products` -- dense aggregation (eq. (3), Fig. 2(a)) and
   disaggregation (eq. (5), Fig. 3(a)), and the Tucker-format procedures of
   Section II.C (Fig. 2(b) and Fig. 3(b)).
+* :mod:`oracle.boxgrid` -- the spectra on the FMM-FFT box grid (eq. (3), eq. (5)).
 
 Readings of passages that are silent or garbled are listed in each module.
 """
-from . import geometry, farfield, hosvd, products  # noqa: F401
+from . import geometry, farfield, hosvd, products, boxgrid  # noqa: F401

@@ -19,9 +19,10 @@ LIB_PATH = os.path.join(_HERE, "libtuckfmm.so")
 __all__ = [
     "FMM_OK", "FMM_C128", "FMM_C64", "FMM_BF16X2", "FMM_BF16X3", "FmmError", "Layout", "exported_symbols",
     "fmm_last_error", "fmm_version", "fmm_device_count",
-    "fmm_geometry_build", "fmm_geometry_info", "fmm_geometry_tables", "fmm_geometry_layout", "fmm_farfield_fill",
+    "fmm_geometry_build", "fmm_geometry_info", "fmm_geometry_tables", "fmm_geometry_layout", "fmm_geometry_boxes",
+    "fmm_farfield_fill",
     "fmm_geometry_destroy", "fmm_tucker_create", "fmm_farfield_compress", "fmm_farfield_compress_svd",
-    "fmm_tucker_set_group",
+    "fmm_tucker_set_group", "fmm_tucker_set_box_grid",
     "fmm_tucker_ranks", "fmm_tucker_export", "fmm_tucker_storage_bytes", "fmm_tucker_upload",
     "fmm_tucker_aggregate", "fmm_tucker_disaggregate", "fmm_tucker_pass", "fmm_graph_capture", "fmm_graph_launch",
     "fmm_tucker_tune", "fmm_tucker_destroy", "fmm_dense_create", "fmm_dense_aggregate", "fmm_dense_disaggregate",
@@ -76,6 +77,7 @@ _SIGS = {
     "fmm_geometry_info": (_st, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
     "fmm_geometry_tables": (_st, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "fmm_geometry_layout": (_st, [_vp, ctypes.POINTER(fmm_layout)]),
+    "fmm_geometry_boxes": (_st, [_vp, _vp, _vp]),
     "fmm_farfield_fill": (_st, [_vp, _i32, _i32, _vp, _vp]),
     "fmm_geometry_destroy": (None, [_vp]),
     "fmm_tucker_create": (_st, [ctypes.POINTER(fmm_layout), ctypes.POINTER(_vp)]),
@@ -83,6 +85,7 @@ _SIGS = {
     "fmm_farfield_compress_svd": (_st, [ctypes.POINTER(fmm_layout), _vp, _i32, _i32, _f64, _vp,
                                         ctypes.POINTER(_vp)]),
     "fmm_tucker_set_group": (_st, [_vp, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp]),
+    "fmm_tucker_set_box_grid": (_st, [_vp, _i32, _i32, _i32, _vp]),
     "fmm_tucker_ranks": (_st, [_vp, _vp]),
     "fmm_tucker_export": (_st, [_vp, _i32, _i32, _vp, _vp, _vp, _vp]),
     "fmm_tucker_storage_bytes": (_st, [_vp, _st, ctypes.POINTER(_sz), ctypes.POINTER(_sz)]),
@@ -216,6 +219,15 @@ def fmm_geometry_layout(geom):
     return Layout(lay.n_theta, lay.n_phi, tabs["offsets"])
 
 
+def fmm_geometry_boxes(geom):
+    """(K, box_of_group int64 [n_groups]): the K x K x K box grid and each group's box."""
+    _, g = fmm_geometry_info(geom)
+    k = _i32()
+    boxes = np.empty(g, np.int64)
+    _check(_lib.fmm_geometry_boxes(geom, ctypes.byref(k), boxes.ctypes.data))
+    return int(k.value), boxes
+
+
 def fmm_farfield_fill(geom, first_group, count, farfield, stream=None):
     _check(_lib.fmm_farfield_fill(geom, int(first_group), int(count), _ptr(farfield), _stream(stream)))
 
@@ -251,6 +263,16 @@ def fmm_tucker_set_group(h, group, alpha, core, u_theta, u_phi, u_beta):
     rt, rp, rb = core.shape
     _check(_lib.fmm_tucker_set_group(h, int(group), int(alpha), rt, rp, rb, core.ctypes.data, ut.ctypes.data,
                                      up.ctypes.data, ub.ctypes.data))
+
+
+def fmm_tucker_set_box_grid(h, dims, box_of_group):
+    """dims = (K_x, K_y, K_z) and box_of_group [n_groups]; dims = None clears the grid."""
+    if dims is None:
+        _check(_lib.fmm_tucker_set_box_grid(h, 0, 0, 0, None))
+        return
+    boxes = np.ascontiguousarray(box_of_group, dtype=np.int64)
+    kx, ky, kz = (int(d) for d in dims)
+    _check(_lib.fmm_tucker_set_box_grid(h, kx, ky, kz, boxes.ctypes.data))
 
 
 def fmm_tucker_ranks(h, n_groups):

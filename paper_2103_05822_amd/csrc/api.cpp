@@ -84,7 +84,7 @@ bool aligned(const void* p, size_t a) { return reinterpret_cast<uintptr_t>(p) % 
 struct ArenaPlan {
   size_t header_bytes = 0, factor_bytes = 0, total_bytes = 0, factor_bytes_paper = 0;
   std::vector<TuckItem> items;
-  std::vector<int32_t> order, pass;
+  std::vector<int32_t> order, pass, zero_rows;
   TuckMax mx{};
 };
 
@@ -118,6 +118,7 @@ fmm_status plan_arena(const fmm_tucker_s* h, fmm_prec prec, ArenaPlan* P) {
       it.ld_c = (it.rt * it.rp + E - 1) / E * E;
       it.group = g;
       it.alpha = a;
+      it.frow = h->box.empty() ? 2 * g + a : (int32_t)(a * h->n_boxes + h->box[g]);
       it.row0 = L.offsets[g];
       // both orders of the two angular products; take the cheaper one
       const double c_theta = (double)L.n_theta * it.rp * (it.rt + L.n_phi);
@@ -156,8 +157,17 @@ fmm_status plan_arena(const fmm_tucker_s* h, fmm_prec prec, ArenaPlan* P) {
     P->pass[2 * i] = P->order[i];        // aggregation of the i-th largest item
     P->pass[2 * i + 1] = ~P->order[i];   // and its disaggregation
   }
-  P->header_bytes =
-      align_up(P->items.size() * sizeof(TuckItem) + (P->order.size() + P->pass.size()) * sizeof(int32_t), 256);
+  // box grid: the rows of the empty boxes, written zero by the aggregation
+  if (!h->box.empty()) {
+    std::vector<char> used((size_t)h->n_boxes, 0);
+    for (int64_t b : h->box) used[(size_t)b] = 1;
+    for (int a = 0; a < 2; ++a)
+      for (int64_t b = 0; b < h->n_boxes; ++b)
+        if (!used[(size_t)b]) P->zero_rows.push_back((int32_t)(a * h->n_boxes + b));
+  }
+  P->header_bytes = align_up(P->items.size() * sizeof(TuckItem) +
+                                 (P->order.size() + P->pass.size() + P->zero_rows.size()) * sizeof(int32_t),
+                             256);
   P->factor_bytes = off;
   P->total_bytes = P->header_bytes + P->factor_bytes;
   return FMM_OK;
@@ -264,6 +274,9 @@ fmm_status run_stage(fmm_tucker_t h, PrecSlot& s, fmm_prec prec, int nrhs, int s
   Route r;
   fmm_status st = route_of(s, prec, nrhs, &r);
   if (st != FMM_OK) return st;
+  if (stage != 1 && s.plan.n_zero_rows > 0)  // box grid: F is zero on empty boxes (eq. (3))
+    TFMM_HIP(launch_zero_rows(elem_bytes(prec), F, s.plan.zero_rows, s.plan.n_zero_rows,
+                              (int64_t)L.ndir() * nrhs, hs));
   if (r.mfma) {
     // 16-byte operand loads: with an even nrhs every row offset keeps this alignment
     for (const void* p : {x, (const void*)F, G, (const void*)V})
@@ -375,6 +388,40 @@ extern "C" fmm_status fmm_tucker_set_group(fmm_tucker_t h, int32_t group, int32_
   return FMM_OK;
 }
 
+extern "C" fmm_status fmm_tucker_set_box_grid(fmm_tucker_t h, int32_t kx, int32_t ky, int32_t kz,
+                                              const int64_t* box_of_group) {
+  clear_error();
+  if (!h) return fail(FMM_ERR_ARG, "handle is NULL");
+  const int G = h->layout.n_groups;
+  std::vector<int64_t> box;
+  int64_t K = 0;
+  if (kx == 0 && ky == 0 && kz == 0 && box_of_group == nullptr) {
+    // back to the group-compact layout
+  } else {
+    if (kx < 1 || ky < 1 || kz < 1) return fail(FMM_ERR_ARG, "box grid sizes must be >= 1 (or all 0 to clear)");
+    if (!box_of_group) return fail(FMM_ERR_ARG, "box_of_group is NULL");
+    K = (int64_t)kx * ky * kz;
+    if (K > (int64_t)1 << 30) return fail(FMM_ERR_SIZE, "box grid of %lld boxes exceeds 2^30", (long long)K);
+    if (K < G) return fail(FMM_ERR_SHAPE, "%lld boxes cannot hold %d groups", (long long)K, G);
+    std::vector<char> used((size_t)K, 0);
+    box.assign(box_of_group, box_of_group + G);
+    for (int g = 0; g < G; ++g) {
+      if (box[g] < 0 || box[g] >= K) return fail(FMM_ERR_ARG, "box of group %d out of range", g);
+      if (used[(size_t)box[g]]) return fail(FMM_ERR_ARG, "box %lld holds two groups", (long long)box[g]);
+      used[(size_t)box[g]] = 1;
+    }
+  }
+  h->n_boxes = K;
+  h->box = std::move(box);
+  drop_graph(h);
+  for (auto& s : h->slot) {  // item rows and zero lists live in the arenas: upload again
+    s.ready = false;
+    mrhs_release(s);
+    s.tuned.clear();
+  }
+  return FMM_OK;
+}
+
 extern "C" fmm_status fmm_tucker_ranks(fmm_tucker_t h, int32_t* ranks) {
   clear_error();
   if (!h || !ranks) return fail(FMM_ERR_ARG, "handle and ranks must be non-NULL");
@@ -445,6 +492,9 @@ extern "C" fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* are
   p += P.order.size() * sizeof(int32_t);
   const size_t pass_off = (size_t)(p - img.data());
   std::memcpy(p, P.pass.data(), P.pass.size() * sizeof(int32_t));
+  p += P.pass.size() * sizeof(int32_t);
+  const size_t zero_off = (size_t)(p - img.data());
+  if (!P.zero_rows.empty()) std::memcpy(p, P.zero_rows.data(), P.zero_rows.size() * sizeof(int32_t));
   char* fac = img.data() + P.header_bytes;
   const size_t n_t = P.items.size();
   const unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -490,6 +540,8 @@ extern "C" fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* are
   pl.items = reinterpret_cast<const TuckItem*>(sl.arena);
   pl.order = reinterpret_cast<const int32_t*>(sl.arena + order_off);
   pl.pass_list = reinterpret_cast<const int32_t*>(sl.arena + pass_off);
+  pl.zero_rows = P.zero_rows.empty() ? nullptr : reinterpret_cast<const int32_t*>(sl.arena + zero_off);
+  pl.n_zero_rows = (int)P.zero_rows.size();
   pl.n_items = (int)P.items.size();
   pl.n_basis = h->layout.n_basis();
   pl.factors = sl.arena + P.header_bytes;

@@ -27,7 +27,8 @@ struct alignas(16) TuckItem {
   int32_t group, alpha;
   int32_t theta_first;  // 1: contract U^theta before U^phi in the angular stages
   int32_t ident;        // 1: identity angular factors (no angular products)
-  int32_t pad1, pad2;
+  int32_t frow;         // row of the item's fibre in F and G: 2 group + alpha, or alpha K + box on a box grid
+  int32_t pad2;
 };
 static_assert(sizeof(TuckItem) == 96, "TuckItem layout");
 
@@ -41,11 +42,15 @@ struct TuckMax {
 //   order     : the 2G items, largest first
 //   pass_list : the 4G entries of a whole pass, largest first; entry e >= 0 is the
 //               aggregation of item e, e < 0 the disaggregation of item ~e
+//   zero_rows : on a box grid, the rows alpha K + box of the empty boxes, which the
+//               aggregation writes zero
 struct TuckPlan {
   const void* factors = nullptr;
   const TuckItem* items = nullptr;
   const int32_t* order = nullptr;
   const int32_t* pass_list = nullptr;
+  const int32_t* zero_rows = nullptr;  // rows of F on empty boxes (box grid only)
+  int n_zero_rows = 0;
   int n_items = 0;
   int64_t n_basis = 0;
   TuckMax mx{};

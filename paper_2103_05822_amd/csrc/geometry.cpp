@@ -173,6 +173,7 @@ extern "C" fmm_status fmm_geometry_build(const double* verts, int64_t n_verts, c
       G->centers.push_back(origin[0] + (ix + 0.5) * box);
       G->centers.push_back(origin[1] + (iy + 0.5) * box);
       G->centers.push_back(origin[2] + (iz + 0.5) * box);
+      G->box_lin.push_back(L);
     }
   }
   G->offsets.push_back(ne);
@@ -218,6 +219,14 @@ extern "C" fmm_status fmm_geometry_tables(fmm_geometry_t g, int64_t* offsets, in
   if (centers) std::copy(g->centers.begin(), g->centers.end(), centers);
   if (theta) std::copy(g->theta.begin(), g->theta.end(), theta);
   if (phi) std::copy(g->phi.begin(), g->phi.end(), phi);
+  return FMM_OK;
+}
+
+extern "C" fmm_status fmm_geometry_boxes(fmm_geometry_t g, int32_t* boxes_per_axis, int64_t* box_of_group) {
+  clear_error();
+  if (!g) return fail(FMM_ERR_ARG, "geometry is NULL");
+  if (boxes_per_axis) *boxes_per_axis = g->K;
+  if (box_of_group) std::copy(g->box_lin.begin(), g->box_lin.end(), box_of_group);
   return FMM_OK;
 }
 

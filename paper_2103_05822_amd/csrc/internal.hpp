@@ -120,6 +120,10 @@ void mrhs_release(PrecSlot& s);
 struct fmm_tucker_s {
   tuckfmm::Layout layout;
   std::vector<tuckfmm::TensorFactors> t;  // [n_groups * 2], index 2g + alpha
+  // box grid of F and G (eq. (3)): K boxes, box[g] the box of group g; empty: the
+  // group-compact layout [n_groups][2]
+  int64_t n_boxes = 0;
+  std::vector<int64_t> box;
   tuckfmm::PrecSlot slot[4];
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -147,6 +151,7 @@ struct fmm_geometry_s {
   std::vector<double> length;
   std::vector<int64_t> offsets;   // [G+1]
   std::vector<double> centers;    // [G][3]
+  std::vector<int64_t> box_lin;   // [G] linear box index (ix * K + iy) * K + iz
   std::vector<double> theta, phi; // grid
   std::vector<double> dirs;       // [ndir][9]: k_hat, theta_hat, phi_hat
   // device copies for fmm_farfield_fill

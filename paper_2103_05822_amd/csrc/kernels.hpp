@@ -26,6 +26,10 @@ size_t tucker_lds_bytes(const TuckMax& mx);
 hipError_t launch_cgemm(int variant, const CGemm* probs, const CTile* tiles, int n_tiles, const CGemmBases& b,
                         hipStream_t s);
 hipError_t launch_zero_c64(void* v, int64_t n, hipStream_t s);
+// Zero rows[0 .. n_rows) of a row-major array of rows of row_elems complex values of
+// elem_bytes (8 or 16) each.
+hipError_t launch_zero_rows(size_t elem_bytes, void* base, const int32_t* rows, int n_rows, int64_t row_elems,
+                            hipStream_t s);
 
 // Dense (plain) aggregation / disaggregation.
 template <typename T>

@@ -63,7 +63,7 @@ CGemm make_gemm(int32_t M, int32_t N, int32_t K, int64_t a, int32_t abase, int32
 void item_products(const TuckItem& it, const Layout& L, int R, int r0, int rc, const int64_t sa[3],
                    const int64_t sd[3], CGemm out[8]) {
   const int nt = L.n_theta, np = L.n_phi, Q = it.rt * it.rp;
-  const int64_t fo = ((int64_t)it.group * 2 + it.alpha) * L.ndir() * R + r0;  // F / G of the item
+  const int64_t fo = (int64_t)it.frow * L.ndir() * R + r0;  // F / G of the item
   const int64_t xo = it.row0 * R + r0;                                        // x / V of the group
   const int32_t F_ = kBaseFactors, S_ = kBaseScratch;
   // aggregation

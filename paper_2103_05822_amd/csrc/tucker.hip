@@ -267,7 +267,7 @@ __device__ __forceinline__ void agg_angular(const typename Tr<T>::c* __restrict_
   const C* ut = fac + it.off_ut;    // [n_theta][rt]
   const C* upt = fac + it.off_upt;  // [rp][n_phi]
   const int ndir = n_theta * n_phi;
-  C* Fo = F + ((int64_t)(it.group * 2 + it.alpha) * ndir) * nrhs + r;
+  C* Fo = F + ((int64_t)it.frow * ndir) * nrhs + r;
   if (it.ident) {  // truncated-SVD item: t already holds the directions
     for (int i = tid; i < ndir; i += NT) Fo[(int64_t)i * nrhs] = ts[i];
     return;
@@ -314,7 +314,7 @@ __device__ __forceinline__ void dis_angular(const typename Tr<T>::c* __restrict_
   const int rt = it.rt, rp = it.rp, Q = rt * rp;
   const C* ut = fac + it.off_ut;  // [n_theta][rt]
   const C* up = fac + it.off_up;  // [n_phi][rp]
-  const C* Gi = Gin + ((int64_t)(it.group * 2 + it.alpha) * ndir) * nrhs + r;
+  const C* Gi = Gin + ((int64_t)it.frow * ndir) * nrhs + r;
   if (zero_v)
     for (int n = tid; n < it.nb; n += NT) V[(it.row0 + n) * nrhs + r] = czero<C>();
   // the angular order mirrors the aggregation choice
@@ -466,7 +466,31 @@ hipError_t zero(C* v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// One row per blockIdx.x, the row's elements split over blockIdx.y.
+template <typename C>
+__global__ __launch_bounds__(256) void zero_rows_kernel(C* __restrict__ base, const int32_t* __restrict__ rows,
+                                                        int64_t row_elems) {
+  C* row = base + (int64_t)rows[blockIdx.x] * row_elems;
+  for (int64_t i = (int64_t)blockIdx.y * 256 + threadIdx.x; i < row_elems; i += (int64_t)gridDim.y * 256)
+    row[i] = czero<C>();
+}
+
 }  // namespace
+
+hipError_t launch_zero_rows(size_t elem_bytes, void* base, const int32_t* rows, int n_rows, int64_t row_elems,
+                            hipStream_t s) {
+  if (n_rows <= 0 || row_elems <= 0) return hipSuccess;
+  const unsigned ny = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (row_elems + 2047) / 2048), 1024);
+  if (elem_bytes == 16)
+    hipLaunchKernelGGL(zero_rows_kernel<Tr<double>::c>, dim3((unsigned)n_rows, ny), dim3(256), 0, s,
+                       static_cast<Tr<double>::c*>(base), rows, row_elems);
+  else if (elem_bytes == 8)
+    hipLaunchKernelGGL(zero_rows_kernel<Tr<float>::c>, dim3((unsigned)n_rows, ny), dim3(256), 0, s,
+                       static_cast<Tr<float>::c*>(base), rows, row_elems);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
 
 template <typename T>
 size_t tucker_lds_bytes(const TuckMax& mx) {

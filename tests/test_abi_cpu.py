@@ -118,8 +118,37 @@ def test_geometry_matches_oracle(w):
         assert np.array_equal(tab["phi"], P.phi)
         n, ng = T.fmm_geometry_info(g)
         assert (n, ng) == (P.n_basis, P.n_groups)
+        K, boxes = T.fmm_geometry_boxes(g)
+        assert K == w.boxes_per_axis
+        ix, iy, iz = P.box_index.T
+        assert np.array_equal(boxes, (ix * K + iy) * K + iz)
     finally:
         T.fmm_geometry_destroy(g)
+
+
+def test_box_grid_validation_and_arena():
+    rng = synth.rng(12)
+    lay = T.Layout(4, 7, [0, 5, 12, 13])
+    h = T.fmm_tucker_create(lay)
+    try:
+        for g in range(3):
+            nb = int(lay.offsets[g + 1] - lay.offsets[g])
+            for a in range(2):
+                T.fmm_tucker_set_group(h, g, a, *synth.synthetic_tucker(rng, 4, 7, nb, 2, 3, 1))
+        fb0, ab0 = T.fmm_tucker_storage_bytes(h, T.FMM_C64)
+        assert _status(T.fmm_tucker_set_box_grid, h, (2, 0, 2), [0, 1, 2]) == -1    # size < 1
+        assert _status(T.fmm_tucker_set_box_grid, h, (1, 1, 2), [0, 1, 2]) == -2    # 2 boxes, 3 groups
+        assert _status(T.fmm_tucker_set_box_grid, h, (2, 2, 2), [0, 8, 2]) == -1    # box out of range
+        assert _status(T.fmm_tucker_set_box_grid, h, (2, 2, 2), [0, -1, 2]) == -1
+        assert _status(T.fmm_tucker_set_box_grid, h, (2, 2, 2), [3, 1, 3]) == -1    # two groups in a box
+        assert _status(T.fmm_tucker_set_box_grid, h, (1 << 11, 1 << 10, 1 << 10), [0, 1, 2]) == -3
+        T.fmm_tucker_set_box_grid(h, (2, 3, 4), [5, 0, 23])
+        fb1, ab1 = T.fmm_tucker_storage_bytes(h, T.FMM_C64)
+        assert fb1 == fb0 and ab1 >= ab0   # same factors; the header lists 2 * 21 empty rows
+        T.fmm_tucker_set_box_grid(h, None, None)
+        assert T.fmm_tucker_storage_bytes(h, T.FMM_C64) == (fb0, ab0)
+    finally:
+        T.fmm_tucker_destroy(h)
 
 
 def test_geometry_rejects_bad_meshes():
