@@ -59,6 +59,7 @@ def parse():
                    help="groups per far-field fill + compress chunk when the dense tensor is not kept")
     p.add_argument("--mrhs-steps", type=int, default=10, help="timed passes per multi-RHS precision")
     p.add_argument("--no-svd", action="store_true", help="skip the truncated-SVD comparison")
+    p.add_argument("--no-grid", action="store_true", help="skip the box-grid pass")
     p.add_argument("--save-factors", default=None, help="write the compressed factors to this .npz")
     p.add_argument("--load-factors", default=None, help="read the factors from this .npz instead of compressing")
     return p.parse_args()
@@ -352,6 +353,11 @@ def main():
         result["svd_comparison"], svd_out = svd_comparison(args, T, torch, lay, dense, w, x32, g32,
                                                            tucker_ms, fac32)
 
+    # ------------------------------------------------- box-grid spectra (eq. (3), (5))
+    if not args.no_grid:
+        result["box_grid"] = box_grid_pass(T, torch, geom, h, lay, w, arenas[T.FMM_C64], x32, g32, F32, V32,
+                                           tucker_ms, per_stage_bytes["tucker_pass_f32"])
+
     # ------------------------------------------------------------ multi-RHS section
     mr_out = {}
     if args.nrhs > 0:
@@ -375,6 +381,54 @@ def main():
 
 
 MRHS_PRECS = {"c128": 0, "c64": 1, "bf16x2": 2, "bf16x3": 3}
+
+
+def box_grid_pass(T, torch, geom, h, lay, w, ar, x32, g32, F32, V32, tucker_ms, pass_bytes):
+    """The FP32 pass with the spectra on the K x K x K box grid: F and G are
+    [2][K][K][K][N_dir] tensors, the aggregation also writes zero on the empty boxes.
+    Checks that the groups' fibres and V equal the group-compact pass bit for bit, and
+    restores the compact layout (uploads C64 again into the same arena)."""
+    G, nd = lay.n_groups, lay.n_dir
+    K, boxes = T.fmm_geometry_boxes(geom)
+    nbox = K ** 3
+    T.fmm_tucker_set_box_grid(h, (K, K, K), boxes)
+    try:
+        _, nbytes = T.fmm_tucker_storage_bytes(h, T.FMM_C64)
+        # the header grows by the list of empty-box rows
+        gar = ar if nbytes <= ar.numel() else torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        T.fmm_tucker_upload(h, T.FMM_C64, gar)
+        bidx = torch.from_numpy(boxes).to("cuda")
+        Gg = torch.zeros((2, nbox, nd), dtype=torch.complex64, device="cuda")
+        Gg[:, bidx] = g32.transpose(0, 1)          # input construction: each group's G in its box
+        Fg = torch.empty((2, nbox, nd), dtype=torch.complex64, device="cuda")
+        Vg = torch.empty_like(V32)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            T.fmm_graph_capture(h, T.FMM_C64, 1, x32, Fg, Gg, Vg, s)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            T.fmm_graph_launch(h, s)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+        for a, b in evs:
+            a.record(s)
+            T.fmm_graph_launch(h, s)
+            b.record(s)
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        same = bool(torch.equal(Fg[:, bidx].transpose(0, 1), F32) and torch.equal(Vg, V32))
+        empty = torch.ones(nbox, dtype=torch.bool, device="cuda")
+        empty[bidx] = False
+        zeros_ok = bool((Fg[:, empty] == 0).all())
+        zero_bytes = 2 * (nbox - G) * nd * 8
+        rep = {"boxes": [K, K, K], "n_boxes": nbox, "pass_ms": round(ms, 4),
+               "GBps": round((pass_bytes + zero_bytes) / (ms * 1e-3) / 1e9, 1),
+               "zero_fill_bytes": zero_bytes, "overhead_vs_compact": round(ms / tucker_ms - 1.0, 4),
+               "fibres_and_V_equal_compact": same, "empty_boxes_zero": zeros_ok}
+        log("box grid: %s" % rep)
+        return rep
+    finally:
+        T.fmm_tucker_set_box_grid(h, None, None)
+        T.fmm_tucker_upload(h, T.FMM_C64, ar)
 
 
 def svd_comparison(args, T, torch, lay, dense, w, x32, g32, tucker_ms, tucker_fac_bytes):
