@@ -60,8 +60,8 @@ def parse():
     p.add_argument("--mrhs-steps", type=int, default=10, help="timed passes per multi-RHS precision")
     p.add_argument("--no-svd", action="store_true", help="skip the truncated-SVD comparison")
     p.add_argument("--no-grid", action="store_true", help="skip the box-grid pass")
-    p.add_argument("--save-factors", default=None, help="write the compressed factors to this .npz")
-    p.add_argument("--load-factors", default=None, help="read the factors from this .npz instead of compressing")
+    p.add_argument("--save-factors", default=None, help="write the compressed factors to this file")
+    p.add_argument("--load-factors", default=None, help="read the factors from this file instead of compressing")
     return p.parse_args()
 
 
@@ -135,26 +135,16 @@ def dense_stage_bytes(offsets, n_theta, n_phi, es):
     return int(es * (n * 2 * n_theta * n_phi + n + 2 * g * n_theta * n_phi))
 
 
-def save_factors(T, h, lay, ranks, path):
-    """All (group, polarisation) factors in the ABI's shapes, FP64, one .npz."""
-    arrs = {"ranks": ranks, "offsets": lay.offsets, "grid": np.array([lay.n_theta, lay.n_phi])}
-    for g in range(lay.n_groups):
-        nb = int(lay.offsets[g + 1] - lay.offsets[g])
-        for a in range(2):
-            c, ut, up, ub = T.fmm_tucker_export(h, g, a, ranks[g, a], lay.n_theta, lay.n_phi, nb)
-            arrs["%d_%d_c" % (g, a)], arrs["%d_%d_t" % (g, a)] = c, ut
-            arrs["%d_%d_p" % (g, a)], arrs["%d_%d_b" % (g, a)] = up, ub
-    np.savez(path, **arrs)
+def save_factors(T, h, path):
+    """The handle's FP64 factors in the library's own file format."""
+    T.fmm_tucker_save(h, path)
 
 
 def load_factors(T, lay, path):
-    z = np.load(path)
-    assert np.array_equal(z["offsets"], lay.offsets), "factor file is for another layout"
-    h = T.fmm_tucker_create(lay)
-    for g in range(lay.n_groups):
-        for a in range(2):
-            T.fmm_tucker_set_group(h, g, a, z["%d_%d_c" % (g, a)], z["%d_%d_t" % (g, a)],
-                                   z["%d_%d_p" % (g, a)], z["%d_%d_b" % (g, a)])
+    h = T.fmm_tucker_load(path)
+    if not np.array_equal(T.fmm_tucker_layout(h).offsets, lay.offsets):
+        T.fmm_tucker_destroy(h)
+        raise SystemExit("factor file %s is for another layout" % path)
     return h
 
 
@@ -217,7 +207,7 @@ def main():
     t_compress = time.time() - t0
     ranks = T.fmm_tucker_ranks(h, G)
     if args.save_factors:
-        save_factors(T, h, lay, ranks, args.save_factors)
+        save_factors(T, h, args.save_factors)
         log("factors saved to %s" % args.save_factors)
     log("compress: %.1f s, mean ranks %s" % (t_compress, ranks.reshape(-1, 3).mean(0).round(1)))
     arenas = {}

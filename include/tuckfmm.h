@@ -48,7 +48,8 @@ typedef enum {
   FMM_ERR_DEVICE = -4,       /* no usable GPU, or a HIP runtime error            */
   FMM_ERR_NUMERIC = -5,      /* NaN/Inf input or eigensolver failure             */
   FMM_ERR_UNSUPPORTED = -6,  /* precision or shape not supported by this build   */
-  FMM_ERR_STATE = -7         /* call order violated (e.g. compute before upload) */
+  FMM_ERR_STATE = -7,        /* call order violated (e.g. compute before upload) */
+  FMM_ERR_IO = -8            /* file missing, unreadable, truncated or corrupt   */
 } fmm_status;
 
 /* Storage / arithmetic precision of a compute path.
@@ -212,6 +213,24 @@ fmm_status fmm_tucker_set_group(fmm_tucker_t h, int32_t group, int32_t alpha, in
  * FMM_ERR_SHAPE (fewer boxes than groups), FMM_ERR_SIZE (more than 2^30 boxes).  Like
  * fmm_tucker_set_group it makes earlier uploads stale: upload again before computing. */
 fmm_status fmm_tucker_set_box_grid(fmm_tucker_t h, int32_t kx, int32_t ky, int32_t kz, const int64_t* box_of_group);
+
+/* Save the handle's FP64 factors, ranks, layout and box grid to a binary file (host
+ * only), so that the setup of eq. (4) and Section II.B is done once.  Little-endian
+ * 8-byte words: magic, version, layout, box grid, then per (group, alpha) the ranks,
+ * the identity flag and the four complex128 arrays in fmm_tucker_set_group's shapes,
+ * then a checksum (sum of all words mod 2^64).  FMM_ERR_STATE if a tensor is unset,
+ * FMM_ERR_IO if the file cannot be written.  Uploads are not saved. */
+fmm_status fmm_tucker_save(fmm_tucker_t h, const char* path);
+
+/* Load a handle written by fmm_tucker_save into a new handle (*out; NULL on error).
+ * The factors are bit-identical to the saved ones; precisions must be uploaded
+ * again.  FMM_ERR_IO for a missing, truncated or corrupt file (checksum, ranks, sizes
+ * or identity flags inconsistent). */
+fmm_status fmm_tucker_load(const char* path, fmm_tucker_t* out);
+
+/* The handle's layout (offsets pointer owned by the handle, valid until it is
+ * destroyed), e.g. to size buffers for a loaded handle. */
+fmm_status fmm_tucker_layout(fmm_tucker_t h, fmm_layout* out);
 
 /* Ranks of every tensor: host int32 [n_groups][2][3] = (r_theta, r_phi, r_beta). */
 fmm_status fmm_tucker_ranks(fmm_tucker_t h, int32_t* ranks);

@@ -22,7 +22,8 @@ __all__ = [
     "fmm_geometry_build", "fmm_geometry_info", "fmm_geometry_tables", "fmm_geometry_layout", "fmm_geometry_boxes",
     "fmm_farfield_fill",
     "fmm_geometry_destroy", "fmm_tucker_create", "fmm_farfield_compress", "fmm_farfield_compress_svd",
-    "fmm_tucker_set_group", "fmm_tucker_set_box_grid",
+    "fmm_tucker_set_group", "fmm_tucker_set_box_grid", "fmm_tucker_save", "fmm_tucker_load",
+    "fmm_tucker_layout",
     "fmm_tucker_ranks", "fmm_tucker_export", "fmm_tucker_storage_bytes", "fmm_tucker_upload",
     "fmm_tucker_aggregate", "fmm_tucker_disaggregate", "fmm_tucker_pass", "fmm_graph_capture", "fmm_graph_launch",
     "fmm_tucker_tune", "fmm_tucker_destroy", "fmm_dense_create", "fmm_dense_aggregate", "fmm_dense_disaggregate",
@@ -31,7 +32,8 @@ __all__ = [
 
 FMM_OK = 0
 STATUS = {0: "FMM_OK", -1: "FMM_ERR_ARG", -2: "FMM_ERR_SHAPE", -3: "FMM_ERR_SIZE", -4: "FMM_ERR_DEVICE",
-          -5: "FMM_ERR_NUMERIC", -6: "FMM_ERR_UNSUPPORTED", -7: "FMM_ERR_STATE"}
+          -5: "FMM_ERR_NUMERIC", -6: "FMM_ERR_UNSUPPORTED", -7: "FMM_ERR_STATE",
+          -8: "FMM_ERR_IO"}
 FMM_C128, FMM_C64, FMM_BF16X2, FMM_BF16X3 = 0, 1, 2, 3
 
 if not os.path.exists(LIB_PATH):
@@ -86,6 +88,9 @@ _SIGS = {
                                         ctypes.POINTER(_vp)]),
     "fmm_tucker_set_group": (_st, [_vp, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp]),
     "fmm_tucker_set_box_grid": (_st, [_vp, _i32, _i32, _i32, _vp]),
+    "fmm_tucker_save": (_st, [_vp, ctypes.c_char_p]),
+    "fmm_tucker_layout": (_st, [_vp, ctypes.POINTER(fmm_layout)]),
+    "fmm_tucker_load": (_st, [ctypes.c_char_p, ctypes.POINTER(_vp)]),
     "fmm_tucker_ranks": (_st, [_vp, _vp]),
     "fmm_tucker_export": (_st, [_vp, _i32, _i32, _vp, _vp, _vp, _vp]),
     "fmm_tucker_storage_bytes": (_st, [_vp, _st, ctypes.POINTER(_sz), ctypes.POINTER(_sz)]),
@@ -273,6 +278,23 @@ def fmm_tucker_set_box_grid(h, dims, box_of_group):
     boxes = np.ascontiguousarray(box_of_group, dtype=np.int64)
     kx, ky, kz = (int(d) for d in dims)
     _check(_lib.fmm_tucker_set_box_grid(h, kx, ky, kz, boxes.ctypes.data))
+
+
+def fmm_tucker_save(h, path):
+    _check(_lib.fmm_tucker_save(h, os.fsencode(path)))
+
+
+def fmm_tucker_load(path):
+    out = _vp()
+    _check(_lib.fmm_tucker_load(os.fsencode(path), ctypes.byref(out)))
+    return out.value
+
+
+def fmm_tucker_layout(h):
+    lay = fmm_layout()
+    _check(_lib.fmm_tucker_layout(h, ctypes.byref(lay)))
+    offsets = np.ctypeslib.as_array(lay.offsets, shape=(lay.n_groups + 1,)).copy()
+    return Layout(lay.n_theta, lay.n_phi, offsets)
 
 
 def fmm_tucker_ranks(h, n_groups):

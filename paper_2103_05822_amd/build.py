@@ -16,8 +16,8 @@ OUT = os.path.join(PKG, "libtuckfmm.so")
 BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.cpp", "geometry.cpp", "compress.cpp", "mrhs_plan.cpp", "tucker.hip", "dense.hip", "setup.hip",
-           "mrhs.hip"]
+SOURCES = ["api.cpp", "geometry.cpp", "compress.cpp", "mrhs_plan.cpp", "serialize.cpp", "tucker.hip", "dense.hip",
+           "setup.hip", "mrhs.hip"]
 
 COMMON = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

@@ -412,6 +412,9 @@ extern "C" fmm_status fmm_tucker_set_box_grid(fmm_tucker_t h, int32_t kx, int32_
     }
   }
   h->n_boxes = K;
+  h->box_dims[0] = K ? kx : 0;
+  h->box_dims[1] = K ? ky : 0;
+  h->box_dims[2] = K ? kz : 0;
   h->box = std::move(box);
   drop_graph(h);
   for (auto& s : h->slot) {  // item rows and zero lists live in the arenas: upload again
@@ -419,6 +422,17 @@ extern "C" fmm_status fmm_tucker_set_box_grid(fmm_tucker_t h, int32_t kx, int32_
     mrhs_release(s);
     s.tuned.clear();
   }
+  return FMM_OK;
+}
+
+extern "C" fmm_status fmm_tucker_layout(fmm_tucker_t h, fmm_layout* out) {
+  clear_error();
+  if (!h || !out) return fail(FMM_ERR_ARG, "handle and out must be non-NULL");
+  out->n_theta = h->layout.n_theta;
+  out->n_phi = h->layout.n_phi;
+  out->n_groups = h->layout.n_groups;
+  out->reserved = 0;
+  out->offsets = h->layout.offsets.data();
   return FMM_OK;
 }
 

@@ -123,6 +123,7 @@ struct fmm_tucker_s {
   // box grid of F and G (eq. (3)): K boxes, box[g] the box of group g; empty: the
   // group-compact layout [n_groups][2]
   int64_t n_boxes = 0;
+  int32_t box_dims[3] = {0, 0, 0};
   std::vector<int64_t> box;
   tuckfmm::PrecSlot slot[4];
   hipGraph_t graph = nullptr;

@@ -169,3 +169,52 @@ def test_geometry_rejects_bad_meshes():
             assert _status(T.fmm_farfield_fill, g, 0, 1, 256, 0) == -4       # no device
     finally:
         T.fmm_geometry_destroy(g)
+
+
+def test_save_load_round_trip(tmp_path):
+    """A saved handle loads with bit-identical factors, ranks, storage and box grid;
+    truncated or altered files are refused."""
+    rng = synth.rng(13)
+    lay = T.Layout(4, 7, [0, 5, 12, 13])
+    h = T.fmm_tucker_create(lay)
+    h2 = None
+    try:
+        assert _status(T.fmm_tucker_save, h, str(tmp_path / "unset.tuck")) == -7
+        for g in range(3):
+            nb = int(lay.offsets[g + 1] - lay.offsets[g])
+            for a in range(2):
+                if g == 1 and a == 0:   # one identity (truncated-SVD) tensor
+                    f = (synth.complex_normal(rng, (4, 7, 3)), np.eye(4, dtype=complex), np.eye(7, dtype=complex),
+                         synth.complex_normal(rng, (nb, 3)))
+                else:
+                    f = synth.synthetic_tucker(rng, 4, 7, nb, *synth.synthetic_ranks(rng, nb, 4, 7))
+                T.fmm_tucker_set_group(h, g, a, *f)
+        T.fmm_tucker_set_box_grid(h, (2, 3, 2), [11, 0, 6])
+        path = str(tmp_path / "h.tuck")
+        T.fmm_tucker_save(h, path)
+        h2 = T.fmm_tucker_load(path)
+        lay2 = T.fmm_tucker_layout(h2)
+        assert (lay2.n_theta, lay2.n_phi, lay2.n_groups) == (4, 7, 3)
+        assert np.array_equal(lay2.offsets, lay.offsets)
+        r1, r2 = T.fmm_tucker_ranks(h, 3), T.fmm_tucker_ranks(h2, 3)
+        assert np.array_equal(r1, r2)
+        for g in range(3):
+            nb = int(lay.offsets[g + 1] - lay.offsets[g])
+            for a in range(2):
+                for x, y in zip(T.fmm_tucker_export(h, g, a, r1[g, a], 4, 7, nb),
+                                T.fmm_tucker_export(h2, g, a, r2[g, a], 4, 7, nb)):
+                    assert np.array_equal(x, y)
+        for prec in (T.FMM_C128, T.FMM_C64):
+            assert T.fmm_tucker_storage_bytes(h, prec) == T.fmm_tucker_storage_bytes(h2, prec)
+        data = open(path, "rb").read()
+        assert len(data) % 8 == 0
+        for bad, name in ((data[:-8], "trunc"), (data[:200] + bytes([data[200] ^ 1]) + data[201:], "flip"),
+                          (b"NOTAFILE" + data[8:], "magic")):
+            p = str(tmp_path / name)
+            open(p, "wb").write(bad)
+            assert _status(T.fmm_tucker_load, p) == -8
+        assert _status(T.fmm_tucker_load, str(tmp_path / "missing.tuck")) == -8
+    finally:
+        T.fmm_tucker_destroy(h)
+        if h2:
+            T.fmm_tucker_destroy(h2)

@@ -497,3 +497,36 @@ def test_compress_svd_end_to_end(gamma):
                 assert np.linalg.norm(got - ref) <= 1e-9 * anorm, (gg, a)
         err = np.linalg.norm(V[lo:hi] - v_dense[lo:hi])
         assert err <= vbound * (1 + 1e-6) + 1e-12 * np.linalg.norm(v_dense[lo:hi]), (gg, err, vbound)
+
+
+def test_saved_handle_computes_the_same(tmp_path):
+    """A handle written by fmm_tucker_save and read back runs the same pass bit for bit."""
+    w, v, t, P = small_problem()
+    lay = T.Layout(w.n_theta, w.n_phi, P.offsets)
+    g = T.fmm_geometry_build(v, t, w.origin, w.box, w.boxes_per_axis, w.k, w.n_theta, w.n_phi)
+    hs = []
+    try:
+        banner("save/load small")
+        D = dev(np.zeros((P.n_basis, 2, w.n_theta, w.n_phi), np.complex128))
+        T.fmm_farfield_fill(g, 0, P.n_groups, D)
+        hs.append(T.fmm_farfield_compress(lay, D, 0, P.n_groups, 1e-6))
+        path = str(tmp_path / "small.tuck")
+        T.fmm_tucker_save(hs[0], path)
+        hs.append(T.fmm_tucker_load(path))
+        rng = synth.rng(14)
+        x = dev(synth.complex_normal(rng, P.n_basis), np.complex64)
+        gin = dev(synth.complex_normal(rng, (P.n_groups, 2, P.n_dir)), np.complex64)
+        outs, ars = [], []
+        for h in hs:
+            _, nbytes = T.fmm_tucker_storage_bytes(h, T.FMM_C64)
+            ars.append(arena(nbytes))
+            T.fmm_tucker_upload(h, T.FMM_C64, ars[-1])
+            F = dev(np.zeros((P.n_groups, 2, P.n_dir), np.complex64))
+            V = dev(np.zeros(P.n_basis, np.complex64))
+            T.fmm_tucker_pass(h, T.FMM_C64, 1, x, F, gin, V)
+            outs.append((host(F), host(V)))
+    finally:
+        for h in hs:
+            T.fmm_tucker_destroy(h)
+        T.fmm_geometry_destroy(g)
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
