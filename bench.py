@@ -16,6 +16,11 @@ accuracy against the FP64 oracle on sampled groups and the oracle's own CPU
 throughput are reported beside it.
 
 Prints exactly one JSON line on stdout; progress goes to stderr.
+
+``--sweep gamma|digits|box`` instead measures the trends of Figs. 5-7 (trihedral)
+and 9-11 (sphere): memory and FP64 aggregation / disaggregation time of the Tucker
+and truncated-SVD models against the dense far-fields while the tolerance, the FMM
+accuracy (grid size) or the box size changes; it prints one JSON line of points.
 """
 import argparse
 import json
@@ -44,7 +49,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="sphere30",
                    choices=["sphere30", "sphere30g29", "sphere6", "small", "sphere20b0.5", "sphere20b1", "sphere20b2",
-                            "sphere20b4", "sphere45"])
+                            "sphere20b4", "sphere45", "trihedral", "trihedral_small"])
     p.add_argument("--sample-groups", type=int, default=6, help="groups checked against the oracle")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU timing")
     p.add_argument("--no-oracle", action="store_true", help="skip accuracy sampling and the CPU baseline")
@@ -60,6 +65,8 @@ def parse():
     p.add_argument("--mrhs-steps", type=int, default=10, help="timed passes per multi-RHS precision")
     p.add_argument("--no-svd", action="store_true", help="skip the truncated-SVD comparison")
     p.add_argument("--no-grid", action="store_true", help="skip the box-grid pass")
+    p.add_argument("--sweep", choices=["gamma", "digits", "box"], default=None,
+                   help="measure compression and speedup trends instead of the pass benchmark")
     p.add_argument("--save-factors", default=None, help="write the compressed factors to this file")
     p.add_argument("--load-factors", default=None, help="read the factors from this file instead of compressing")
     return p.parse_args()
@@ -68,7 +75,7 @@ def parse():
 def workload(name):
     from synth import workloads as W
     table = {"sphere30": W.SPHERE30, "sphere30g29": W.SPHERE30_G29, "sphere6": W.SPHERE6, "small": W.SMALL,
-             "sphere45": W.SPHERE45}
+             "sphere45": W.SPHERE45, "trihedral": W.TRIHEDRAL, "trihedral_small": W.TRIHEDRAL_SMALL}
     for box, wl in W.SPHERE20.items():
         table["sphere20b%g" % box] = wl
     return table[name]
@@ -163,10 +170,13 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     w = workload(args.workload)
+    if args.sweep:
+        print(json.dumps(sweep(args, T, torch, synth, w)), flush=True)
+        return
     t_setup = time.time()
 
     # ---------------------------------------------------------------- setup (untimed)
-    verts, tris = synth.icosphere(w.freq, w.radius)
+    verts, tris = w.mesh()
     geom = T.fmm_geometry_build(verts, tris, w.origin, w.box, w.boxes_per_axis, w.k, w.n_theta, w.n_phi)
     lay = T.fmm_geometry_layout(geom)
     N, G, nd = lay.n_basis, lay.n_groups, lay.n_dir
@@ -371,6 +381,105 @@ def main():
 
 
 MRHS_PRECS = {"c128": 0, "c64": 1, "bf16x2": 2, "bf16x3": 3}
+
+# L of the angular grid (Section II.A: L = 2kR + (2kR)^(1/3) 1.8 d^(2/3), R half the box
+# diagonal, rounded, plus one) for the sweep points, by (box edge, digits d).
+GRID_ORDER = {(0.5, 3): 13, (1.0, 3): 20, (1.5, 3): 27, (2.0, 3): 33,
+              (0.5, 4): 14, (1.0, 4): 22, (1.5, 4): 29, (2.0, 4): 35,
+              (0.5, 5): 16, (1.0, 5): 24, (1.5, 5): 31, (2.0, 5): 37,
+              (0.5, 6): 17, (1.0, 6): 25, (1.5, 6): 32, (2.0, 6): 39}
+
+
+def time_ms(torch, fn, reps=5):
+    fn()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+
+def sweep(args, T, torch, synth, w):
+    """Trends of Figs. 5-7 / 9-11: per point, far-fields filled and compressed on the
+    GPU by both methods at the point's tolerance, FP64 memory (2^20-byte MB as the
+    paper's tables) and FP64 stage times, plus the FP32 pass of each method."""
+    import math
+    if args.sweep == "gamma":
+        pts = [(w.box, 5, g) for g in (1e-3, 1e-4, 1e-5, 1e-6, 1e-7)]
+    elif args.sweep == "digits":
+        pts = [(w.box, d, w.gamma) for d in (3, 4, 5, 6)]
+    else:
+        pts = [(b, 5, w.gamma) for b in (0.5, 1.0, 1.5, 2.0)]
+    verts, tris = w.mesh()
+    out = {"sweep": args.sweep, "workload": w.name, "n_basis": w.n_basis, "points": []}
+    for box, digits, gamma in pts:
+        L = GRID_ORDER[(box, digits)]
+        nt, nph = L + 1, 2 * L + 1
+        K = int(math.ceil(w.diameter / box - 1e-12))
+        t0 = time.time()
+        geom = T.fmm_geometry_build(verts, tris, w.origin, box, K, w.k, nt, nph)
+        lay = T.fmm_geometry_layout(geom)
+        N, G, nd = lay.n_basis, lay.n_groups, lay.n_dir
+        dense = torch.empty((N, 2, nt, nph), dtype=torch.complex128, device="cuda")
+        T.fmm_farfield_fill(geom, 0, G, dense)
+        torch.cuda.synchronize()
+        handles = {}
+        for name, fn in (("tucker", T.fmm_farfield_compress), ("svd", T.fmm_farfield_compress_svd)):
+            h = None
+            for g0 in range(0, G, args.setup_chunk):
+                h = fn(lay, dense[int(lay.offsets[g0]):], g0, min(args.setup_chunk, G - g0), gamma, handle=h)
+            handles[name] = h
+            log("sweep point box=%g digits=%d gamma=%g: %s compressed (%.1f s)" % (box, digits, gamma, name,
+                                                                                   time.time() - t0))
+        rng = synth.rng(w.seeds.get("x", 0))
+        x = synth.complex_normal(rng, N)
+        gin = synth.complex_normal(rng, (G, 2, nd))
+        x64, g64 = torch.from_numpy(x).to("cuda"), torch.from_numpy(gin).to("cuda")
+        x32, g32 = x64.to(torch.complex64), g64.to(torch.complex64)
+        F64 = torch.empty((G, 2, nd), dtype=torch.complex128, device="cuda")
+        V64 = torch.empty(N, dtype=torch.complex128, device="cuda")
+        F32, V32 = F64.to(torch.complex64), V64.to(torch.complex64)
+        dplan = T.fmm_dense_create(lay)
+        pt = {"box": box, "digits": digits, "gamma": gamma, "L": L, "grid": [nt, nph], "n_groups": G,
+              "n_avg": round(N / G, 1),
+              "dense_MB": round(16 * 2 * N * nd / 2 ** 20, 1),
+              "ms": {"dense_agg": time_ms(torch, lambda: T.fmm_dense_aggregate(dplan, T.FMM_C128, dense, 1, x64, F64)),
+                     "dense_disagg": time_ms(torch, lambda: T.fmm_dense_disaggregate(dplan, T.FMM_C128, dense, 1,
+                                                                                     g64, V64))}}
+        T.fmm_dense_destroy(dplan)
+        dense = None
+        torch.cuda.empty_cache()
+        for name, h in handles.items():
+            ranks = T.fmm_tucker_ranks(h, G)
+            fb, _ = T.fmm_tucker_storage_bytes(h, T.FMM_C128)
+            pt[name + "_MB"] = round(fb / 2 ** 20, 1)
+            pt[name + "_ranks_mean"] = [round(float(v), 1) for v in ranks.reshape(-1, 3).mean(0)]
+            for prec, tag, xx, gg, FF, VV in ((T.FMM_C128, "64", x64, g64, F64, V64),
+                                             (T.FMM_C64, "32", x32, g32, F32, V32)):
+                _, ab = T.fmm_tucker_storage_bytes(h, prec)
+                ar = torch.empty(ab, dtype=torch.uint8, device="cuda")
+                T.fmm_tucker_upload(h, prec, ar)
+                if prec == T.FMM_C128:
+                    pt["ms"][name + "_agg"] = time_ms(torch, lambda: T.fmm_tucker_aggregate(h, prec, 1, xx, FF))
+                    pt["ms"][name + "_disagg"] = time_ms(torch, lambda: T.fmm_tucker_disaggregate(h, prec, 1, gg, VV))
+                else:
+                    pt["ms"][name + "_pass_f32"] = time_ms(torch, lambda: T.fmm_tucker_pass(h, prec, 1, xx, FF, gg, VV))
+                del ar
+            T.fmm_tucker_destroy(h)
+        m = pt["ms"]
+        for name in handles:
+            pt[name + "_compression"] = round(pt["dense_MB"] / pt[name + "_MB"], 2)
+            pt[name + "_speedup_agg"] = round(m["dense_agg"] / m[name + "_agg"], 2)
+            pt[name + "_speedup_disagg"] = round(m["dense_disagg"] / m[name + "_disagg"], 2)
+            pt[name + "_speedup_pass_f32"] = round((m["dense_agg"] + m["dense_disagg"]) / m[name + "_pass_f32"], 2)
+        pt["ms"] = {k: round(v, 4) for k, v in m.items()}
+        T.fmm_geometry_destroy(geom)
+        torch.cuda.empty_cache()
+        log("sweep point: %s" % json.dumps(pt))
+        out["points"].append(pt)
+    return out
 
 
 def box_grid_pass(T, torch, geom, h, lay, w, ar, x32, g32, F32, V32, tucker_ms, pass_bytes):

@@ -104,7 +104,8 @@ int32_t fmm_device_count(void);
 /* ---------------------------------------------------------------- geometry */
 
 /* RWG basis functions (Section II.A, the basis of ref. [20]) and FMM groups
- * (Section II.A, the box partition of FMM-FFT) of a closed triangle mesh.  Host only.
+ * (Section II.A, the box partition of FMM-FFT) of a triangle mesh, closed or open
+ * (e.g. the plates of the trihedral example, Section III.A).  Host only.
  *   verts  host [n_verts][3] double      vertex coordinates (wavelengths)
  *   tris   host [n_tris][3] int32        triangles, counter-clockwise seen from the
  *                                        side the normal points to
@@ -115,8 +116,10 @@ int32_t fmm_device_count(void);
  *   wavenumber k > 0; n_theta >= 1, n_phi >= 1: the angular grid used by
  *          fmm_farfield_fill (Gauss-Legendre nodes in cos(theta), increasing theta;
  *          phi_j = 2 pi j / n_phi).
- * Every edge must be shared by exactly two triangles traversing it in opposite
- * directions (FMM_ERR_SHAPE otherwise).  For an edge (a, b), a < b, T+ is the
+ * An edge shared by two triangles must be traversed by them in opposite directions
+ * and carries one basis function; an edge of one triangle is a free rim and carries
+ * none; an edge of three or more triangles, a degenerate edge or a mesh without
+ * shared edges is FMM_ERR_SHAPE.  For an edge (a, b), a < b, T+ is the
  * triangle traversing a -> b; basis functions are first ordered by (a, b), then
  * stably by group.  The handle copies everything it needs. */
 fmm_status fmm_geometry_build(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,

@@ -34,13 +34,19 @@ import numpy as np
 # --------------------------------------------------------------------------- RWG
 
 def rwg(verts, tris):
-    """Build the RWG basis of a closed, consistently oriented triangle mesh.
+    """Build the RWG basis (ref. [20]) of a consistently oriented triangle mesh.
 
-    Returns a dict of arrays, one row per basis function (edge order):
-      ``edge`` [N,2] end vertices (a < b), ``tri_p``/``tri_m`` [N] triangle indices,
-      ``free_p``/``free_m`` [N] opposite vertices, ``length`` [N] edge length.
-    Raises ``ValueError`` for an edge not shared by exactly two triangles with
-    opposite traversal directions.
+    An edge shared by two triangles that traverse it in opposite directions carries
+    one basis function.  An edge of a single triangle lies on the rim of an open
+    surface (the plates of the trihedral example, Section III.A) and carries none:
+    no current crosses a free edge.
+
+    Returns a dict of arrays, one row per basis function in (a, b) order:
+      ``edge`` [N,2] end vertices (a < b), ``tri_p``/``tri_m`` [N] triangle indices
+      (T+ traverses a -> b), ``free_p``/``free_m`` [N] opposite vertices, ``length``
+      [N] edge length.
+    Raises ``ValueError`` for an edge of more than two triangles or of two triangles
+    traversing it the same way.
     """
     tris = np.asarray(tris, dtype=np.int64)
     nt = tris.shape[0]
@@ -54,24 +60,21 @@ def rwg(verts, tris):
     forward = u < w
     order = np.lexsort((~forward, hi, lo))      # by (lo, hi), forward first
     lo, hi, forward, opp, tri_id = lo[order], hi[order], forward[order], opp[order], tri_id[order]
-    if lo.size % 2:
-        raise ValueError("mesh is not closed")
-    a_lo, b_lo = lo[0::2], lo[1::2]
-    a_hi, b_hi = hi[0::2], hi[1::2]
-    if not (np.array_equal(a_lo, b_lo) and np.array_equal(a_hi, b_hi)):
-        raise ValueError("every edge must be shared by exactly two triangles")
-    if not (np.all(forward[0::2]) and not np.any(forward[1::2])):
+    key = lo * (int(hi.max()) + 1) + hi
+    first = np.flatnonzero(np.concatenate([[True], np.diff(key) != 0]))
+    count = np.diff(np.concatenate([first, [key.size]]))
+    if np.any(count > 2):
+        raise ValueError("an edge is shared by more than two triangles")
+    a = first[count == 2]                       # forward half of each shared edge
+    b = a + 1
+    if not (np.all(forward[a]) and not np.any(forward[b])):
         raise ValueError("triangles are not consistently oriented")
-    if a_lo.size > 1:
-        key = a_lo * (int(hi.max()) + 1) + a_hi
-        if np.any(np.diff(key) <= 0):
-            raise ValueError("an edge is shared by more than two triangles")
     verts = np.asarray(verts, dtype=np.float64)
     return {
-        "edge": np.stack([a_lo, a_hi], axis=1),
-        "tri_p": tri_id[0::2], "tri_m": tri_id[1::2],
-        "free_p": opp[0::2], "free_m": opp[1::2],
-        "length": np.linalg.norm(verts[a_hi] - verts[a_lo], axis=1),
+        "edge": np.stack([lo[a], hi[a]], axis=1),
+        "tri_p": tri_id[a], "tri_m": tri_id[b],
+        "free_p": opp[a], "free_m": opp[b],
+        "length": np.linalg.norm(verts[hi[a]] - verts[lo[a]], axis=1),
     }
 
 

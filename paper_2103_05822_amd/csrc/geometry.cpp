@@ -78,7 +78,7 @@ extern "C" fmm_status fmm_geometry_build(const double* verts, int64_t n_verts, c
   G->n_theta = n_theta;
   G->n_phi = n_phi;
 
-  // ---- RWG: every edge shared by exactly two oppositely traversing triangles
+  // ---- RWG basis functions on the edges shared by two triangles
   std::vector<DirEdge> de(3 * n_tris);
   for (int64_t t = 0; t < n_tris; ++t) {
     const int32_t* v = tris + 3 * t;
@@ -99,34 +99,41 @@ extern "C" fmm_status fmm_geometry_build(const double* verts, int64_t n_verts, c
     if (a.forward != b.forward) return a.forward > b.forward;
     return a.tri < b.tri;
   });
-  if (de.size() % 2) {
-    delete G;
-    return fail(FMM_ERR_SHAPE, "mesh is not closed");
-  }
-  const int64_t ne = (int64_t)de.size() / 2;
-  std::vector<int64_t> elo(ne), ehi(ne);
-  std::vector<int32_t> tp(ne), tm(ne), fp(ne), fm(ne);
-  for (int64_t e = 0; e < ne; ++e) {
-    const DirEdge& a = de[2 * e];
-    const DirEdge& b = de[2 * e + 1];
-    if (a.lo != b.lo || a.hi != b.hi || a.lo == a.hi) {
+  // an edge of two oppositely traversing triangles carries a basis function; an edge
+  // of one triangle is on the rim of an open surface and carries none
+  std::vector<int64_t> elo, ehi;
+  std::vector<int32_t> tp, tm, fp, fm;
+  for (size_t i = 0; i < de.size();) {
+    size_t j = i + 1;
+    while (j < de.size() && de[j].lo == de[i].lo && de[j].hi == de[i].hi) ++j;
+    if (de[i].lo == de[i].hi) {
       delete G;
-      return fail(FMM_ERR_SHAPE, "every edge must be shared by exactly two triangles");
+      return fail(FMM_ERR_SHAPE, "degenerate triangle edge at vertex %d", de[i].lo);
     }
-    if (!(a.forward == 1 && b.forward == 0)) {
-      delete G;
-      return fail(FMM_ERR_SHAPE, "triangles are not consistently oriented");
-    }
-    if (e > 0 && de[2 * e - 1].lo == a.lo && de[2 * e - 1].hi == a.hi) {
+    if (j - i > 2) {
       delete G;
       return fail(FMM_ERR_SHAPE, "an edge is shared by more than two triangles");
     }
-    elo[e] = a.lo;
-    ehi[e] = a.hi;
-    tp[e] = a.tri;
-    fp[e] = a.opp;
-    tm[e] = b.tri;
-    fm[e] = b.opp;
+    if (j - i == 2) {
+      const DirEdge& a = de[i];
+      const DirEdge& b = de[i + 1];
+      if (!(a.forward == 1 && b.forward == 0)) {
+        delete G;
+        return fail(FMM_ERR_SHAPE, "triangles are not consistently oriented");
+      }
+      elo.push_back(a.lo);
+      ehi.push_back(a.hi);
+      tp.push_back(a.tri);
+      fp.push_back(a.opp);
+      tm.push_back(b.tri);
+      fm.push_back(b.opp);
+    }
+    i = j;
+  }
+  const int64_t ne = (int64_t)elo.size();
+  if (ne == 0) {
+    delete G;
+    return fail(FMM_ERR_SHAPE, "the mesh has no edge shared by two triangles");
   }
 
   // ---- grouping by edge midpoint

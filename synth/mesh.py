@@ -116,3 +116,53 @@ def icosphere(freq, radius=1.0, center=(0.0, 0.0, 0.0)):
     r = float(radius)
     verts = verts * r + np.asarray(center, dtype=np.float64)[None, :]
     return verts, tri
+
+
+def trihedral(edge, n):
+    """Trihedral corner reflector: three mutually perpendicular square plates of side
+    ``edge`` in the planes x = 0, y = 0 and z = 0, meeting at the origin and spanning
+    the first octant.  Each plate is an ``n x n`` grid of squares, each square split
+    into two triangles along its (0,0)-(1,1) diagonal.  Points on the three shared
+    axes are one vertex each, so the plates are joined along the axes.
+
+    Triangles are oriented with normals -x, -y, -z (away from the octant), which
+    traverses every shared edge in opposite directions from its two triangles.  The
+    mesh has 3 n (n + 1) + 1 vertices, 6 n^2 triangles and 9 n^2 - 3 n edges with two
+    triangles (the plates' outer rims, 6 n edges, have one).
+
+    Returns ``(vertices [V,3] float64, triangles [F,3] int32)``.
+    """
+    n = int(n)
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    h = float(edge) / n
+    key = {}
+    verts = []
+
+    def vid(i, j, k):
+        if (i, j, k) not in key:
+            key[(i, j, k)] = len(verts)
+            verts.append((i * h, j * h, k * h))
+        return key[(i, j, k)]
+
+    tris = []
+    # plate axis pairs (u, v) and the normal each plate gets
+    plates = [((0, 1), np.array([0.0, 0.0, -1.0])),   # z = 0: u = x, v = y
+              ((0, 2), np.array([0.0, -1.0, 0.0])),   # y = 0: u = x, v = z
+              ((1, 2), np.array([-1.0, 0.0, 0.0]))]   # x = 0: u = y, v = z
+    for (au, av), normal in plates:
+        eu = np.zeros(3)
+        ev = np.zeros(3)
+        eu[au] = 1.0
+        ev[av] = 1.0
+        flip = np.dot(np.cross(eu, ev), normal) < 0
+        for a in range(n):
+            for b in range(n):
+                def p(da, db):
+                    c = [0, 0, 0]
+                    c[au], c[av] = a + da, b + db
+                    return vid(*c)
+                p00, p10, p11, p01 = p(0, 0), p(1, 0), p(1, 1), p(0, 1)
+                for t in ((p00, p10, p11), (p00, p11, p01)):
+                    tris.append((t[0], t[2], t[1]) if flip else t)
+    return np.array(verts, dtype=np.float64), np.array(tris, dtype=np.int32)

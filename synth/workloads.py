@@ -1,14 +1,17 @@
-"""Workload parameters of the synthetic stand-ins for the paper's sphere examples.
+"""Workload parameters of the synthetic stand-ins for the paper's examples.
 
 Lengths are in wavelengths (lambda = 1, wavenumber k = 2 pi).  The angular grids
 are written out as integers; ``tests/test_oracle_geometry.py`` checks them against the
 sampling rule of Section II.A as the oracle implements it (n_theta = L + 1,
 n_phi = 2 L + 1, L from the box's enclosing radius and the FMM accuracy).
 
-Every workload is a geodesic sphere of diameter ``diameter`` meshed with
+A sphere workload is a geodesic sphere of diameter ``diameter`` meshed with
 frequency ``freq`` (``30 freq^2`` basis functions), grouped by a cubic box grid of
 edge ``box`` anchored at the sphere's bounding-box corner (-R, -R, -R) with
-``ceil(diameter / box)`` boxes per axis.
+``ceil(diameter / box)`` boxes per axis.  A trihedral workload is the corner
+reflector of three square plates of side ``diameter`` meshed with ``freq`` squares
+per side (``9 freq^2 - 3 freq`` basis functions), its box grid anchored at the
+corner (0, 0, 0).
 """
 import math
 from dataclasses import dataclass, field
@@ -25,6 +28,7 @@ class Workload:
     gamma: float
     nrhs: int = 1
     seeds: dict = field(default_factory=dict)
+    shape: str = "sphere"
 
     @property
     def radius(self):
@@ -36,6 +40,8 @@ class Workload:
 
     @property
     def n_basis(self):
+        if self.shape == "trihedral":
+            return 9 * self.freq * self.freq - 3 * self.freq
         return 30 * self.freq * self.freq
 
     @property
@@ -44,8 +50,17 @@ class Workload:
 
     @property
     def origin(self):
+        if self.shape == "trihedral":
+            return (0.0, 0.0, 0.0)
         r = self.radius
         return (-r, -r, -r)
+
+    def mesh(self):
+        """``(vertices, triangles)`` of the workload's surface."""
+        from .mesh import icosphere, trihedral
+        if self.shape == "trihedral":
+            return trihedral(self.diameter, self.freq)
+        return icosphere(self.freq, self.radius)
 
 
 # Small workload: 1-wavelength sphere, 1280 triangles, 1920 basis functions,
@@ -78,4 +93,16 @@ SPHERE20 = {
 SPHERE45 = Workload("sphere-45lambda-f277-box2-grid38x75", 45.0, 277, 2.0, 38, 75, 1e-5, 32,
                     {"x": 3, "sample": 4})
 
-ALL = {w.name: w for w in [SMALL, SPHERE30, SPHERE30_G29, SPHERE6, SPHERE45, *SPHERE20.values()]}
+# The paper's second example: a trihedral corner reflector of three 6-lambda plates
+# (Section III.A; the paper meshes it with 42,477 basis functions, here 69 squares
+# per side give 42,642), box 2 lambda (19 non-empty boxes of the 3 x 3 x 3 grid),
+# 38 x 75 grid (L = 37, the grid of its Table I memory figure).
+TRIHEDRAL = Workload("trihedral-6lambda-n69-box2-grid38x75", 6.0, 69, 2.0, 38, 75, 1e-6,
+                     seeds={"x": 0, "g": 1}, shape="trihedral")
+# Small trihedral for CPU checks: 2-lambda plates, 12 squares per side (1260 basis
+# functions), box 1 lambda (7 groups), 25 x 49 grid (L = 24).
+TRIHEDRAL_SMALL = Workload("trihedral-2lambda-n12-box1-grid25x49", 2.0, 12, 1.0, 25, 49, 1e-6,
+                           seeds={"x": 0, "g": 1}, shape="trihedral")
+
+ALL = {w.name: w for w in [SMALL, SPHERE30, SPHERE30_G29, SPHERE6, SPHERE45, *SPHERE20.values(),
+                           TRIHEDRAL, TRIHEDRAL_SMALL]}

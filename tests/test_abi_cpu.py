@@ -104,9 +104,9 @@ def test_factor_import_export_round_trip_and_storage():
         T.fmm_tucker_destroy(h)
 
 
-@pytest.mark.parametrize("w", [W.SMALL, W.SPHERE6], ids=lambda w: w.name)
+@pytest.mark.parametrize("w", [W.SMALL, W.SPHERE6, W.TRIHEDRAL_SMALL], ids=lambda w: w.name)
 def test_geometry_matches_oracle(w):
-    v, t = synth.icosphere(w.freq, w.radius)
+    v, t = w.mesh()
     g = T.fmm_geometry_build(v, t, w.origin, w.box, w.boxes_per_axis, w.k, w.n_theta, w.n_phi)
     try:
         tab = T.fmm_geometry_tables(g)
@@ -154,7 +154,8 @@ def test_box_grid_validation_and_arena():
 def test_geometry_rejects_bad_meshes():
     v, t = synth.icosphere(2, 1.0)
     args = ((-1.0,) * 3, 2.0, 1, 2 * np.pi, 4, 7)
-    assert _status(T.fmm_geometry_build, v, t[:-1], *args) == -2
+    assert _status(T.fmm_geometry_build, v, np.concatenate([t, t[:1, [0, 2, 1]]]), *args) == -2
+    assert _status(T.fmm_geometry_build, v, t[:1], *args) == -2          # no shared edge
     bad = t.copy()
     bad[0] = bad[0][[0, 2, 1]]
     assert _status(T.fmm_geometry_build, v, bad, *args) == -2

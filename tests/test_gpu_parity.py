@@ -39,9 +39,8 @@ def ragged_layout(n_theta=5, n_phi=9):
     return T.Layout(n_theta, n_phi, np.concatenate([[0], np.cumsum(sizes)]))
 
 
-def small_problem():
-    w = W.SMALL
-    v, t = synth.icosphere(w.freq, w.radius)
+def small_problem(w=W.SMALL):
+    v, t = w.mesh()
     return w, v, t, geo.Problem(v, t, w.origin, w.box, w.boxes_per_axis, w.n_theta, w.n_phi)
 
 
@@ -247,12 +246,13 @@ def test_dense_ragged_layout(prec, nrhs):
 
 # -------------------------------------------------------------------- far-field + compress
 
-def test_farfield_fill_matches_oracle():
-    w, v, t, P = small_problem()
+@pytest.mark.parametrize("w", [W.SMALL, W.TRIHEDRAL_SMALL], ids=["sphere", "trihedral"])
+def test_farfield_fill_matches_oracle(w):
+    w, v, t, P = small_problem(w)
     D_ref = ff.farfield_all(P)
     g = T.fmm_geometry_build(v, t, w.origin, w.box, w.boxes_per_axis, w.k, w.n_theta, w.n_phi)
     try:
-        banner("farfield fill small")
+        banner("farfield fill %s" % w.name)
         D = dev(np.zeros(D_ref.shape, np.complex128))
         T.fmm_farfield_fill(g, 0, P.n_groups, D)
         D = host(D)
@@ -266,18 +266,20 @@ def test_farfield_fill_matches_oracle():
     assert np.array_equal(D2, D[P.offsets[3]:P.offsets[5]])
 
 
+@pytest.mark.parametrize("w", [W.SMALL, W.TRIHEDRAL_SMALL], ids=["sphere", "trihedral"])
 @pytest.mark.parametrize("gamma", [1e-6, 1e-4, 0.0])
-def test_compress_end_to_end(gamma):
+def test_compress_end_to_end(gamma, w):
     """GPU far-field -> GPU HOSVD -> GPU Tucker products against the oracle's dense
     products with its own far-field: the difference is the compression error,
-    bounded by gamma ||A||_F ||x|| per tensor (plus rounding)."""
-    w, v, t, P = small_problem()
+    bounded by gamma ||A||_F ||x|| per tensor (plus rounding).  Closed (sphere) and
+    open (trihedral plates) surfaces."""
+    w, v, t, P = small_problem(w)
     D_ref = ff.farfield_all(P)
     lay = T.Layout(w.n_theta, w.n_phi, P.offsets)
     g = T.fmm_geometry_build(v, t, w.origin, w.box, w.boxes_per_axis, w.k, w.n_theta, w.n_phi)
     h = None
     try:
-        banner("compress small gamma=%g" % gamma)
+        banner("compress %s gamma=%g" % (w.name, gamma))
         D = dev(np.zeros(D_ref.shape, np.complex128))
         T.fmm_farfield_fill(g, 0, P.n_groups, D)
         h = T.fmm_farfield_compress(lay, D, 0, P.n_groups, gamma)

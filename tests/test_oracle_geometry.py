@@ -62,14 +62,74 @@ def test_rwg_orientation_rule():
         assert np.isclose(b["length"][n], np.linalg.norm(v[b_] - v[a_]))
 
 
-def test_rwg_rejects_open_or_misoriented_mesh():
+def test_rwg_open_and_misoriented_meshes():
     v, t = synth.icosphere(2, 1.0)
-    with pytest.raises(ValueError):
-        geo.rwg(v, t[:-1])
+    full = geo.rwg(v, t)
+    holed = geo.rwg(v, t[:-1])               # a hole: its three edges become rim edges
+    assert holed["edge"].shape[0] == full["edge"].shape[0] - 3
+    rim = {tuple(sorted((int(t[-1][i]), int(t[-1][(i + 1) % 3])))) for i in range(3)}
+    assert not rim & {tuple(e) for e in holed["edge"].tolist()}
     bad = t.copy()
     bad[0] = bad[0][[0, 2, 1]]
     with pytest.raises(ValueError):
         geo.rwg(v, bad)
+    with pytest.raises(ValueError):          # three triangles on one edge
+        geo.rwg(v, np.concatenate([t, t[:1, [0, 2, 1]]]))
+
+
+@pytest.mark.parametrize("n", [1, 2, 5])
+def test_trihedral_mesh(n):
+    """Counts, Euler characteristic of a disc, orientation and the junctions along
+    the axes, checked by brute force over the triangles."""
+    v, t = synth.trihedral(6.0, n)
+    assert v.shape == (3 * n * (n + 1) + 1, 3) and t.shape == (6 * n * n, 3)
+    edges = {}
+    for k, tri in enumerate(t.tolist()):
+        for i in range(3):
+            e = tuple(sorted((tri[i], tri[(i + 1) % 3])))
+            edges.setdefault(e, []).append(k)
+    shared = [e for e, ts in edges.items() if len(ts) == 2]
+    assert len(shared) == 9 * n * n - 3 * n and len(edges) - len(shared) == 6 * n
+    assert v.shape[0] - len(edges) + t.shape[0] == 1
+    # normals point away from the first octant; plate k holds triangles 2 n^2 k ..
+    a, b, c = v[t[:, 0]], v[t[:, 1]], v[t[:, 2]]
+    nrm = np.cross(b - a, c - a)
+    for k, axis in enumerate((2, 1, 0)):
+        sl = slice(2 * n * n * k, 2 * n * n * (k + 1))
+        assert np.all(nrm[sl, axis] < 0) and np.allclose(np.delete(nrm[sl], axis, axis=1), 0.0)
+    # edges on the axes join two plates
+    plate = lambda k: k // (2 * n * n)
+    on_axis = [e for e in shared if np.count_nonzero(v[e[0]]) <= 1 and np.count_nonzero(v[e[1]]) <= 1
+               and np.count_nonzero(v[e[0]] + v[e[1]]) == 1]
+    assert len(on_axis) == 3 * n
+    assert all(plate(edges[e][0]) != plate(edges[e][1]) for e in on_axis)
+    b_ = geo.rwg(v, t)
+    assert sorted(map(tuple, b_["edge"].tolist())) == sorted(shared)
+
+
+def test_trihedral_workloads(golden_dir):
+    """Basis counts and groups of the trihedral workloads, and the sizes of the three
+    kinds of box of Table II (trihedral corner, dihedral edge, flat plate) against
+    the paper's for boxes of 0.5 and 2 lambda (the mesh differs: 42,642 basis
+    functions against the paper's 42,477; box means within 5% at 2 lambda and 10%
+    at 0.5 lambda, where the 0.5-lambda boxes cut the 6/69-lambda squares)."""
+    for w, groups in ((W.TRIHEDRAL_SMALL, 7), (W.TRIHEDRAL, 19)):
+        v, t = w.mesh()
+        P = geo.Problem(v, t, w.origin, w.box, w.boxes_per_axis, w.n_theta, w.n_phi)
+        assert P.n_basis == w.n_basis and P.n_groups == groups
+    ref = json.load(open(os.path.join(golden_dir, "paper_trihedral_boxes.json")))
+    assert abs(W.TRIHEDRAL.n_basis - ref["n_basis"]) / ref["n_basis"] < 0.005
+    for box, paper in ref["box_lambda_to_nbeta"].items():
+        a = float(box)
+        L = geo.grid_order(a, 5)
+        P = geo.Problem(v, t, (0.0, 0.0, 0.0), a, int(math.ceil(6.0 / a - 1e-12)), L + 1, 2 * L + 1)
+        nb = P.group_sizes()
+        zeros = (P.box_index == 0).sum(axis=1)   # 3: the corner box, 2: on an axis, 1: on one plate
+        assert np.count_nonzero(zeros == 3) == 1
+        tol = 0.05 if a >= 2.0 else 0.10
+        for kind, want in zip((3, 2, 1), paper):
+            got = nb[zeros == kind].mean()
+            assert abs(got - want) / want < tol, (box, kind, got, want)
 
 
 def test_grouping_small_workload():
@@ -110,7 +170,7 @@ def test_grid_order_reproduces_table_iv(golden_dir):
 
 
 def test_workload_grids_follow_the_rule():
-    for w in [W.SPHERE30, W.SPHERE6, W.SPHERE45, *W.SPHERE20.values()]:
+    for w in [W.SPHERE30, W.SPHERE6, W.SPHERE45, *W.SPHERE20.values(), W.TRIHEDRAL, W.TRIHEDRAL_SMALL]:
         L = geo.grid_order(w.box, 5)
         assert (w.n_theta, w.n_phi) == (L + 1, 2 * L + 1), w.name
 
