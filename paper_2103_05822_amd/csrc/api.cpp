@@ -84,12 +84,33 @@ bool aligned(const void* p, size_t a) { return reinterpret_cast<uintptr_t>(p) % 
 struct ArenaPlan {
   size_t header_bytes = 0, factor_bytes = 0, total_bytes = 0, factor_bytes_paper = 0;
   std::vector<TuckItem> items;
+  std::vector<TuckUnit> units;
+  std::vector<TuckSplit> splits;
+  int64_t part_stride = 0;
   std::vector<int32_t> order, pass, zero_rows;
   TuckMax mx{};
 };
 
 // Bytes streamed by one item (U^beta and the core), the key of the work lists.
 double item_cost(const TuckItem& it) { return (double)it.rb * ((double)it.ld_ub + (double)it.ld_c); }
+
+// Items streaming more than this many elements run as blocks of their r_beta rows
+// on several workgroups, so that a layout of few large groups still spreads over
+// the whole GPU: at least kSplitMin elements per block, and no splitting while the
+// items already give about kSplitUnits blocks of that size.
+constexpr double kSplitMin = 65536.0;
+constexpr double kSplitUnits = 512.0;
+constexpr int kSplitMinRows = 4;
+
+double split_elems(const std::vector<TuckItem>& items) {
+  if (const char* env = std::getenv("TUCKFMM_SPLIT_ELEMS")) {
+    const double v = std::atof(env);
+    if (v >= 1.0) return v;
+  }
+  double total = 0.0;
+  for (const TuckItem& it : items) total += item_cost(it);
+  return std::max(kSplitMin, total / kSplitUnits);
+}
 
 fmm_status plan_arena(const fmm_tucker_s* h, fmm_prec prec, ArenaPlan* P) {
   const Layout& L = h->layout;
@@ -146,15 +167,48 @@ fmm_status plan_arena(const fmm_tucker_s* h, fmm_prec prec, ArenaPlan* P) {
     }
   }
   P->mx = mx;
+  // work units: whole items, or row blocks of the items above the split size
+  const double split = split_elems(P->items);
+  int64_t agg_off = 0, dis_off = 0;
+  std::vector<double> ucost;
+  for (int i = 0; i < 2 * G; ++i) {
+    const TuckItem& it = P->items[i];
+    const double c = item_cost(it);
+    int parts = (int)std::min<double>(std::ceil(c / split), (it.rb + kSplitMinRows - 1) / kSplitMinRows);
+    if (parts > 1) {
+      const int rows = (it.rb + parts - 1) / parts;
+      parts = (it.rb + rows - 1) / rows;
+      TuckSplit sp{};
+      sp.item = i;
+      sp.n_parts = parts;
+      sp.q_pad = (it.rt * it.rp + 1) / 2 * 2;
+      sp.nb_pad = (it.nb + 1) / 2 * 2;
+      sp.agg_off = agg_off;
+      sp.dis_off = dis_off;
+      agg_off += (int64_t)parts * sp.q_pad;
+      dis_off += (int64_t)parts * sp.nb_pad;
+      const int j = (int)P->splits.size();
+      P->splits.push_back(sp);
+      for (int s = 0; s < parts; ++s) {
+        const int b0 = s * rows, b1 = std::min(it.rb, b0 + rows);
+        P->units.push_back(TuckUnit{i, b0, b1, j, s, 0});
+        ucost.push_back(c * (b1 - b0) / it.rb);
+      }
+    } else {
+      P->units.push_back(TuckUnit{i, 0, it.rb, -1, 0, 0});
+      ucost.push_back(c);
+    }
+  }
+  for (TuckSplit& sp : P->splits) sp.dis_off += agg_off;  // one buffer: agg blocks, then dis blocks
+  P->part_stride = (agg_off + dis_off + 31) / 32 * 32;
   // work lists in longest-processing-time order
-  const int n = 2 * G;
+  const int n = (int)P->units.size();
   P->order.resize(n);
   std::iota(P->order.begin(), P->order.end(), 0);
-  std::stable_sort(P->order.begin(), P->order.end(),
-                   [&](int32_t a, int32_t b) { return item_cost(P->items[a]) > item_cost(P->items[b]); });
+  std::stable_sort(P->order.begin(), P->order.end(), [&](int32_t a, int32_t b) { return ucost[a] > ucost[b]; });
   P->pass.resize((size_t)2 * n);
   for (int i = 0; i < n; ++i) {
-    P->pass[2 * i] = P->order[i];        // aggregation of the i-th largest item
+    P->pass[2 * i] = P->order[i];        // aggregation of the i-th largest unit
     P->pass[2 * i + 1] = ~P->order[i];   // and its disaggregation
   }
   // box grid: the rows of the empty boxes, written zero by the aggregation
@@ -165,7 +219,8 @@ fmm_status plan_arena(const fmm_tucker_s* h, fmm_prec prec, ArenaPlan* P) {
       for (int64_t b = 0; b < h->n_boxes; ++b)
         if (!used[(size_t)b]) P->zero_rows.push_back((int32_t)(a * h->n_boxes + b));
   }
-  P->header_bytes = align_up(P->items.size() * sizeof(TuckItem) +
+  P->header_bytes = align_up(P->items.size() * sizeof(TuckItem) + P->units.size() * sizeof(TuckUnit) +
+                                 P->splits.size() * sizeof(TuckSplit) +
                                  (P->order.size() + P->pass.size() + P->zero_rows.size()) * sizeof(int32_t),
                              256);
   P->factor_bytes = off;
@@ -267,6 +322,33 @@ fmm_status route_of(const PrecSlot& s, fmm_prec prec, int nrhs, Route* r) {
   return FMM_OK;
 }
 
+// Drops a captured graph (it may point at tables or factors about to change).
+void drop_graph(fmm_tucker_t h);
+
+// Partial-sum buffer of the split items for nrhs right-hand sides (grown on demand;
+// a graph captured with the old buffer is dropped).
+fmm_status ensure_part(fmm_tucker_t h, PrecSlot& s, fmm_prec prec, int nrhs) {
+  if (s.plan.n_splits == 0) return FMM_OK;
+  const size_t need = (size_t)s.plan.part_stride * nrhs * elem_bytes(prec);
+  if (need > s.part_bytes) {
+    drop_graph(h);
+    if (s.part) (void)hipFree(s.part);
+    s.part = nullptr;
+    s.part_bytes = 0;
+    TFMM_HIP(hipMalloc(&s.part, need));
+    s.part_bytes = need;
+  }
+  s.plan.part = s.part;
+  return FMM_OK;
+}
+
+void part_release(PrecSlot& s) {
+  if (s.part) (void)hipFree(s.part);
+  s.part = nullptr;
+  s.part_bytes = 0;
+  s.plan.part = nullptr;
+}
+
 // Launches one stage (0 aggregation, 1 disaggregation, 2 both) for a validated call.
 fmm_status run_stage(fmm_tucker_t h, PrecSlot& s, fmm_prec prec, int nrhs, int stage, const void* x, void* F,
                      const void* G, void* V, hipStream_t hs) {
@@ -285,6 +367,7 @@ fmm_status run_stage(fmm_tucker_t h, PrecSlot& s, fmm_prec prec, int nrhs, int s
     if ((st = mrhs_get(s, L, nrhs, r.tile_steps, r.rhs_chunk, &mp)) != FMM_OK) return st;
     return mrhs_run(*mp, s, r.variant, stage, x, F, G, V, hs);
   }
+  if ((st = ensure_part(h, s, prec, nrhs)) != FMM_OK) return st;
   if (prec == FMM_C128) {
     if ((st = lds_check(tucker_lds_bytes<double>(s.plan.mx))) != FMM_OK) return st;
     if (stage == 0) TFMM_HIP(launch_tucker_agg<double>(s.plan, r.threads, L.n_theta, L.n_phi, nrhs, x, F, hs));
@@ -299,7 +382,6 @@ fmm_status run_stage(fmm_tucker_t h, PrecSlot& s, fmm_prec prec, int nrhs, int s
   return FMM_OK;
 }
 
-// Drops a captured graph (it may point at tables or factors about to change).
 void drop_graph(fmm_tucker_t h) {
   if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
   if (h->graph) (void)hipGraphDestroy(h->graph);
@@ -501,6 +583,12 @@ extern "C" fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* are
   char* p = img.data();
   std::memcpy(p, P.items.data(), P.items.size() * sizeof(TuckItem));
   p += P.items.size() * sizeof(TuckItem);
+  const size_t units_off = (size_t)(p - img.data());
+  std::memcpy(p, P.units.data(), P.units.size() * sizeof(TuckUnit));
+  p += P.units.size() * sizeof(TuckUnit);
+  const size_t splits_off = (size_t)(p - img.data());
+  if (!P.splits.empty()) std::memcpy(p, P.splits.data(), P.splits.size() * sizeof(TuckSplit));
+  p += P.splits.size() * sizeof(TuckSplit);
   const size_t order_off = (size_t)(p - img.data());
   std::memcpy(p, P.order.data(), P.order.size() * sizeof(int32_t));
   p += P.order.size() * sizeof(int32_t);
@@ -537,8 +625,8 @@ extern "C" fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* are
     // workgroup size of the streaming kernels from the mean streamed elements per item:
     // small items leave most of a large workgroup idle
     double c = 0.0;
-    for (const TuckItem& it : P.items) c += item_cost(it);
-    c /= std::max<size_t>(1, P.items.size());
+    for (const TuckUnit& u : P.units) c += item_cost(P.items[u.item]) * (u.b1 - u.b0) / P.items[u.item].rb;
+    c /= std::max<size_t>(1, P.units.size());
     // (measured on MI355X: mean 12k and 50k elements run best at 128, 258k at 256)
     sl.threads = c >= 1.5e6 ? 512 : (c >= 1e5 ? 256 : 128);
     if (const char* env = std::getenv("TUCKFMM_STREAM_THREADS")) {
@@ -556,6 +644,12 @@ extern "C" fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* are
   pl.pass_list = reinterpret_cast<const int32_t*>(sl.arena + pass_off);
   pl.zero_rows = P.zero_rows.empty() ? nullptr : reinterpret_cast<const int32_t*>(sl.arena + zero_off);
   pl.n_zero_rows = (int)P.zero_rows.size();
+  pl.units = reinterpret_cast<const TuckUnit*>(sl.arena + units_off);
+  pl.splits = P.splits.empty() ? nullptr : reinterpret_cast<const TuckSplit*>(sl.arena + splits_off);
+  pl.n_units = (int)P.units.size();
+  pl.n_splits = (int)P.splits.size();
+  pl.part_stride = P.part_stride;
+  pl.part = nullptr;
   pl.n_items = (int)P.items.size();
   pl.n_basis = h->layout.n_basis();
   pl.factors = sl.arena + P.header_bytes;
@@ -622,6 +716,8 @@ extern "C" fmm_status fmm_graph_capture(fmm_tucker_t h, fmm_prec prec, int32_t n
   if (r.mfma) {
     MrhsPlan* mp = nullptr;
     if ((st = mrhs_get(*s, h->layout, nrhs, r.tile_steps, r.rhs_chunk, &mp)) != FMM_OK) return st;
+  } else if ((st = ensure_part(h, *s, prec, nrhs)) != FMM_OK) {
+    return st;
   }
   TFMM_HIP(hipStreamBeginCapture(hs, hipStreamCaptureModeThreadLocal));
   fmm_status d = run_stage(h, *s, prec, nrhs, 2, x, F, G, V, hs);
@@ -733,7 +829,10 @@ extern "C" fmm_status fmm_graph_launch(fmm_tucker_t h, void* stream) {
 extern "C" void fmm_tucker_destroy(fmm_tucker_t h) {
   if (!h) return;
   drop_graph(h);
-  for (auto& s : h->slot) mrhs_release(s);
+  for (auto& s : h->slot) {
+    mrhs_release(s);
+    part_release(s);
+  }
   delete h;
 }
 

@@ -32,6 +32,28 @@ struct alignas(16) TuckItem {
 };
 static_assert(sizeof(TuckItem) == 96, "TuckItem layout");
 
+// Work unit of the streaming kernels: a whole item (split < 0), or rows [b0, b1) of
+// the item's U^beta^T and core when the item is split over several workgroups; then
+// the unit writes partial sums to block `sub` of split entry `split`.
+struct TuckUnit {
+  int32_t item;
+  int32_t b0, b1;
+  int32_t split, sub;
+  int32_t pad;
+};
+static_assert(sizeof(TuckUnit) == 24, "TuckUnit layout");
+
+// A split item: its n_parts partial blocks, per right-hand side at
+//   agg: part + r part_stride + agg_off + s q_pad   (q_pad complex values each)
+//   dis: part + r part_stride + dis_off + s nb_pad  (nb_pad complex values each)
+// are summed in order s = 0, 1, ... by the finishing kernel.
+struct TuckSplit {
+  int64_t agg_off, dis_off;
+  int32_t item, n_parts;
+  int32_t q_pad, nb_pad;
+};
+static_assert(sizeof(TuckSplit) == 32, "TuckSplit layout");
+
 // Maxima over all items of a precision slot; they size the kernels' LDS.
 struct TuckMax {
   int32_t nb, rt, rp, rb, q;
@@ -39,9 +61,11 @@ struct TuckMax {
 };
 
 // Device pointers and sizes of one uploaded precision.
-//   order     : the 2G items, largest first
-//   pass_list : the 4G entries of a whole pass, largest first; entry e >= 0 is the
-//               aggregation of item e, e < 0 the disaggregation of item ~e
+//   units     : the work units (whole items and row blocks of split items)
+//   order     : the units, largest first
+//   pass_list : 2 n_units entries of a whole pass, largest first; entry e >= 0 is the
+//               aggregation of unit e, e < 0 the disaggregation of unit ~e
+//   splits    : the split items, summed by the finishing kernel
 //   zero_rows : on a box grid, the rows alpha K + box of the empty boxes, which the
 //               aggregation writes zero
 struct TuckPlan {
@@ -51,6 +75,11 @@ struct TuckPlan {
   const int32_t* pass_list = nullptr;
   const int32_t* zero_rows = nullptr;  // rows of F on empty boxes (box grid only)
   int n_zero_rows = 0;
+  const TuckUnit* units = nullptr;
+  const TuckSplit* splits = nullptr;
+  int n_units = 0, n_splits = 0;
+  int64_t part_stride = 0;  // partial-sum elements per right-hand side
+  void* part = nullptr;     // library-owned partial sums (device), set per call
   int n_items = 0;
   int64_t n_basis = 0;
   TuckMax mx{};

@@ -89,6 +89,8 @@ struct PrecSlot {
   int threads = 512;                // default workgroup size of the streaming kernels
   std::list<MrhsPlan> mrhs;         // built on first use per (nrhs, knobs); stable addresses
   std::vector<TuneChoice> tuned;
+  void* part = nullptr;             // library-owned partial sums of split items (device)
+  size_t part_bytes = 0;
 };
 
 // Multi-RHS path (mrhs_plan.cpp).

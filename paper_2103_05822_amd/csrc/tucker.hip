@@ -214,37 +214,41 @@ __device__ __forceinline__ void atomic_add_c(double2* p, double2 v) {
 
 // ------------------------------------------------------------------ aggregation
 
-// Streaming phase: y = U^beta^T x (row-dots), then t = core^T y (column axpy) written
-// as packs to `t_out` in LDS.  t[q], q = theta' r_phi + phi'.
+// Streaming phase over rows [b0, b1) of U^beta^T and the core: y = U^beta^T x
+// (row-dots), then t = core^T y (column axpy) written as packs to `t_out` -- LDS for
+// a whole item, the unit's partial-sum block in global memory for a row block of a
+// split item.  t[q], q = theta' r_phi + phi'.
 template <typename T, int NT>
 __device__ __forceinline__ void agg_stream(const typename Tr<T>::c* __restrict__ fac, const TuckItem& it,
                                            const Lds<T>& L, unsigned char* smem, int nrhs, int r,
-                                           const typename Tr<T>::c* __restrict__ x, typename Tr<T>::c* t_out) {
+                                           const typename Tr<T>::c* __restrict__ x, int b0, int b1,
+                                           typename Tr<T>::c* t_out) {
   using C = typename Tr<T>::c;
   using P = typename Tr<T>::pack;
   constexpr int E = Tr<T>::E;
   C* xs = reinterpret_cast<C*>(smem);
   C* ys = xs + L.r1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nb = it.nb, rb = it.rb, Q = it.rt * it.rp;
+  const int nb = it.nb, Q = it.rt * it.rp;
   const int nbp = round_up(nb, E);
 
   // x of the group into LDS (zero padded to whole packs)
   for (int n = tid; n < nbp; n += NT) xs[n] = n < nb ? x[(it.row0 + n) * nrhs + r] : czero<C>();
   __syncthreads();
 
-  // y = U^beta^T x
-  wave_rowdots<T>(fac + it.off_ubt, it.ld_ub, wave, rb, (NT / 64), reinterpret_cast<const P*>(xs), nbp / E, ys,
-                  lane);
+  // y = U^beta^T x (rows b0 .. b1 - 1)
+  wave_rowdots<T>(fac + it.off_ubt, it.ld_ub, b0 + wave, b1, (NT / 64), reinterpret_cast<const P*>(xs), nbp / E,
+                  ys, lane);
   __syncthreads();
 
-  // t = core^T y; t_out may alias x, which is no longer read
+  // t = core^T y over the same rows; t_out may alias x, which is no longer read
   const int qpk = round_up(Q, E) / E;
   for (int base = 0; base < qpk; base += NT * kColPacks) {
     P acc[kColPacks];
 #pragma unroll
     for (int j = 0; j < kColPacks; ++j) acc[j] = pzero<P>();
-    block_colaxpy<T, NT>(fac + it.off_core, it.ld_c, rb, ys, qpk, base, tid, acc);
+    block_colaxpy<T, NT>(fac + it.off_core + (int64_t)b0 * it.ld_c, it.ld_c, b1 - b0, ys + b0, qpk, base, tid,
+                         acc);
 #pragma unroll
     for (int j = 0; j < kColPacks; ++j) {
       const int p = base + tid + NT * j;
@@ -345,21 +349,23 @@ __device__ __forceinline__ void dis_angular(const typename Tr<T>::c* __restrict_
   for (int o = Q + tid; o < round_up(Q, E); o += NT) S2[o] = czero<C>();  // pack padding
 }
 
-// Streaming phase: s = core S (row-dots) with S in LDS region s2, then
-// V[n] += conj(sum_b U^beta[n][b] s[b]) (column axpy, atomic adds).
+// Streaming phase over rows [b0, b1): s = core S (row-dots) with S in LDS region s2,
+// then v[n] = sum_b U^beta[n][b] s[b] (column axpy).  A whole item adds conj(v) to V
+// (atomic adds); a row block of a split item (part_out != nullptr) stores v as its
+// partial-sum block.
 template <typename T, int NT>
 __device__ __forceinline__ void dis_stream(const typename Tr<T>::c* __restrict__ fac, const TuckItem& it,
-                                           const Lds<T>& L, unsigned char* smem, int nrhs, int r,
-                                           typename Tr<T>::c* __restrict__ V) {
+                                           const Lds<T>& L, unsigned char* smem, int nrhs, int r, int b0, int b1,
+                                           typename Tr<T>::c* part_out, typename Tr<T>::c* __restrict__ V) {
   using C = typename Tr<T>::c;
   using P = typename Tr<T>::pack;
   constexpr int E = Tr<T>::E;
   C* S2 = reinterpret_cast<C*>(smem) + L.s1;
   C* s3 = S2 + L.s2;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int rb = it.rb, Q = it.rt * it.rp;
+  const int Q = it.rt * it.rp;
   // s[b] = sum_q core[b][q] S[q]
-  wave_rowdots<T>(fac + it.off_core, it.ld_c, wave, rb, (NT / 64), reinterpret_cast<const P*>(S2),
+  wave_rowdots<T>(fac + it.off_core, it.ld_c, b0 + wave, b1, (NT / 64), reinterpret_cast<const P*>(S2),
                   round_up(Q, E) / E, s3, lane);
   __syncthreads();
   // V[n] += conj(sum_b U^beta[n][b] s[b])
@@ -370,11 +376,14 @@ __device__ __forceinline__ void dis_stream(const typename Tr<T>::c* __restrict__
     P acc[kColPacks];
 #pragma unroll
     for (int j = 0; j < kColPacks; ++j) acc[j] = pzero<P>();
-    block_colaxpy<T, NT>(fac + it.off_ubt, it.ld_ub, rb, s3, npk, base, tid, acc);
+    block_colaxpy<T, NT>(fac + it.off_ubt + (int64_t)b0 * it.ld_ub, it.ld_ub, b1 - b0, s3 + b0, npk, base, tid,
+                         acc);
 #pragma unroll
     for (int j = 0; j < kColPacks; ++j) {
       const int p = base + tid + NT * j;
-      if (p < npk) {
+      if (p < npk && part_out) {
+        reinterpret_cast<P*>(part_out)[p] = acc[j];
+      } else if (p < npk) {
         const C* vals = reinterpret_cast<const C*>(&acc[j]);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -388,68 +397,150 @@ __device__ __forceinline__ void dis_stream(const typename Tr<T>::c* __restrict__
 
 // ---------------------------------------------------------------------- kernels
 
+// Aggregation of one work unit: a whole item (stream, angular phase, F written) or a
+// row block of a split item (its partial t stored for the finishing kernel).
+template <typename T, int NT>
+__device__ __forceinline__ void agg_unit(const typename Tr<T>::c* __restrict__ fac, const TuckItem* items,
+                                         const TuckUnit& u, const TuckSplit* splits, const Lds<T>& L,
+                                         unsigned char* smem, int n_theta, int n_phi, int nrhs, int r,
+                                         const typename Tr<T>::c* __restrict__ x, typename Tr<T>::c* __restrict__ F,
+                                         typename Tr<T>::c* part, int64_t part_stride) {
+  using C = typename Tr<T>::c;
+  const TuckItem it = items[u.item];
+  if (u.split < 0) {
+    C* ts = reinterpret_cast<C*>(smem);  // t over x
+    agg_stream<T, NT>(fac, it, L, smem, nrhs, r, x, 0, it.rb, ts);
+    __syncthreads();
+    agg_angular<T, NT>(fac, it, L, smem, ts, n_theta, n_phi, nrhs, r, F);
+  } else {
+    const TuckSplit sp = splits[u.split];
+    agg_stream<T, NT>(fac, it, L, smem, nrhs, r, x, u.b0, u.b1,
+                      part + r * part_stride + sp.agg_off + (int64_t)u.sub * sp.q_pad);
+  }
+}
+
+// Disaggregation of one work unit: angular phase, then the stream over the unit's
+// rows; a whole item adds into V, a row block stores its partial v.
+template <typename T, int NT>
+__device__ __forceinline__ void dis_unit(const typename Tr<T>::c* __restrict__ fac, const TuckItem* items,
+                                         const TuckUnit& u, const TuckSplit* splits, const Lds<T>& L,
+                                         unsigned char* smem, int n_theta, int n_phi, int nrhs, int r,
+                                         const typename Tr<T>::c* __restrict__ G, typename Tr<T>::c* __restrict__ V,
+                                         typename Tr<T>::c* part, int64_t part_stride) {
+  using C = typename Tr<T>::c;
+  const TuckItem it = items[u.item];
+  C* dst = nullptr;
+  if (u.split >= 0) {
+    const TuckSplit sp = splits[u.split];
+    dst = part + r * part_stride + sp.dis_off + (int64_t)u.sub * sp.nb_pad;
+  }
+  dis_angular<T, NT>(fac, it, L, smem, n_theta, n_phi, nrhs, r, G, reinterpret_cast<C*>(smem) + L.s1, false, V);
+  __syncthreads();
+  dis_stream<T, NT>(fac, it, L, smem, nrhs, r, u.b0, u.b1, dst, V);
+}
+
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void tucker_agg_kernel(const typename Tr<T>::c* __restrict__ fac,
-                                                              const TuckItem* __restrict__ items,
-                                                              const int32_t* __restrict__ order, TuckMax mx,
-                                                              int n_theta, int n_phi, int nrhs,
-                                                              const typename Tr<T>::c* __restrict__ x,
-                                                              typename Tr<T>::c* __restrict__ F) {
-  using C = typename Tr<T>::c;
+                                                        const TuckItem* __restrict__ items,
+                                                        const TuckUnit* __restrict__ units,
+                                                        const TuckSplit* __restrict__ splits,
+                                                        const int32_t* __restrict__ order, TuckMax mx, int n_theta,
+                                                        int n_phi, int nrhs, const typename Tr<T>::c* __restrict__ x,
+                                                        typename Tr<T>::c* __restrict__ F, typename Tr<T>::c* part,
+                                                        int64_t part_stride) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const TuckItem it = items[order[blockIdx.x]];
-  const Lds<T> L(mx);
-  C* ts = reinterpret_cast<C*>(smem);  // t over x
-  agg_stream<T, NT>(fac, it, L, smem, nrhs, blockIdx.y, x, ts);
-  __syncthreads();
-  agg_angular<T, NT>(fac, it, L, smem, ts, n_theta, n_phi, nrhs, blockIdx.y, F);
+  const TuckUnit u = units[order[blockIdx.x]];
+  agg_unit<T, NT>(fac, items, u, splits, Lds<T>(mx), smem, n_theta, n_phi, nrhs, blockIdx.y, x, F, part,
+                  part_stride);
 }
 
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void tucker_dis_kernel(const typename Tr<T>::c* __restrict__ fac,
-                                                              const TuckItem* __restrict__ items,
-                                                              const int32_t* __restrict__ order, TuckMax mx,
-                                                              int n_theta, int n_phi, int nrhs,
-                                                              const typename Tr<T>::c* __restrict__ G,
-                                                              typename Tr<T>::c* __restrict__ V) {
-  using C = typename Tr<T>::c;
+                                                        const TuckItem* __restrict__ items,
+                                                        const TuckUnit* __restrict__ units,
+                                                        const TuckSplit* __restrict__ splits,
+                                                        const int32_t* __restrict__ order, TuckMax mx, int n_theta,
+                                                        int n_phi, int nrhs, const typename Tr<T>::c* __restrict__ G,
+                                                        typename Tr<T>::c* __restrict__ V, typename Tr<T>::c* part,
+                                                        int64_t part_stride) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const TuckItem it = items[order[blockIdx.x]];
-  const Lds<T> L(mx);
-  dis_angular<T, NT>(fac, it, L, smem, n_theta, n_phi, nrhs, blockIdx.y, G, reinterpret_cast<C*>(smem) + L.s1, false, V);
-  __syncthreads();
-  dis_stream<T, NT>(fac, it, L, smem, nrhs, blockIdx.y, V);
+  const TuckUnit u = units[order[blockIdx.x]];
+  dis_unit<T, NT>(fac, items, u, splits, Lds<T>(mx), smem, n_theta, n_phi, nrhs, blockIdx.y, G, V, part,
+                  part_stride);
 }
 
 // One launch for a whole aggregation + disaggregation pass: work-list entry e is
-// aggregation item e if e >= 0 and disaggregation item ~e otherwise.  Both stages'
-// items interleave in one longest-first list, so small items of either stage fill
-// the end of the launch.
+// the aggregation of unit e if e >= 0 and the disaggregation of unit ~e otherwise.
+// Both stages' units interleave in one longest-first list, so small units of either
+// stage fill the end of the launch.
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void tucker_pass_kernel(const typename Tr<T>::c* __restrict__ fac,
-                                                               const TuckItem* __restrict__ items,
-                                                               const int32_t* __restrict__ list, TuckMax mx,
-                                                               int n_theta, int n_phi, int nrhs,
-                                                               const typename Tr<T>::c* __restrict__ x,
-                                                               typename Tr<T>::c* __restrict__ F,
-                                                               const typename Tr<T>::c* __restrict__ G,
-                                                               typename Tr<T>::c* __restrict__ V) {
-  using C = typename Tr<T>::c;
+                                                         const TuckItem* __restrict__ items,
+                                                         const TuckUnit* __restrict__ units,
+                                                         const TuckSplit* __restrict__ splits,
+                                                         const int32_t* __restrict__ list, TuckMax mx, int n_theta,
+                                                         int n_phi, int nrhs, const typename Tr<T>::c* __restrict__ x,
+                                                         typename Tr<T>::c* __restrict__ F,
+                                                         const typename Tr<T>::c* __restrict__ G,
+                                                         typename Tr<T>::c* __restrict__ V, typename Tr<T>::c* part,
+                                                         int64_t part_stride) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int32_t e = list[blockIdx.x];
   const Lds<T> L(mx);
-  const int r = blockIdx.y;
-  if (e >= 0) {
-    const TuckItem it = items[e];
-    C* ts = reinterpret_cast<C*>(smem);  // t over x
-    agg_stream<T, NT>(fac, it, L, smem, nrhs, r, x, ts);
+  if (e >= 0)
+    agg_unit<T, NT>(fac, items, units[e], splits, L, smem, n_theta, n_phi, nrhs, blockIdx.y, x, F, part,
+                    part_stride);
+  else
+    dis_unit<T, NT>(fac, items, units[~e], splits, L, smem, n_theta, n_phi, nrhs, blockIdx.y, G, V, part,
+                    part_stride);
+}
+
+// Finishing kernel of the split items, after the units: blocks [0, n_agg) sum the
+// partial t of split entry blockIdx.x (in block order, so the result does not depend
+// on the schedule) and run the angular phase into F; blocks [n_agg, gridDim.x) sum
+// the partial v of split entry blockIdx.x - n_agg and add conj(v) to V.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void tucker_finish_kernel(const typename Tr<T>::c* __restrict__ fac,
+                                                           const TuckItem* __restrict__ items,
+                                                           const TuckSplit* __restrict__ splits, int n_agg,
+                                                           TuckMax mx, int n_theta, int n_phi, int nrhs,
+                                                           const typename Tr<T>::c* __restrict__ part,
+                                                           int64_t part_stride, typename Tr<T>::c* __restrict__ F,
+                                                           typename Tr<T>::c* __restrict__ V) {
+  using C = typename Tr<T>::c;
+  constexpr int E = Tr<T>::E;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int r = blockIdx.y, tid = threadIdx.x;
+  const bool agg = (int)blockIdx.x < n_agg;
+  const TuckSplit sp = splits[agg ? blockIdx.x : blockIdx.x - n_agg];
+  const TuckItem it = items[sp.item];
+  const C* base = part + r * part_stride;
+  if (agg) {
+    const int Q = it.rt * it.rp;
+    C* ts = reinterpret_cast<C*>(smem);
+    for (int q = tid; q < round_up(Q, E); q += NT) {
+      C acc = czero<C>();
+      if (q < Q)
+        for (int s = 0; s < sp.n_parts; ++s) {
+          const C v = base[sp.agg_off + (int64_t)s * sp.q_pad + q];
+          acc.x += v.x;
+          acc.y += v.y;
+        }
+      ts[q] = acc;
+    }
     __syncthreads();
-    agg_angular<T, NT>(fac, it, L, smem, ts, n_theta, n_phi, nrhs, r, F);
+    agg_angular<T, NT>(fac, it, Lds<T>(mx), smem, ts, n_theta, n_phi, nrhs, r, F);
   } else {
-    const TuckItem it = items[~e];
-    dis_angular<T, NT>(fac, it, L, smem, n_theta, n_phi, nrhs, r, G, reinterpret_cast<C*>(smem) + L.s1, false, V);
-    __syncthreads();
-    dis_stream<T, NT>(fac, it, L, smem, nrhs, r, V);
+    C* Vo = V + it.row0 * nrhs + r;
+    for (int n = tid; n < it.nb; n += NT) {
+      C acc = czero<C>();
+      for (int s = 0; s < sp.n_parts; ++s) {
+        const C v = base[sp.dis_off + (int64_t)s * sp.nb_pad + n];
+        acc.x += v.x;
+        acc.y += v.y;
+      }
+      atomic_add_c(Vo + (int64_t)n * nrhs, conjc(acc));
+    }
   }
 }
 
@@ -520,16 +611,36 @@ size_t tucker_lds_bytes(const TuckMax& mx) {
   }
 
 template <typename T>
+hipError_t launch_finish(const TuckPlan& pl, int threads, int n_agg, int n_dis, int n_theta, int n_phi, int nrhs,
+                         void* F, void* V, hipStream_t s) {
+  using C = typename Tr<T>::c;
+  if (n_agg + n_dis == 0) return hipSuccess;
+  const size_t lds = n_agg ? Lds<T>(pl.mx).agg_bytes() : 0;
+  // n_dis > 0 with n_agg == 0 runs the disaggregation blocks only: splits from 0
+  const TuckSplit* sp = pl.splits;
+  TFMM_NT_SWITCH(threads,
+                 hipLaunchKernelGGL((tucker_finish_kernel<T, NT>), dim3(n_agg + n_dis, nrhs), dim3(NT), lds, s,
+                                    static_cast<const C*>(pl.factors), pl.items, sp, n_agg, pl.mx, n_theta, n_phi,
+                                    nrhs, static_cast<const C*>(pl.part), pl.part_stride, static_cast<C*>(F),
+                                    static_cast<C*>(V)))
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_tucker_agg(const TuckPlan& pl, int threads, int n_theta, int n_phi, int nrhs, const void* x,
                              void* F, hipStream_t s) {
   using C = typename Tr<T>::c;
-  if (pl.n_items == 0) return hipSuccess;
+  if (pl.n_units == 0) return hipSuccess;
+  if (pl.n_splits > 0 && pl.part == nullptr) return hipErrorInvalidValue;
   TFMM_NT_SWITCH(threads,
-                 hipLaunchKernelGGL((tucker_agg_kernel<T, NT>), dim3(pl.n_items, nrhs), dim3(NT),
+                 hipLaunchKernelGGL((tucker_agg_kernel<T, NT>), dim3(pl.n_units, nrhs), dim3(NT),
                                     Lds<T>(pl.mx).agg_bytes(), s, static_cast<const C*>(pl.factors), pl.items,
-                                    pl.order, pl.mx, n_theta, n_phi, nrhs, static_cast<const C*>(x),
-                                    static_cast<C*>(F)))
-  return hipGetLastError();
+                                    pl.units, pl.splits, pl.order, pl.mx, n_theta, n_phi, nrhs,
+                                    static_cast<const C*>(x), static_cast<C*>(F), static_cast<C*>(pl.part),
+                                    pl.part_stride))
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finish<T>(pl, threads, pl.n_splits, 0, n_theta, n_phi, nrhs, F, nullptr, s);
 }
 
 template <typename T>
@@ -537,14 +648,18 @@ hipError_t launch_tucker_disagg(const TuckPlan& pl, int threads, int n_theta, in
                                 void* V, hipStream_t s) {
   using C = typename Tr<T>::c;
   if (threads != 128 && threads != 256 && threads != 512) return hipErrorInvalidValue;
+  if (pl.n_splits > 0 && pl.part == nullptr) return hipErrorInvalidValue;
   hipError_t e = zero(static_cast<C*>(V), pl.n_basis * nrhs, s);
-  if (e != hipSuccess || pl.n_items == 0) return e;
+  if (e != hipSuccess || pl.n_units == 0) return e;
   TFMM_NT_SWITCH(threads,
-                 hipLaunchKernelGGL((tucker_dis_kernel<T, NT>), dim3(pl.n_items, nrhs), dim3(NT),
+                 hipLaunchKernelGGL((tucker_dis_kernel<T, NT>), dim3(pl.n_units, nrhs), dim3(NT),
                                     Lds<T>(pl.mx).dis_bytes(), s, static_cast<const C*>(pl.factors), pl.items,
-                                    pl.order, pl.mx, n_theta, n_phi, nrhs, static_cast<const C*>(G),
-                                    static_cast<C*>(V)))
-  return hipGetLastError();
+                                    pl.units, pl.splits, pl.order, pl.mx, n_theta, n_phi, nrhs,
+                                    static_cast<const C*>(G), static_cast<C*>(V), static_cast<C*>(pl.part),
+                                    pl.part_stride))
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finish<T>(pl, threads, 0, pl.n_splits, n_theta, n_phi, nrhs, nullptr, V, s);
 }
 
 template <typename T>
@@ -552,14 +667,18 @@ hipError_t launch_tucker_pass(const TuckPlan& pl, int threads, int n_theta, int 
                               void* F, const void* G, void* V, hipStream_t s) {
   using C = typename Tr<T>::c;
   if (threads != 128 && threads != 256 && threads != 512) return hipErrorInvalidValue;
+  if (pl.n_splits > 0 && pl.part == nullptr) return hipErrorInvalidValue;
   hipError_t e = zero(static_cast<C*>(V), pl.n_basis * nrhs, s);
-  if (e != hipSuccess || pl.n_items == 0) return e;
+  if (e != hipSuccess || pl.n_units == 0) return e;
   TFMM_NT_SWITCH(threads,
-                 hipLaunchKernelGGL((tucker_pass_kernel<T, NT>), dim3(2 * pl.n_items, nrhs), dim3(NT),
-                                    Lds<T>(pl.mx).bytes(), s, static_cast<const C*>(pl.factors), pl.items,
-                                    pl.pass_list, pl.mx, n_theta, n_phi, nrhs, static_cast<const C*>(x),
-                                    static_cast<C*>(F), static_cast<const C*>(G), static_cast<C*>(V)))
-  return hipGetLastError();
+                 hipLaunchKernelGGL((tucker_pass_kernel<T, NT>), dim3(2 * pl.n_units, nrhs), dim3(NT),
+                                    Lds<T>(pl.mx).bytes(), s, static_cast<const C*>(pl.factors), pl.items, pl.units,
+                                    pl.splits, pl.pass_list, pl.mx, n_theta, n_phi, nrhs, static_cast<const C*>(x),
+                                    static_cast<C*>(F), static_cast<const C*>(G), static_cast<C*>(V),
+                                    static_cast<C*>(pl.part), pl.part_stride))
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finish<T>(pl, threads, pl.n_splits, pl.n_splits, n_theta, n_phi, nrhs, F, V, s);
 }
 
 template size_t tucker_lds_bytes<float>(const TuckMax&);

@@ -532,3 +532,56 @@ def test_saved_handle_computes_the_same(tmp_path):
             T.fmm_tucker_destroy(h)
         T.fmm_geometry_destroy(g)
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("split", [1, 700, 5000])
+@pytest.mark.parametrize("prec,nrhs", [(T.FMM_C128, 1), (T.FMM_C64, 1), (T.FMM_C128, 3), (T.FMM_C64, 2)],
+                         ids=["c128-1", "c64-1", "c128-3", "c64-2"])
+def test_split_items(prec, nrhs, split, monkeypatch):
+    """Items split into row blocks over several workgroups (forced at upload with a
+    small split size; 1 gives blocks of four rows) against the oracle; the pass equals
+    the separate stages bit for bit, and graph replays repeat it.  Half the groups are
+    in truncated-SVD form."""
+    import torch
+    monkeypatch.setenv("TUCKFMM_SPLIT_ELEMS", str(split))
+    lay = ragged_layout()
+    banner("split items prec=%d nrhs=%d split=%d" % (prec, nrhs, split))
+    gen = random_tucker(lay, 80, "random")
+    svd = svd_as_tucker(lay, random_svd(lay, 81, "full"))
+    tuck = [gen[g] if g % 2 else svd[g] for g in range(lay.n_groups)]
+    rng = synth.rng(82)
+    shp = (nrhs,) if nrhs > 1 else ()
+    x = synth.complex_normal(rng, (lay.n_basis,) + shp)
+    gin = synth.complex_normal(rng, (lay.n_groups, 2, lay.n_dir) + shp)
+    f_ref, v_ref = oracle_tucker(lay, tuck, x, gin)
+    h = make_handle(lay, tuck)
+    try:
+        _, nbytes = T.fmm_tucker_storage_bytes(h, prec)
+        ar = arena(nbytes)
+        T.fmm_tucker_upload(h, prec, ar)
+        xd, gd = dev(x, CDT[prec]), dev(gin, CDT[prec])
+        F1 = dev(np.zeros(f_ref.shape, CDT[prec]))
+        V1 = dev(np.zeros(v_ref.shape, CDT[prec]))
+        T.fmm_tucker_aggregate(h, prec, nrhs, xd, F1)
+        T.fmm_tucker_disaggregate(h, prec, nrhs, gd, V1)
+        F1, V1 = host(F1), host(V1)
+        tol = TOL[prec]
+        assert max_rel(F1, f_ref) < tol and l2_rel(F1, f_ref) < tol
+        assert max_rel(V1, v_ref) < tol and l2_rel(V1, v_ref) < tol
+        F = dev(np.zeros(f_ref.shape, CDT[prec]))
+        V = dev(np.zeros(v_ref.shape, CDT[prec]))
+        T.fmm_tucker_pass(h, prec, nrhs, xd, F, gd, V)
+        assert np.array_equal(host(F), F1) and np.array_equal(host(V), V1)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            T.fmm_graph_capture(h, prec, nrhs, xd, F, gd, V, s)
+        torch.cuda.synchronize()
+        for _ in range(2):
+            F.zero_()
+            V.zero_()
+            torch.cuda.synchronize()
+            T.fmm_graph_launch(h, s)
+            s.synchronize()
+            assert np.array_equal(host(F), F1) and np.array_equal(host(V), V1)
+    finally:
+        T.fmm_tucker_destroy(h)
