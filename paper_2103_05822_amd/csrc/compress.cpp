@@ -9,9 +9,15 @@
 //   2. their Hermitian eigendecompositions with rocSOLVER ZHEEVD: eigenvectors are
 //      the left singular vectors of the unfoldings, eigenvalues the squared
 //      singular values;
-//   3. per mode, the smallest rank whose discarded tail satisfies
-//      sum_{i>=r} s_i^2 <= gamma^2/3 ||A||_F^2 (host, FP64);
-//   4. the core C = A x_3 U^beta* x_1 U^theta* x_2 U^phi* with three ZGEMMs.
+//   3. per mode, the energy the tensor keeps along every eigenvector, ||u_i^H A_(p)||^2,
+//      from the projections themselves (a ZGEMM and a reduction): the Gram
+//      eigenvalues carry absolute errors near eps s_max^2 each, which summed over a
+//      long tail would swamp the threshold at small gamma, while the projected
+//      energies are sums of squares of accurately computed entries;
+//   4. per mode, the smallest rank whose discarded tail satisfies
+//      sum_{i>=r} e_i <= gamma^2/3 ||A||_F^2 (host, FP64), which bounds the mode's
+//      projection error exactly;
+//   5. the core C = A x_3 U^beta* x_1 U^theta* x_2 U^phi* with three ZGEMMs.
 // The eigensolver is latency-bound for these sizes, so tensors are spread over
 // several worker threads, each with its own stream, rocBLAS handle and workspace.
 #include <rocblas/rocblas.h>
@@ -100,6 +106,32 @@ struct Job {
 
 std::string hip_msg(const char* what, hipError_t e) { return std::string(what) + ": " + hipGetErrorString(e); }
 
+// The FP64 scratch of one worker (buf[4]): eigenvalues, eigensolver work, the
+// projected energies (each nbm + nt + np doubles: basis, theta, phi modes) and the
+// eigensolver's three info words.
+struct Scalars {
+  double *lb, *lt, *lp, *ework, *eb, *et, *ep;
+  rocblas_int* info;
+  Scalars(void* buf, int nbm, int nt, int np) {
+    lb = static_cast<double*>(buf);
+    lt = lb + nbm;
+    lp = lt + nt;
+    ework = lp + np;
+    eb = ework + nbm + nt + np;
+    et = eb + nbm;
+    ep = et + nt;
+    info = reinterpret_cast<rocblas_int*>(ep + np);
+  }
+  static size_t bytes(int nbm, int nt, int np) { return sizeof(double) * 3 * ((size_t)nbm + nt + np) + 64; }
+};
+
+// Reversed copy: ascending eigenvalue order -> descending.
+std::vector<double> reversed(const double* a, int n) {
+  std::vector<double> v(n);
+  for (int i = 0; i < n; ++i) v[i] = a[n - 1 - i];
+  return v;
+}
+
 // Truncated SVD of tensor t (basis mode only): U^beta from the basis-mode Gram matrix,
 // rank rule sqrt(sum_{i>=r} s_i^2) <= gamma ||A||_F, W = A conj(U^beta) (N_dir x r_beta).
 // Stored as a Tucker item with identity angular factors and core W.
@@ -112,11 +144,12 @@ std::string decompose_svd(const Job& J, Worker& w, int t) {
   using Z = rocblas_double_complex;
   Z* slab = static_cast<Z*>(w.buf[0]);
   Z* gb = static_cast<Z*>(w.buf[1]);
-  double* lb = static_cast<double*>(w.buf[4]);
+  const Scalars sc(w.buf[4], J.nb_max, nt, np);
+  double* lb = sc.lb;
   Z* vb = static_cast<Z*>(w.buf[6]);
   Z* y = static_cast<Z*>(w.buf[7]);
-  double* ework = lb + J.nb_max + nt + np;
-  rocblas_int* info = reinterpret_cast<rocblas_int*>(ework + J.nb_max + nt + np);
+  double* ework = sc.ework;
+  rocblas_int* info = sc.info;
 
   hipError_t he = launch_gather_slab(J.farfield, row0, nb, alpha, nt, np, slab, nullptr, w.s);
   if (he != hipSuccess) return hip_msg("gather kernel", he);
@@ -126,23 +159,25 @@ std::string decompose_svd(const Job& J, Worker& w, int t) {
   if (bs != rocblas_status_success) return std::string("zherk: ") + rocblas_status_to_string(bs);
   bs = rocsolver_zheevd(w.h, rocblas_evect_original, rocblas_fill_upper, nb, gb, nb, lb, ework, info);
   if (bs != rocblas_status_success) return std::string("zheevd: ") + rocblas_status_to_string(bs);
-  std::vector<double> lam_h(nb);
+  const Z cone = {1.0, 0.0}, czero = {0.0, 0.0};
+  // energy along every eigenvector: column norms of A^T conj(U^beta) over all columns
+  bs = rocblas_zgemm(w.h, rocblas_operation_none, rocblas_operation_none, nd, nb, nb, &cone, slab, nd, gb, nb,
+                     &czero, y, nd);
+  if (bs != rocblas_status_success) return std::string("energy projection: ") + rocblas_status_to_string(bs);
+  if ((he = launch_strided_energy(y, nb, nd, nd, 1, sc.eb, w.s)) != hipSuccess) return hip_msg("energy kernel", he);
+  std::vector<double> en_h(nb);
   rocblas_int info_h = 0;
-  if ((he = hipMemcpyAsync(lam_h.data(), lb, sizeof(double) * nb, hipMemcpyDeviceToHost, w.s)) != hipSuccess ||
+  if ((he = hipMemcpyAsync(en_h.data(), sc.eb, sizeof(double) * nb, hipMemcpyDeviceToHost, w.s)) != hipSuccess ||
       (he = hipMemcpyAsync(&info_h, info, sizeof(info_h), hipMemcpyDeviceToHost, w.s)) != hipSuccess ||
       (he = hipStreamSynchronize(w.s)) != hipSuccess)
-    return hip_msg("eigenvalue copy", he);
+    return hip_msg("energy copy", he);
   if (info_h != 0) return "NUMERIC:eigensolver did not converge";
-  std::vector<double> eb(nb);
+  const std::vector<double> eb = reversed(en_h.data(), nb);
   double norm2 = 0.0;
-  for (int i = 0; i < nb; ++i) {
-    eb[i] = lam_h[nb - 1 - i];
-    if (!std::isfinite(eb[i])) return "NUMERIC:non-finite far-field values";
-    norm2 += std::max(eb[i], 0.0);
-  }
+  for (double v : eb) norm2 += v;
+  if (!std::isfinite(norm2)) return "NUMERIC:non-finite far-field values";
   const int rb = truncation_rank(eb, J.gamma * J.gamma * norm2);
   if ((he = launch_select_cols_rev(gb, nb, rb, vb, w.s)) != hipSuccess) return hip_msg("column select kernel", he);
-  const Z cone = {1.0, 0.0}, czero = {0.0, 0.0};
   // W (nd x rb) = A conj(U^beta): as in the HOSVD, the Gram eigenvectors are conj(U^beta)
   bs = rocblas_zgemm(w.h, rocblas_operation_none, rocblas_operation_none, nd, rb, nb, &cone, slab, nd, vb, nb,
                      &czero, y, nd);
@@ -185,18 +220,15 @@ std::string decompose(const Job& J, Worker& w, int t) {
   Z* gb = static_cast<Z*>(w.buf[1]);
   Z* gt = static_cast<Z*>(w.buf[2]);
   Z* gp = static_cast<Z*>(w.buf[3]);
-  double* lam = static_cast<double*>(w.buf[4]);
+  const Scalars sc(w.buf[4], J.nb_max, nt, np);
   Z* part = static_cast<Z*>(w.buf[5]);
   Z* vb = static_cast<Z*>(w.buf[6]);
   Z* y = static_cast<Z*>(w.buf[7]);
   Z* z = static_cast<Z*>(w.buf[8]);
   Z* ut = gt + (size_t)nt * nt;  // selected columns live after each Gram matrix
   Z* up = gp + (size_t)np * np;
-  double* lb = lam;
-  double* lt = lb + J.nb_max;
-  double* lp = lt + nt;
-  double* ework = lp + np;
-  rocblas_int* info = reinterpret_cast<rocblas_int*>(ework + J.nb_max + nt + np);
+  double *lb = sc.lb, *lt = sc.lt, *lp = sc.lp, *ework = sc.ework;
+  rocblas_int* info = sc.info;
 
   hipError_t he = launch_gather_slab(J.farfield, row0, nb, alpha, nt, np, slab, nullptr, w.s);
   if (he != hipSuccess) return hip_msg("gather kernel", he);
@@ -213,27 +245,39 @@ std::string decompose(const Job& J, Worker& w, int t) {
     bs = rocsolver_zheevd(w.h, rocblas_evect_original, rocblas_fill_upper, np, gp, np, lp, ework, info + 2);
   if (bs != rocblas_status_success) return std::string("zheevd: ") + rocblas_status_to_string(bs);
 
-  std::vector<double> lam_h((size_t)J.nb_max + nt + np);
+  // energy along every eigenvector of each mode, from the projections:
+  //   basis: column norms of Y = A^T conj(U^beta) (all columns);
+  //   theta: row norms of U^theta^H S_b over all b;  phi: row norms of U^phi^H S_b^T
+  const Z cone = {1.0, 0.0}, czero = {0.0, 0.0};
+  bs = rocblas_zgemm(w.h, rocblas_operation_none, rocblas_operation_none, nd, nb, nb, &cone, slab, nd, gb, nb,
+                     &czero, y, nd);
+  if (bs != rocblas_status_success) return std::string("energy projection: ") + rocblas_status_to_string(bs);
+  if ((he = launch_strided_energy(y, nb, nd, nd, 1, sc.eb, w.s)) != hipSuccess) return hip_msg("energy kernel", he);
+  bs = rocblas_zgemm_strided_batched(w.h, rocblas_operation_conjugate_transpose, rocblas_operation_transpose, nt, np,
+                                     nt, &cone, gt, nt, 0, slab, np, nd, &czero, z, nt, (rocblas_stride)nt * np, nb);
+  if (bs != rocblas_status_success) return std::string("energy projection: ") + rocblas_status_to_string(bs);
+  if ((he = launch_strided_energy(z, nt, 1, (int64_t)np * nb, nt, sc.et, w.s)) != hipSuccess)
+    return hip_msg("energy kernel", he);
+  bs = rocblas_zgemm_strided_batched(w.h, rocblas_operation_conjugate_transpose, rocblas_operation_none, np, nt, np,
+                                     &cone, gp, np, 0, slab, np, nd, &czero, z, np, (rocblas_stride)np * nt, nb);
+  if (bs != rocblas_status_success) return std::string("energy projection: ") + rocblas_status_to_string(bs);
+  if ((he = launch_strided_energy(z, np, 1, (int64_t)nt * nb, np, sc.ep, w.s)) != hipSuccess)
+    return hip_msg("energy kernel", he);
+
+  std::vector<double> en_h((size_t)J.nb_max + nt + np);
   rocblas_int info_h[3];
-  if ((he = hipMemcpyAsync(lam_h.data(), lam, sizeof(double) * lam_h.size(), hipMemcpyDeviceToHost, w.s)) !=
+  if ((he = hipMemcpyAsync(en_h.data(), sc.eb, sizeof(double) * en_h.size(), hipMemcpyDeviceToHost, w.s)) !=
           hipSuccess ||
       (he = hipMemcpyAsync(info_h, info, sizeof(info_h), hipMemcpyDeviceToHost, w.s)) != hipSuccess ||
       (he = hipStreamSynchronize(w.s)) != hipSuccess)
-    return hip_msg("eigenvalue copy", he);
+    return hip_msg("energy copy", he);
   if (info_h[0] != 0 || info_h[1] != 0 || info_h[2] != 0) return "NUMERIC:eigensolver did not converge";
-  auto desc = [](const double* a, int n) {
-    std::vector<double> v(n);
-    for (int i = 0; i < n; ++i) v[i] = a[n - 1 - i];
-    return v;
-  };
-  const std::vector<double> eb = desc(lam_h.data(), nb);
-  const std::vector<double> et = desc(lam_h.data() + J.nb_max, nt);
-  const std::vector<double> ep = desc(lam_h.data() + J.nb_max + nt, np);
+  const std::vector<double> eb = reversed(en_h.data(), nb);
+  const std::vector<double> et = reversed(en_h.data() + J.nb_max, nt);
+  const std::vector<double> ep = reversed(en_h.data() + J.nb_max + nt, np);
   double norm2 = 0.0;
-  for (double v : eb) {
-    if (!std::isfinite(v)) return "NUMERIC:non-finite far-field values";
-    norm2 += std::max(v, 0.0);
-  }
+  for (double v : eb) norm2 += v;
+  if (!std::isfinite(norm2)) return "NUMERIC:non-finite far-field values";
   const double thr2 = J.gamma * J.gamma / 3.0 * norm2;
   const int rb = truncation_rank(eb, thr2);
   const int rt = truncation_rank(et, thr2);
@@ -243,7 +287,6 @@ std::string decompose(const Job& J, Worker& w, int t) {
       (he = launch_select_cols_rev(gt, nt, rt, ut, w.s)) != hipSuccess ||
       (he = launch_select_cols_rev(gp, np, rp, up, w.s)) != hipSuccess)
     return hip_msg("column select kernel", he);
-  const Z cone = {1.0, 0.0}, czero = {0.0, 0.0};
   // Y (nd x rb) = A^T conj(U^beta); the eigenvectors of conj(A A^H) are conj(U^beta)
   bs = rocblas_zgemm(w.h, rocblas_operation_none, rocblas_operation_none, nd, rb, nb, &cone, slab, nd, vb, nb,
                      &czero, y, nd);
@@ -304,7 +347,7 @@ std::string setup_worker(Worker& w, const Job& J, int device) {
       cz * nbm * nbm,                                              // basis-mode Gram / eigenvectors
       cz * (size_t)nt * nt * 2,                                    // theta Gram + selected columns
       cz * (size_t)np * np * 2,                                    // phi Gram + selected columns
-      sizeof(double) * 2 * (nbm + nt + np) + 64,                   // eigenvalues, work, info
+      Scalars::bytes((int)nbm, nt, np),                            // eigenvalues, work, energies, info
       cz * (size_t)mode_gram_chunks(J.nb_max) * (nt * nt + np * np),  // Gram partials
       cz * nbm * nbm,                                              // selected basis-mode columns
       cz * (size_t)nd * nbm,                                       // Y

@@ -52,6 +52,9 @@ int mode_gram_chunks(int nb);
 hipError_t launch_mode_gram(const void* slab, int nb, int nt, int np, void* part, void* gt, void* gp,
                             hipStream_t s);
 hipError_t launch_select_cols_rev(const void* src, int n, int r, void* dst, hipStream_t s);
+// out[k] = sum_l |a[k sk + l sl]|^2, k < K, l < L (complex128 a, FP64 sums).
+hipError_t launch_strided_energy(const void* a, int K, int64_t sk, int64_t L, int64_t sl, double* out,
+                                 hipStream_t s);
 hipError_t launch_gather_slab(const void* farfield, int64_t row0, int nb, int alpha, int n_theta, int n_phi,
                               void* out_tp, void* out_pt, hipStream_t s);
 

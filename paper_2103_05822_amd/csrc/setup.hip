@@ -73,6 +73,26 @@ __global__ __launch_bounds__(256) void select_cols_rev_kernel(const double2* __r
   }
 }
 
+// out[k] = sum_l |a[k sk + l sl]|^2 for k < K, l < L (FP64; one workgroup per k):
+// the energy a tensor keeps along each candidate factor column.
+__global__ __launch_bounds__(256) void strided_energy_kernel(const double2* __restrict__ a, int64_t sk, int64_t L,
+                                                             int64_t sl, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int64_t k = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t l = threadIdx.x; l < L; l += 256) {
+    const double2 v = a[k * sk + l * sl];
+    acc += v.x * v.x + v.y * v.y;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[k] = red[0];
+}
+
 // Gram matrices of the theta and phi unfoldings of one tensor held as a slab
 // s [nb][nt][np] (one n_theta x n_phi block S_n per basis function):
 //   Gt = sum_n S_n S_n^H  (nt x nt),   Gp = sum_n S_n^T conj(S_n)  (np x np).
@@ -196,6 +216,14 @@ hipError_t launch_select_cols_rev(const void* src, int n, int r, void* dst, hipS
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(select_cols_rev_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
                      static_cast<const double2*>(src), n, r, static_cast<double2*>(dst));
+  return hipGetLastError();
+}
+
+hipError_t launch_strided_energy(const void* a, int K, int64_t sk, int64_t L, int64_t sl, double* out,
+                                 hipStream_t s) {
+  if (K <= 0) return hipSuccess;
+  hipLaunchKernelGGL(strided_energy_kernel, dim3((unsigned)K), dim3(256), 0, s, static_cast<const double2*>(a), sk,
+                     L, sl, out);
   return hipGetLastError();
 }
 
