@@ -154,24 +154,33 @@ std::string decompose_svd(const Job& J, Worker& w, int t) {
   hipError_t he = launch_gather_slab(J.farfield, row0, nb, alpha, nt, np, slab, nullptr, w.s);
   if (he != hipSuccess) return hip_msg("gather kernel", he);
   const double one = 1.0, zero = 0.0;
-  rocblas_status bs = rocblas_zherk(w.h, rocblas_fill_upper, rocblas_operation_conjugate_transpose, nb, nd, &one,
-                                    slab, nd, &zero, gb, nb);
-  if (bs != rocblas_status_success) return std::string("zherk: ") + rocblas_status_to_string(bs);
-  bs = rocsolver_zheevd(w.h, rocblas_evect_original, rocblas_fill_upper, nb, gb, nb, lb, ework, info);
-  if (bs != rocblas_status_success) return std::string("zheevd: ") + rocblas_status_to_string(bs);
   const Z cone = {1.0, 0.0}, czero = {0.0, 0.0};
-  // energy along every eigenvector: column norms of A^T conj(U^beta) over all columns
-  bs = rocblas_zgemm(w.h, rocblas_operation_none, rocblas_operation_none, nd, nb, nb, &cone, slab, nd, gb, nb,
-                     &czero, y, nd);
-  if (bs != rocblas_status_success) return std::string("energy projection: ") + rocblas_status_to_string(bs);
-  if ((he = launch_strided_energy(y, nb, nd, nd, 1, sc.eb, w.s)) != hipSuccess) return hip_msg("energy kernel", he);
+  rocblas_status bs = rocblas_status_success;
   std::vector<double> en_h(nb);
-  rocblas_int info_h = 0;
-  if ((he = hipMemcpyAsync(en_h.data(), sc.eb, sizeof(double) * nb, hipMemcpyDeviceToHost, w.s)) != hipSuccess ||
-      (he = hipMemcpyAsync(&info_h, info, sizeof(info_h), hipMemcpyDeviceToHost, w.s)) != hipSuccess ||
-      (he = hipStreamSynchronize(w.s)) != hipSuccess)
-    return hip_msg("energy copy", he);
-  if (info_h != 0) return "NUMERIC:eigensolver did not converge";
+  // divide and conquer first, QR iteration if the eigenvectors come back non-finite
+  for (int attempt = 0;; ++attempt) {
+    bs = rocblas_zherk(w.h, rocblas_fill_upper, rocblas_operation_conjugate_transpose, nb, nd, &one, slab, nd, &zero,
+                       gb, nb);
+    if (bs != rocblas_status_success) return std::string("zherk: ") + rocblas_status_to_string(bs);
+    bs = attempt ? rocsolver_zheev(w.h, rocblas_evect_original, rocblas_fill_upper, nb, gb, nb, lb, ework, info)
+                 : rocsolver_zheevd(w.h, rocblas_evect_original, rocblas_fill_upper, nb, gb, nb, lb, ework, info);
+    if (bs != rocblas_status_success) return std::string("eigensolver: ") + rocblas_status_to_string(bs);
+    // energy along every eigenvector: column norms of A^T conj(U^beta) over all columns
+    bs = rocblas_zgemm(w.h, rocblas_operation_none, rocblas_operation_none, nd, nb, nb, &cone, slab, nd, gb, nb,
+                       &czero, y, nd);
+    if (bs != rocblas_status_success) return std::string("energy projection: ") + rocblas_status_to_string(bs);
+    if ((he = launch_strided_energy(y, nb, nd, nd, 1, sc.eb, w.s)) != hipSuccess) return hip_msg("energy kernel", he);
+    rocblas_int info_h = 0;
+    if ((he = hipMemcpyAsync(en_h.data(), sc.eb, sizeof(double) * nb, hipMemcpyDeviceToHost, w.s)) != hipSuccess ||
+        (he = hipMemcpyAsync(&info_h, info, sizeof(info_h), hipMemcpyDeviceToHost, w.s)) != hipSuccess ||
+        (he = hipStreamSynchronize(w.s)) != hipSuccess)
+      return hip_msg("energy copy", he);
+    if (info_h != 0) return "NUMERIC:eigensolver did not converge";
+    bool ok = true;
+    for (double v : en_h) ok = ok && std::isfinite(v);
+    if (ok) break;
+    if (attempt > 0) return "NUMERIC:non-finite far-field values or eigenvectors";
+  }
   const std::vector<double> eb = reversed(en_h.data(), nb);
   double norm2 = 0.0;
   for (double v : eb) norm2 += v;
@@ -233,45 +242,71 @@ std::string decompose(const Job& J, Worker& w, int t) {
   hipError_t he = launch_gather_slab(J.farfield, row0, nb, alpha, nt, np, slab, nullptr, w.s);
   if (he != hipSuccess) return hip_msg("gather kernel", he);
   const double one = 1.0, zero = 0.0;
-  rocblas_status bs = rocblas_zherk(w.h, rocblas_fill_upper, rocblas_operation_conjugate_transpose, nb, nd, &one,
-                                    slab, nd, &zero, gb, nb);
-  if (bs != rocblas_status_success) return std::string("zherk: ") + rocblas_status_to_string(bs);
-  he = launch_mode_gram(slab, nb, nt, np, part, gt, gp, w.s);
-  if (he != hipSuccess) return hip_msg("mode_gram kernel", he);
-  bs = rocsolver_zheevd(w.h, rocblas_evect_original, rocblas_fill_upper, nb, gb, nb, lb, ework, info);
-  if (bs == rocblas_status_success)
-    bs = rocsolver_zheevd(w.h, rocblas_evect_original, rocblas_fill_upper, nt, gt, nt, lt, ework, info + 1);
-  if (bs == rocblas_status_success)
-    bs = rocsolver_zheevd(w.h, rocblas_evect_original, rocblas_fill_upper, np, gp, np, lp, ework, info + 2);
-  if (bs != rocblas_status_success) return std::string("zheevd: ") + rocblas_status_to_string(bs);
-
-  // energy along every eigenvector of each mode, from the projections:
-  //   basis: column norms of Y = A^T conj(U^beta) (all columns);
-  //   theta: row norms of U^theta^H S_b over all b;  phi: row norms of U^phi^H S_b^T
   const Z cone = {1.0, 0.0}, czero = {0.0, 0.0};
-  bs = rocblas_zgemm(w.h, rocblas_operation_none, rocblas_operation_none, nd, nb, nb, &cone, slab, nd, gb, nb,
-                     &czero, y, nd);
-  if (bs != rocblas_status_success) return std::string("energy projection: ") + rocblas_status_to_string(bs);
-  if ((he = launch_strided_energy(y, nb, nd, nd, 1, sc.eb, w.s)) != hipSuccess) return hip_msg("energy kernel", he);
-  bs = rocblas_zgemm_strided_batched(w.h, rocblas_operation_conjugate_transpose, rocblas_operation_transpose, nt, np,
-                                     nt, &cone, gt, nt, 0, slab, np, nd, &czero, z, nt, (rocblas_stride)nt * np, nb);
-  if (bs != rocblas_status_success) return std::string("energy projection: ") + rocblas_status_to_string(bs);
-  if ((he = launch_strided_energy(z, nt, 1, (int64_t)np * nb, nt, sc.et, w.s)) != hipSuccess)
-    return hip_msg("energy kernel", he);
-  bs = rocblas_zgemm_strided_batched(w.h, rocblas_operation_conjugate_transpose, rocblas_operation_none, np, nt, np,
-                                     &cone, gp, np, 0, slab, np, nd, &czero, z, np, (rocblas_stride)np * nt, nb);
-  if (bs != rocblas_status_success) return std::string("energy projection: ") + rocblas_status_to_string(bs);
-  if ((he = launch_strided_energy(z, np, 1, (int64_t)nt * nb, np, sc.ep, w.s)) != hipSuccess)
-    return hip_msg("energy kernel", he);
-
+  rocblas_status bs = rocblas_status_success;
   std::vector<double> en_h((size_t)J.nb_max + nt + np);
-  rocblas_int info_h[3];
-  if ((he = hipMemcpyAsync(en_h.data(), sc.eb, sizeof(double) * en_h.size(), hipMemcpyDeviceToHost, w.s)) !=
-          hipSuccess ||
-      (he = hipMemcpyAsync(info_h, info, sizeof(info_h), hipMemcpyDeviceToHost, w.s)) != hipSuccess ||
-      (he = hipStreamSynchronize(w.s)) != hipSuccess)
-    return hip_msg("energy copy", he);
-  if (info_h[0] != 0 || info_h[1] != 0 || info_h[2] != 0) return "NUMERIC:eigensolver did not converge";
+  // Two attempts: the divide-and-conquer eigensolver, then, for a mode whose
+  // eigenvectors came back non-finite (seen with an exactly zero row in the
+  // unfolding, e.g. the phi pattern of a plate at phi = 0), QR iteration.
+  bool qr_b = false, qr_ang = false;
+  for (int attempt = 0;; ++attempt) {
+    const bool do_b = attempt == 0 || qr_b, do_ang = attempt == 0 || qr_ang;
+    if (do_b) {
+      bs = rocblas_zherk(w.h, rocblas_fill_upper, rocblas_operation_conjugate_transpose, nb, nd, &one, slab, nd,
+                         &zero, gb, nb);
+      if (bs != rocblas_status_success) return std::string("zherk: ") + rocblas_status_to_string(bs);
+      bs = qr_b ? rocsolver_zheev(w.h, rocblas_evect_original, rocblas_fill_upper, nb, gb, nb, lb, ework, info)
+                : rocsolver_zheevd(w.h, rocblas_evect_original, rocblas_fill_upper, nb, gb, nb, lb, ework, info);
+      if (bs != rocblas_status_success) return std::string("eigensolver: ") + rocblas_status_to_string(bs);
+    }
+    if (do_ang) {
+      if ((he = launch_mode_gram(slab, nb, nt, np, part, gt, gp, w.s)) != hipSuccess)
+        return hip_msg("mode_gram kernel", he);
+      auto heev = qr_ang ? rocsolver_zheev : rocsolver_zheevd;
+      bs = heev(w.h, rocblas_evect_original, rocblas_fill_upper, nt, gt, nt, lt, ework, info + 1);
+      if (bs == rocblas_status_success)
+        bs = heev(w.h, rocblas_evect_original, rocblas_fill_upper, np, gp, np, lp, ework, info + 2);
+      if (bs != rocblas_status_success) return std::string("eigensolver: ") + rocblas_status_to_string(bs);
+    }
+
+    // energy along every eigenvector of each mode, from the projections:
+    //   basis: column norms of Y = A^T conj(U^beta) (all columns);
+    //   theta: row norms of U^theta^H S_b over all b;  phi: row norms of U^phi^H S_b^T
+    bs = rocblas_zgemm(w.h, rocblas_operation_none, rocblas_operation_none, nd, nb, nb, &cone, slab, nd, gb, nb,
+                       &czero, y, nd);
+    if (bs != rocblas_status_success) return std::string("energy projection: ") + rocblas_status_to_string(bs);
+    if ((he = launch_strided_energy(y, nb, nd, nd, 1, sc.eb, w.s)) != hipSuccess) return hip_msg("energy kernel", he);
+    bs = rocblas_zgemm_strided_batched(w.h, rocblas_operation_conjugate_transpose, rocblas_operation_transpose, nt,
+                                       np, nt, &cone, gt, nt, 0, slab, np, nd, &czero, z, nt, (rocblas_stride)nt * np,
+                                       nb);
+    if (bs != rocblas_status_success) return std::string("energy projection: ") + rocblas_status_to_string(bs);
+    if ((he = launch_strided_energy(z, nt, 1, (int64_t)np * nb, nt, sc.et, w.s)) != hipSuccess)
+      return hip_msg("energy kernel", he);
+    bs = rocblas_zgemm_strided_batched(w.h, rocblas_operation_conjugate_transpose, rocblas_operation_none, np, nt, np,
+                                       &cone, gp, np, 0, slab, np, nd, &czero, z, np, (rocblas_stride)np * nt, nb);
+    if (bs != rocblas_status_success) return std::string("energy projection: ") + rocblas_status_to_string(bs);
+    if ((he = launch_strided_energy(z, np, 1, (int64_t)nt * nb, np, sc.ep, w.s)) != hipSuccess)
+      return hip_msg("energy kernel", he);
+
+    rocblas_int info_h[3];
+    if ((he = hipMemcpyAsync(en_h.data(), sc.eb, sizeof(double) * en_h.size(), hipMemcpyDeviceToHost, w.s)) !=
+            hipSuccess ||
+        (he = hipMemcpyAsync(info_h, info, sizeof(info_h), hipMemcpyDeviceToHost, w.s)) != hipSuccess ||
+        (he = hipStreamSynchronize(w.s)) != hipSuccess)
+      return hip_msg("energy copy", he);
+    if (info_h[0] != 0 || info_h[1] != 0 || info_h[2] != 0) return "NUMERIC:eigensolver did not converge";
+    auto finite = [&](size_t off, int n) {
+      for (int i = 0; i < n; ++i)
+        if (!std::isfinite(en_h[off + i])) return false;
+      return true;
+    };
+    const bool ok_b = finite(0, nb);
+    const bool ok_ang = finite(J.nb_max, nt) && finite((size_t)J.nb_max + nt, np);
+    if (ok_b && ok_ang) break;
+    if (attempt > 0) return "NUMERIC:non-finite far-field values or eigenvectors";
+    qr_b = !ok_b;
+    qr_ang = !ok_ang;
+  }
   const std::vector<double> eb = reversed(en_h.data(), nb);
   const std::vector<double> et = reversed(en_h.data() + J.nb_max, nt);
   const std::vector<double> ep = reversed(en_h.data() + J.nb_max + nt, np);

@@ -585,3 +585,43 @@ def test_split_items(prec, nrhs, split, monkeypatch):
             assert np.array_equal(host(F), F1) and np.array_equal(host(V), V1)
     finally:
         T.fmm_tucker_destroy(h)
+
+
+def test_compress_plate_with_a_zero_pattern_row():
+    """A flat box of the trihedral's y = 0 plate: its phi-polarised pattern is exactly
+    zero at phi = 0 (phi_hat . J = J_y = 0 there), so the phi unfolding has a zero row.
+    The divide-and-conquer eigensolver has returned non-finite eigenvectors for that
+    Gram matrix; the compressor must detect it, recompute, and match the oracle's
+    ranks with finite factors and the gamma bound."""
+    w = W.TRIHEDRAL
+    v, t = w.mesh()
+    P = geo.Problem(v, t, w.origin, w.box, w.boxes_per_axis, w.n_theta, w.n_phi)
+    g = int(np.nonzero((P.box_index == [1, 0, 1]).all(axis=1))[0][0])
+    banner("compress trihedral plate group %d" % g)
+    blk = ff.farfield_group(P, g)
+    assert np.all(blk[:, 1, :, 0] == 0)
+    nb = blk.shape[0]
+    lay = T.Layout(w.n_theta, w.n_phi, [0, nb])
+    gamma = 1e-6
+    h = T.fmm_farfield_compress(lay, dev(blk), 0, 1, gamma)
+    try:
+        ranks = T.fmm_tucker_ranks(h, 1)
+        facs = [T.fmm_tucker_export(h, 0, a, ranks[0, a], w.n_theta, w.n_phi, nb) for a in range(2)]
+        x = synth.complex_normal(synth.rng(15), nb)
+        _, nbytes = T.fmm_tucker_storage_bytes(h, T.FMM_C128)
+        ar = arena(nbytes)
+        T.fmm_tucker_upload(h, T.FMM_C128, ar)
+        F = dev(np.zeros((1, 2, P.n_dir), np.complex128))
+        T.fmm_tucker_aggregate(h, T.FMM_C128, 1, dev(x), F)
+        F = host(F)
+    finally:
+        T.fmm_tucker_destroy(h)
+    from oracle import hosvd as H
+    f_dense = pr.dense_aggregate(blk, x)
+    for a in range(2):
+        assert all(np.all(np.isfinite(f)) for f in facs[a])
+        c_ref, _, _ = H.hosvd(H.tensorize(blk, a), gamma)
+        assert np.all(np.abs(np.array(facs[a][0].shape) - np.array(c_ref.shape)) <= 1), (facs[a][0].shape,
+                                                                                         c_ref.shape)
+        bound = gamma * np.linalg.norm(blk[:, a]) * np.linalg.norm(x)
+        assert np.linalg.norm(F[0, a] - f_dense[a]) <= bound * (1 + 1e-6)
