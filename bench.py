@@ -466,6 +466,9 @@ def sweep(args, T, torch, synth, w):
                     pt["ms"][name + "_disagg"] = time_ms(torch, lambda: T.fmm_tucker_disaggregate(h, prec, 1, gg, VV))
                 else:
                     pt["ms"][name + "_pass_f32"] = time_ms(torch, lambda: T.fmm_tucker_pass(h, prec, 1, xx, FF, gg, VV))
+                if not (bool(torch.isfinite(torch.view_as_real(FF)).all()) and
+                        bool(torch.isfinite(torch.view_as_real(VV)).all())):
+                    raise SystemExit("sweep point %s: non-finite %s outputs" % (json.dumps(pt), name))
                 del ar
             T.fmm_tucker_destroy(h)
         m = pt["ms"]
