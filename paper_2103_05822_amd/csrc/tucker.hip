@@ -38,6 +38,26 @@ namespace {
 // parameter of every phase: one workgroup per item.
 constexpr int kColPacks = 2;  // column packs per thread per chunk in the axpy stages
 
+// U^beta^T and the core are read once per pass: non-temporal loads keep these
+// streams from displacing x, G, V and the work tables in the caches.
+template <typename P>
+struct NtVec;
+template <>
+struct NtVec<float4> {
+  typedef float v __attribute__((ext_vector_type(4)));
+};
+template <>
+struct NtVec<double2> {
+  typedef double v __attribute__((ext_vector_type(2)));
+};
+template <typename P>
+__device__ __forceinline__ P ldnt(const P* p) {
+  const auto v = __builtin_nontemporal_load(reinterpret_cast<const typename NtVec<P>::v*>(p));
+  P o;
+  __builtin_memcpy(&o, &v, sizeof(P));
+  return o;
+}
+
 // LDS regions (complex elements).
 // Aggregation:    r1 = x (n_beta), later t (r_theta r_phi);  r2 = y (r_beta), later
 //                 the angular intermediate.
@@ -81,8 +101,8 @@ __device__ __forceinline__ void wave_rowdots(const typename Tr<T>::c* rows, int 
       P u[4], w[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        u[i] = r[i][p];
-        w[i] = r[i][p + 64];
+        u[i] = ldnt(r[i] + p);
+        w[i] = ldnt(r[i] + p + 64);
       }
       const P v0 = vec[p], v1 = vec[p + 64];
 #pragma unroll
@@ -94,7 +114,7 @@ __device__ __forceinline__ void wave_rowdots(const typename Tr<T>::c* rows, int 
     if (p < npk) {
       P u[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) u[i] = r[i][p];
+      for (int i = 0; i < 4; ++i) u[i] = ldnt(r[i] + p);
       const P v0 = vec[p];
 #pragma unroll
       for (int i = 0; i < 4; ++i) pdot(a[i], u[i], v0);
@@ -111,11 +131,11 @@ __device__ __forceinline__ void wave_rowdots(const typename Tr<T>::c* rows, int 
     C a0 = czero<C>(), a1 = czero<C>();
     int p = lane;
     for (; p + 64 < npk; p += 128) {
-      const P u0 = r0[p], u1 = r0[p + 64];
+      const P u0 = ldnt(r0 + p), u1 = ldnt(r0 + p + 64);
       pdot(a0, u0, vec[p]);
       pdot(a1, u1, vec[p + 64]);
     }
-    if (p < npk) pdot(a0, r0[p], vec[p]);
+    if (p < npk) pdot(a0, ldnt(r0 + p), vec[p]);
     a0.x += a1.x;
     a0.y += a1.y;
     a0 = wave_sum(a0);
@@ -142,7 +162,7 @@ __device__ __forceinline__ void block_colaxpy(const typename Tr<T>::c* rows, int
     for (int i = 0; i < 4; ++i) {
       const P* r = reinterpret_cast<const P*>(rows + (int64_t)(b + i) * ld);
 #pragma unroll
-      for (int j = 0; j < kColPacks; ++j) u[i][j] = in[j] ? r[p0 + NT * j] : pzero<P>();
+      for (int j = 0; j < kColPacks; ++j) u[i][j] = in[j] ? ldnt(r + p0 + NT * j) : pzero<P>();
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -156,7 +176,7 @@ __device__ __forceinline__ void block_colaxpy(const typename Tr<T>::c* rows, int
     const C c = coef[b];
 #pragma unroll
     for (int j = 0; j < kColPacks; ++j)
-      if (in[j]) paxpy(acc[j], r[p0 + NT * j], c);
+      if (in[j]) paxpy(acc[j], ldnt(r + p0 + NT * j), c);
   }
 }
 
