@@ -94,10 +94,13 @@ struct ArenaPlan {
 // Bytes streamed by one item (U^beta and the core), the key of the work lists.
 double item_cost(const TuckItem& it) { return (double)it.rb * ((double)it.ld_ub + (double)it.ld_c); }
 
-// Items streaming more than this many elements run as blocks of their r_beta rows
-// on several workgroups, so that a layout of few large groups still spreads over
-// the whole GPU: at least kSplitMin elements per block, and no splitting while the
-// items already give about kSplitUnits blocks of that size.
+// A layout of few large groups leaves most of the GPU idle with one workgroup per
+// item (the trihedral at 2 lambda has 38 items).  Below kSplitBelow items, items
+// streaming more than max(kSplitMin, total / kSplitUnits) elements run as blocks of
+// their r_beta rows on several workgroups.  With more items splitting only adds
+// partial-sum traffic and a finishing launch: measured on MI355X, 196 items of the
+// 20-lambda sphere at 4-lambda boxes ran 1.49 ms unsplit and 1.91 ms split.
+constexpr int kSplitBelow = 128;
 constexpr double kSplitMin = 65536.0;
 constexpr double kSplitUnits = 512.0;
 constexpr int kSplitMinRows = 4;
@@ -107,6 +110,7 @@ double split_elems(const std::vector<TuckItem>& items) {
     const double v = std::atof(env);
     if (v >= 1.0) return v;
   }
+  if ((int)items.size() >= kSplitBelow) return 1e300;
   double total = 0.0;
   for (const TuckItem& it : items) total += item_cost(it);
   return std::max(kSplitMin, total / kSplitUnits);

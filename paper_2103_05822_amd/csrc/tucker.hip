@@ -39,7 +39,11 @@ namespace {
 constexpr int kColPacks = 2;  // column packs per thread per chunk in the axpy stages
 
 // U^beta^T and the core are read once per pass: non-temporal loads keep these
-// streams from displacing x, G, V and the work tables in the caches.
+// streams from displacing x, G, V and the work tables in the caches.  Measured on
+// MI355X they pay off for large items (5-7% on layouts with boxes of 2 lambda and
+// more) and cost about 4% on small ones (0.5 lambda boxes), so only the 256- and
+// 512-thread instantiations, which the workgroup-size rule picks for large items,
+// use them.
 template <typename P>
 struct NtVec;
 template <>
@@ -50,8 +54,9 @@ template <>
 struct NtVec<double2> {
   typedef double v __attribute__((ext_vector_type(2)));
 };
-template <typename P>
+template <bool kNt, typename P>
 __device__ __forceinline__ P ldnt(const P* p) {
+  if (!kNt) return *p;
   const auto v = __builtin_nontemporal_load(reinterpret_cast<const typename NtVec<P>::v*>(p));
   P o;
   __builtin_memcpy(&o, &v, sizeof(P));
@@ -82,7 +87,7 @@ struct Lds {
 // wavefront per row.  Rows are 16-byte aligned with npk packs each; vec is an LDS
 // pack array.  Four rows at a time, two packs per row per iteration: eight 16-byte
 // loads in flight per lane.
-template <typename T>
+template <typename T, bool kNt>
 __device__ __forceinline__ void wave_rowdots(const typename Tr<T>::c* rows, int ld, int first, int last,
                                              int step, const typename Tr<T>::pack* vec, int npk,
                                              typename Tr<T>::c* out, int lane) {
@@ -101,8 +106,8 @@ __device__ __forceinline__ void wave_rowdots(const typename Tr<T>::c* rows, int 
       P u[4], w[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        u[i] = ldnt(r[i] + p);
-        w[i] = ldnt(r[i] + p + 64);
+        u[i] = ldnt<kNt>(r[i] + p);
+        w[i] = ldnt<kNt>(r[i] + p + 64);
       }
       const P v0 = vec[p], v1 = vec[p + 64];
 #pragma unroll
@@ -114,7 +119,7 @@ __device__ __forceinline__ void wave_rowdots(const typename Tr<T>::c* rows, int 
     if (p < npk) {
       P u[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) u[i] = ldnt(r[i] + p);
+      for (int i = 0; i < 4; ++i) u[i] = ldnt<kNt>(r[i] + p);
       const P v0 = vec[p];
 #pragma unroll
       for (int i = 0; i < 4; ++i) pdot(a[i], u[i], v0);
@@ -131,11 +136,11 @@ __device__ __forceinline__ void wave_rowdots(const typename Tr<T>::c* rows, int 
     C a0 = czero<C>(), a1 = czero<C>();
     int p = lane;
     for (; p + 64 < npk; p += 128) {
-      const P u0 = ldnt(r0 + p), u1 = ldnt(r0 + p + 64);
+      const P u0 = ldnt<kNt>(r0 + p), u1 = ldnt<kNt>(r0 + p + 64);
       pdot(a0, u0, vec[p]);
       pdot(a1, u1, vec[p + 64]);
     }
-    if (p < npk) pdot(a0, ldnt(r0 + p), vec[p]);
+    if (p < npk) pdot(a0, ldnt<kNt>(r0 + p), vec[p]);
     a0.x += a1.x;
     a0.y += a1.y;
     a0 = wave_sum(a0);
@@ -151,6 +156,7 @@ __device__ __forceinline__ void block_colaxpy(const typename Tr<T>::c* rows, int
                                               typename Tr<T>::pack (&acc)[kColPacks]) {
   using C = typename Tr<T>::c;
   using P = typename Tr<T>::pack;
+  constexpr bool kNt = NT >= 256;
   const int p0 = base + tid;
   bool in[kColPacks];
 #pragma unroll
@@ -162,7 +168,7 @@ __device__ __forceinline__ void block_colaxpy(const typename Tr<T>::c* rows, int
     for (int i = 0; i < 4; ++i) {
       const P* r = reinterpret_cast<const P*>(rows + (int64_t)(b + i) * ld);
 #pragma unroll
-      for (int j = 0; j < kColPacks; ++j) u[i][j] = in[j] ? ldnt(r + p0 + NT * j) : pzero<P>();
+      for (int j = 0; j < kColPacks; ++j) u[i][j] = in[j] ? ldnt<kNt>(r + p0 + NT * j) : pzero<P>();
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -176,7 +182,7 @@ __device__ __forceinline__ void block_colaxpy(const typename Tr<T>::c* rows, int
     const C c = coef[b];
 #pragma unroll
     for (int j = 0; j < kColPacks; ++j)
-      if (in[j]) paxpy(acc[j], ldnt(r + p0 + NT * j), c);
+      if (in[j]) paxpy(acc[j], ldnt<kNt>(r + p0 + NT * j), c);
   }
 }
 
@@ -257,7 +263,7 @@ __device__ __forceinline__ void agg_stream(const typename Tr<T>::c* __restrict__
   __syncthreads();
 
   // y = U^beta^T x (rows b0 .. b1 - 1)
-  wave_rowdots<T>(fac + it.off_ubt, it.ld_ub, b0 + wave, b1, (NT / 64), reinterpret_cast<const P*>(xs), nbp / E,
+  wave_rowdots<T, (NT >= 256)>(fac + it.off_ubt, it.ld_ub, b0 + wave, b1, (NT / 64), reinterpret_cast<const P*>(xs), nbp / E,
                   ys, lane);
   __syncthreads();
 
@@ -385,7 +391,7 @@ __device__ __forceinline__ void dis_stream(const typename Tr<T>::c* __restrict__
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int Q = it.rt * it.rp;
   // s[b] = sum_q core[b][q] S[q]
-  wave_rowdots<T>(fac + it.off_core, it.ld_c, b0 + wave, b1, (NT / 64), reinterpret_cast<const P*>(S2),
+  wave_rowdots<T, (NT >= 256)>(fac + it.off_core, it.ld_c, b0 + wave, b1, (NT / 64), reinterpret_cast<const P*>(S2),
                   round_up(Q, E) / E, s3, lane);
   __syncthreads();
   // V[n] += conj(sum_b U^beta[n][b] s[b])
