@@ -413,16 +413,21 @@ __device__ __forceinline__ void mma_stage(const typename LdsOf<VARIANT>::type& L
 // One tile: column blocks n0 = tl.n0, tl.n0 + 64, ... below tl.n1, each a full K
 // sweep, walked as one pipeline over (block, K step).  LDS is single buffered: the
 // loads of the next step are issued before the current step's matrix-core work and
-// written to LDS after it.
-template <int VARIANT, bool AVEC>
+// written to LDS after it.  A wavefront whose 16 rows lie past the problem's M
+// (ACTIVE = false: the angular products have M = r_theta, r_phi, n_theta or n_phi,
+// often well below the 64-row tile) still loads, stores and meets every barrier, but
+// issues no matrix-core work, leaving the matrix cores to the other wavefronts.
+template <int VARIANT, bool AVEC, bool ACTIVE>
 __device__ __forceinline__ void run_tile(const CGemm& p, const CTile& tl, const float2* A, const float2* B, float2* Cp,
                                          typename LdsOf<VARIANT>::type& L) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int nsteps = (p.K + kKC - 1) / kKC;
 
   floatx4 acc[kNT];
+  if constexpr (ACTIVE) {
 #pragma unroll
-  for (int t = 0; t < kNT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < kNT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
   Walk wk;
   walk_init(p, A, B, tl.m0, tid, wk);
   walk_block(p, tl.n0, tid, wk);
@@ -444,18 +449,20 @@ __device__ __forceinline__ void run_tile(const CGemm& p, const CTile& tl, const 
         if (ns == 0) walk_block(p, nn0, tid, wk);
         load_stage<AVEC>(p, ns * kKC, wk, st);
       }
-      mma_stage<VARIANT>(L, w, lane, acc);
+      if constexpr (ACTIVE) mma_stage<VARIANT>(L, w, lane, acc);
       if (more) {
         __syncthreads();  // every wavefront is done reading the step
         store_stage<VARIANT>(p, st, L, tid);
         __syncthreads();
       }
     }
-    epilogue(p, Cp, tl.m0, n0, w, lane, acc);
+    if constexpr (ACTIVE) epilogue(p, Cp, tl.m0, n0, w, lane, acc);
     n0 += kBN;
     if (n0 >= tl.n1) break;
+    if constexpr (ACTIVE) {
 #pragma unroll
-    for (int t = 0; t < kNT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int t = 0; t < kNT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
   }
 }
 
@@ -469,11 +476,21 @@ __global__ __launch_bounds__(kMT) void cgemm_kernel(const CGemm* __restrict__ pr
   const float2* A = base_ptr(bases, p.abase);
   const float2* B = base_ptr(bases, p.bbase);
   float2* Cp = base_ptr(bases, p.cbase);
-  // 16-byte A loads: K-contiguous A with an even offset and row stride
-  if (p.lda_k == 1 && !((p.a | p.lda_m) & 1))
-    run_tile<VARIANT, true>(p, tl, A, B, Cp, L);
-  else
-    run_tile<VARIANT, false>(p, tl, A, B, Cp, L);
+  // 16-byte A loads: K-contiguous A with an even offset and row stride; the branch
+  // on the wavefront's rows is uniform per wavefront
+  const bool avec = p.lda_k == 1 && !((p.a | p.lda_m) & 1);
+  const bool active = tl.m0 + 16 * (int)(threadIdx.x >> 6) < p.M;
+  if (avec) {
+    if (active)
+      run_tile<VARIANT, true, true>(p, tl, A, B, Cp, L);
+    else
+      run_tile<VARIANT, true, false>(p, tl, A, B, Cp, L);
+  } else {
+    if (active)
+      run_tile<VARIANT, false, true>(p, tl, A, B, Cp, L);
+    else
+      run_tile<VARIANT, false, false>(p, tl, A, B, Cp, L);
+  }
 }
 
 template <typename C>
