@@ -1,9 +1,11 @@
-"""GPU parity at the benchmark's full size: the 30-lambda sphere (939,870 RWG, 1034
-groups, 38 x 75 grid, gamma = 1e-6) in the configuration bench.py times -- far-fields
-filled and compressed on the GPU group chunk by group chunk, the FP32 pass replayed
-from a captured graph, the BF16x2 matrix-core pass at 64 right-hand sides -- checked
-against the oracle's dense FP64 products on sampled groups (the largest and three
-seeded draws), which the oracle computes one group at a time.
+"""GPU parity at full size, in the configurations bench.py times: the 30-lambda
+sphere (939,870 RWG, 1034 groups, 38 x 75 grid, gamma = 1e-6, 64 RHS), the 20-lambda
+batching sphere at its smallest and largest boxes (0.5 and 4 lambda, 64 RHS) and the
+45-lambda sphere (2,301,870 RWG, gamma = 1e-5, 32 RHS).  Far-fields are filled and
+compressed on the GPU group chunk by group chunk, the FP32 pass is replayed from a
+captured graph and the BF16x2 matrix-core pass runs at the workload's RHS count; both
+are checked against the oracle's dense FP64 products on sampled groups (the largest
+and three seeded draws), which the oracle computes one group at a time.
 
 Bound: the compression error gamma ||A||_F ||x|| per tensor plus the arithmetic's
 (FP32: 1e-5 relative; BF16x2: 4e-5 relative, as in the multi-RHS parity tests).
@@ -31,18 +33,22 @@ def _gpu():
     torch.cuda.set_device(0)
 
 
-def test_sphere30_full_size_sampled_groups():
+CASES = [(W.SPHERE30, 64, 939870, 1034), (W.SPHERE20[0.5], 64, 432000, 7232),
+         (W.SPHERE20[4.0], 64, 432000, 98), (W.SPHERE45, 32, 2301870, 2345)]
+
+
+@pytest.mark.parametrize("w,R,n_basis,n_groups", CASES, ids=[c[0].name for c in CASES])
+def test_full_size_sampled_groups(w, R, n_basis, n_groups):
     import torch
-    w = W.SPHERE30
     v, t = w.mesh()
     geom = T.fmm_geometry_build(v, t, w.origin, w.box, w.boxes_per_axis, w.k, w.n_theta, w.n_phi)
     h = None
     try:
         lay = T.fmm_geometry_layout(geom)
         N, G, nd = lay.n_basis, lay.n_groups, lay.n_dir
-        assert (N, G) == (939870, 1034)
-        banner("full size: streaming compress of %d groups" % G)
-        chunk = 128
+        assert (N, G) == (n_basis, n_groups)
+        banner("full size %s: streaming compress of %d groups" % (w.name, G))
+        chunk = 16
         rows = max(int(lay.offsets[min(G, g0 + chunk)] - lay.offsets[g0]) for g0 in range(0, G, chunk))
         buf = torch.empty((rows, 2, w.n_theta, w.n_phi), dtype=torch.complex128, device="cuda")
         for g0 in range(0, G, chunk):
@@ -55,9 +61,9 @@ def test_sphere30_full_size_sampled_groups():
         ar = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         T.fmm_tucker_upload(h, T.FMM_C64, ar)
 
-        banner("full size: FP32 pass from a captured graph")
+        banner("full size %s: FP32 pass from a captured graph" % w.name)
         x = synth.complex_normal(synth.rng(w.seeds["x"]), N)
-        gin = synth.complex_normal(synth.rng(w.seeds["g"]), (G, 2, nd))
+        gin = synth.complex_normal(synth.rng(w.seeds.get("g", 1)), (G, 2, nd))
         xd = torch.from_numpy(x).to("cuda", torch.complex64)
         gd = torch.from_numpy(gin).to("cuda", torch.complex64)
         F = torch.empty((G, 2, nd), dtype=torch.complex64, device="cuda")
@@ -71,14 +77,13 @@ def test_sphere30_full_size_sampled_groups():
         F1, V1 = F.cpu().numpy(), V.cpu().numpy()
         del F, V, xd, gd
 
-        banner("full size: BF16x2 pass, 64 right-hand sides")
-        # 64 distinct columns from 8 seeded ones times per-column complex scales (drawing
-        # all 64 columns of G would take longer than the rest of the test)
-        R = 64
+        banner("full size %s: BF16x2 pass, %d right-hand sides" % (w.name, R))
+        # R distinct columns from 8 seeded ones times per-column complex scales (drawing
+        # all R columns of G would take longer than the rest of the test)
         scale = (1.0 + np.arange(R) / R) * np.exp(1j * np.arange(R))
         xr = synth.complex_normal(synth.rng(w.seeds["x"] + 100), (N, 8), dtype=np.complex64)
         xr = (np.tile(xr, (1, R // 8)) * scale).astype(np.complex64)
-        gr = synth.complex_normal(synth.rng(w.seeds["g"] + 100), (G, 2, nd, 8), dtype=np.complex64)
+        gr = synth.complex_normal(synth.rng(w.seeds.get("g", 1) + 100), (G, 2, nd, 8), dtype=np.complex64)
         gr = (np.tile(gr, (1, 1, 1, R // 8)) * scale).astype(np.complex64)
         _, nbytes = T.fmm_tucker_storage_bytes(h, T.FMM_BF16X2)
         ar2 = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -94,7 +99,7 @@ def test_sphere30_full_size_sampled_groups():
             T.fmm_tucker_destroy(h)
         T.fmm_geometry_destroy(geom)
 
-    banner("full size: oracle on sampled groups")
+    banner("full size %s: oracle on sampled groups" % w.name)
     P = geo.Problem(v, t, w.origin, w.box, w.boxes_per_axis, w.n_theta, w.n_phi)
     assert np.array_equal(P.offsets, offs)
     nb = P.group_sizes()
