@@ -64,7 +64,7 @@ typedef enum {
  *
  * Kernels.  FMM_C128 always runs the streaming kernels (one workgroup per
  * (group, polarisation, right-hand side), factors streamed from HBM once per
- * right-hand side; 128, 256 or 512 threads by the mean item size, or as tuned; the
+ * right-hand side; 64, 128, 256 or 512 threads by the mean item size, or as tuned; the
  * environment variable TUCKFMM_STREAM_THREADS, read at upload, fixes the default).  FMM_C64 runs the streaming kernels for an odd nrhs or
  * nrhs < 8 and the FP32 matrix-core products otherwise, unless fmm_tucker_tune chose
  * differently for that nrhs.  The matrix-core path computes every contraction of
@@ -287,8 +287,8 @@ fmm_status fmm_graph_capture(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const 
 /* Launch the captured pass on `stream`. */
 fmm_status fmm_graph_launch(fmm_tucker_t h, void* stream);
 
-/* Result of fmm_tucker_tune: path 0 = streaming kernels with `threads` (128, 256 or
- * 512) per workgroup, 1 = matrix-core products with `tile_steps` K steps per
+/* Result of fmm_tucker_tune: path 0 = streaming kernels with `threads` (64, 128, 256
+ * or 512) per workgroup, 1 = matrix-core products with `tile_steps` K steps per
  * workgroup and `rhs_chunk` right-hand sides per chunk; ms = mean time of one pass of
  * the winner. */
 typedef struct {

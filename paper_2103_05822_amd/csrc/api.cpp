@@ -631,11 +631,12 @@ extern "C" fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* are
     double c = 0.0;
     for (const TuckUnit& u : P.units) c += item_cost(P.items[u.item]) * (u.b1 - u.b0) / P.items[u.item].rb;
     c /= std::max<size_t>(1, P.units.size());
-    // (measured on MI355X: mean 12k and 50k elements run best at 128, 258k at 256)
-    sl.threads = c >= 1.5e6 ? 512 : (c >= 1e5 ? 256 : 128);
+    // (measured on MI355X: mean 12k elements runs best at 64 threads, 50k at 128,
+    // 258k at 256, 1.7M at 512)
+    sl.threads = c >= 1.5e6 ? 512 : (c >= 1e5 ? 256 : (c >= 3e4 ? 128 : 64));
     if (const char* env = std::getenv("TUCKFMM_STREAM_THREADS")) {
       const int v = std::atoi(env);
-      if (v == 128 || v == 256 || v == 512) sl.threads = v;
+      if (v == 64 || v == 128 || v == 256 || v == 512) sl.threads = v;
     }
   }
   sl.ready = true;
@@ -751,7 +752,7 @@ extern "C" fmm_status fmm_tucker_tune(fmm_tucker_t h, fmm_prec prec, int32_t nrh
   // several tile sizes and right-hand-side chunks (even nrhs)
   std::vector<TuneChoice> cand;
   if (!prec_is_split(prec))
-    for (int nt : {128, 256, 512}) cand.push_back(TuneChoice{nrhs, 0, 0, 0, nt});
+    for (int nt : {64, 128, 256, 512}) cand.push_back(TuneChoice{nrhs, 0, 0, 0, nt});
   if (prec != FMM_C128 && nrhs % 2 == 0) {
     std::vector<int> chunks{std::min<int>(nrhs, kMrhsDefaultChunk)};
     if (nrhs > 2 * kMrhsDefaultChunk) chunks.push_back(2 * kMrhsDefaultChunk);

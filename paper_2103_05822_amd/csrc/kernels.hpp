@@ -7,7 +7,7 @@
 namespace tuckfmm {
 
 // Tucker aggregation / disaggregation / whole pass over an uploaded plan, one
-// workgroup of `threads` (128, 256 or 512) per item and right-hand side.
+// workgroup of `threads` (64, 128, 256 or 512) per item and right-hand side.
 template <typename T>
 hipError_t launch_tucker_agg(const TuckPlan& pl, int threads, int n_theta, int n_phi, int nrhs, const void* x,
                              void* F, hipStream_t s);

@@ -34,7 +34,7 @@ namespace tuckfmm {
 
 namespace {
 
-// Workgroup size NT (128, 256 or 512 threads, NT / 64 wavefronts) is a template
+// Workgroup size NT (64, 128, 256 or 512 threads, NT / 64 wavefronts) is a template
 // parameter of every phase: one workgroup per item.
 constexpr int kColPacks = 2;  // column packs per thread per chunk in the axpy stages
 
@@ -617,6 +617,11 @@ size_t tucker_lds_bytes(const TuckMax& mx) {
 // Workgroup sizes a launch may take.
 #define TFMM_NT_SWITCH(threads, ...) \
   switch (threads) {                  \
+    case 64: {                        \
+      constexpr int NT = 64;          \
+      __VA_ARGS__;                    \
+      break;                          \
+    }                                 \
     case 128: {                       \
       constexpr int NT = 128;         \
       __VA_ARGS__;                    \
@@ -673,7 +678,7 @@ template <typename T>
 hipError_t launch_tucker_disagg(const TuckPlan& pl, int threads, int n_theta, int n_phi, int nrhs, const void* G,
                                 void* V, hipStream_t s) {
   using C = typename Tr<T>::c;
-  if (threads != 128 && threads != 256 && threads != 512) return hipErrorInvalidValue;
+  if (threads != 64 && threads != 128 && threads != 256 && threads != 512) return hipErrorInvalidValue;
   if (pl.n_splits > 0 && pl.part == nullptr) return hipErrorInvalidValue;
   hipError_t e = zero(static_cast<C*>(V), pl.n_basis * nrhs, s);
   if (e != hipSuccess || pl.n_units == 0) return e;
@@ -692,7 +697,7 @@ template <typename T>
 hipError_t launch_tucker_pass(const TuckPlan& pl, int threads, int n_theta, int n_phi, int nrhs, const void* x,
                               void* F, const void* G, void* V, hipStream_t s) {
   using C = typename Tr<T>::c;
-  if (threads != 128 && threads != 256 && threads != 512) return hipErrorInvalidValue;
+  if (threads != 64 && threads != 128 && threads != 256 && threads != 512) return hipErrorInvalidValue;
   if (pl.n_splits > 0 && pl.part == nullptr) return hipErrorInvalidValue;
   hipError_t e = zero(static_cast<C*>(V), pl.n_basis * nrhs, s);
   if (e != hipSuccess || pl.n_units == 0) return e;

@@ -316,7 +316,7 @@ def test_compress_end_to_end(gamma, w):
             assert np.all(np.abs(np.array(core.shape) - np.array(c_ref.shape)) <= 1), (core.shape, c_ref.shape)
 
 
-@pytest.mark.parametrize("threads", [128, 256, 512])
+@pytest.mark.parametrize("threads", [64, 128, 256, 512])
 @pytest.mark.parametrize("prec", [T.FMM_C128, T.FMM_C64], ids=["c128", "c64"])
 def test_tucker_workgroup_sizes(prec, threads, monkeypatch):
     """Every workgroup size of the streaming kernels (forced at upload) matches the
