@@ -64,8 +64,9 @@ typedef enum {
  *
  * Kernels.  FMM_C128 always runs the streaming kernels (one workgroup per
  * (group, polarisation, right-hand side), factors streamed from HBM once per
- * right-hand side; 64, 128, 256 or 512 threads by the mean item size, or as tuned; the
- * environment variable TUCKFMM_STREAM_THREADS, read at upload, fixes the default).  FMM_C64 runs the streaming kernels for an odd nrhs or
+ * right-hand side; 64, 128, 256 or 512 threads by the mean item size, or as tuned;
+ * the environment variable TUCKFMM_STREAM_THREADS, read at upload, fixes the
+ * default).  FMM_C64 runs the streaming kernels for an odd nrhs or
  * nrhs < 8 and the FP32 matrix-core products otherwise, unless fmm_tucker_tune chose
  * differently for that nrhs.  The matrix-core path computes every contraction of
  * Section II.C as one grouped complex GEMM over all (group, polarisation) items for a
