@@ -74,7 +74,12 @@ typedef enum {
  * vectors and keeps library-owned device tables and scratch per nrhs (freed by a new
  * upload, fmm_tucker_set_group or fmm_tucker_destroy).  Calls of one handle and
  * precision that use the matrix-core path share that scratch: they must not run
- * concurrently on different streams. */
+ * concurrently on different streams.  In layouts of fewer than 128 (group,
+ * polarisation) items the streaming kernels split large items into blocks of their
+ * r_beta rows on several workgroups and sum the blocks' partial results, in block
+ * order, in a finishing kernel (TUCKFMM_SPLIT_ELEMS, read at upload, sets the block
+ * size in streamed elements for any layout); the partial sums live in a
+ * library-owned buffer of the handle, shared the same way. */
 typedef enum { FMM_C128 = 0, FMM_C64 = 1, FMM_BF16X2 = 2, FMM_BF16X3 = 3 } fmm_prec;
 
 /* Problem layout shared by every group-wise call. */
