@@ -125,6 +125,21 @@ struct Scalars {
   static size_t bytes(int nbm, int nt, int np) { return sizeof(double) * 3 * ((size_t)nbm + nt + np) + 64; }
 };
 
+// The tensor's per-basis-function energies (row sums of |A|^2, into `tmp`, nb doubles),
+// checked on the host before any eigensolver sees the data: a NaN or Inf far-field
+// is reported, not decomposed.
+std::string check_finite(Worker& w, const void* slab, int nb, int nd, double* tmp) {
+  hipError_t he = launch_strided_energy(slab, nb, nd, nd, 1, tmp, w.s);
+  if (he != hipSuccess) return hip_msg("energy kernel", he);
+  std::vector<double> e(nb);
+  if ((he = hipMemcpyAsync(e.data(), tmp, sizeof(double) * nb, hipMemcpyDeviceToHost, w.s)) != hipSuccess ||
+      (he = hipStreamSynchronize(w.s)) != hipSuccess)
+    return hip_msg("energy copy", he);
+  for (double v : e)
+    if (!std::isfinite(v)) return "NUMERIC:non-finite far-field values";
+  return std::string();
+}
+
 // Reversed copy: ascending eigenvalue order -> descending.
 std::vector<double> reversed(const double* a, int n) {
   std::vector<double> v(n);
@@ -153,6 +168,10 @@ std::string decompose_svd(const Job& J, Worker& w, int t) {
 
   hipError_t he = launch_gather_slab(J.farfield, row0, nb, alpha, nt, np, slab, nullptr, w.s);
   if (he != hipSuccess) return hip_msg("gather kernel", he);
+  {
+    const std::string bad = check_finite(w, slab, nb, nd, sc.eb);
+    if (!bad.empty()) return bad;
+  }
   const double one = 1.0, zero = 0.0;
   const Z cone = {1.0, 0.0}, czero = {0.0, 0.0};
   rocblas_status bs = rocblas_status_success;
@@ -241,6 +260,10 @@ std::string decompose(const Job& J, Worker& w, int t) {
 
   hipError_t he = launch_gather_slab(J.farfield, row0, nb, alpha, nt, np, slab, nullptr, w.s);
   if (he != hipSuccess) return hip_msg("gather kernel", he);
+  {
+    const std::string bad = check_finite(w, slab, nb, nd, sc.eb);
+    if (!bad.empty()) return bad;
+  }
   const double one = 1.0, zero = 0.0;
   const Z cone = {1.0, 0.0}, czero = {0.0, 0.0};
   rocblas_status bs = rocblas_status_success;

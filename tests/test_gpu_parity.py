@@ -625,3 +625,19 @@ def test_compress_plate_with_a_zero_pattern_row():
                                                                                          c_ref.shape)
         bound = gamma * np.linalg.norm(blk[:, a]) * np.linalg.norm(x)
         assert np.linalg.norm(F[0, a] - f_dense[a]) <= bound * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf], ids=["nan", "inf"])
+@pytest.mark.parametrize("svd", [False, True], ids=["hosvd", "svd"])
+def test_compress_rejects_non_finite_farfield(bad, svd):
+    """A NaN or Inf far-field entry is reported as FMM_ERR_NUMERIC before any
+    eigensolver sees the data, and no handle is left behind."""
+    lay = ragged_layout()
+    banner("compress non-finite %s svd=%s" % (bad, svd))
+    rng = synth.rng(16)
+    D = synth.complex_normal(rng, (lay.n_basis, 2, lay.n_theta, lay.n_phi))
+    D[70, 1, 2, 3] = bad
+    fn = T.fmm_farfield_compress_svd if svd else T.fmm_farfield_compress
+    with pytest.raises(T.FmmError) as err:
+        fn(lay, dev(D), 0, lay.n_groups, 1e-6)
+    assert err.value.status == -5 and "non-finite" in str(err.value)
