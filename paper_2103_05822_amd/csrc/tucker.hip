@@ -1,11 +1,14 @@
 // Tucker-format aggregation and disaggregation (Section II.C, Figs. 2(b) and 3(b)).
 //
-// One 512-thread workgroup (eight 64-wide wavefronts) per (group, polarisation)
-// work item.  The two large operands of an item -- U^beta and the core -- are
-// streamed once from HBM with 16-byte coalesced loads; every intermediate stays in
-// LDS.  Work lists are sorted by decreasing cost, so the hardware dispatcher hands
-// out the largest items first (longest-processing-time order).  The pass kernel
-// runs the aggregation and disaggregation items of all groups in one launch.
+// One workgroup of NT = 64, 128, 256 or 512 threads (NT / 64 wavefronts) per
+// (group, polarisation) work item, NT chosen from the mean item size.  The two large
+// operands of an item -- U^beta and the core -- are streamed once from HBM with
+// 16-byte coalesced loads; every intermediate stays in LDS.  Work lists are sorted by
+// decreasing cost, so the hardware dispatcher hands out the largest items first
+// (longest-processing-time order).  The pass kernel runs the aggregation and
+// disaggregation items of all groups in one launch.  In layouts of few items, large
+// items run as blocks of their r_beta rows (work units) whose partial sums a
+// finishing kernel adds in block order.
 //
 // Aggregation of item (g, alpha), contraction order chosen per item on the host:
 //   y[b]    = sum_n U^beta[n][b] x[n]          row-dot of each U^beta^T row (one
