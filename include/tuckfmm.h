@@ -62,12 +62,12 @@ typedef enum {
  *   FMM_BF16X3 as FMM_BF16X2 with three pieces (hi + mid + lo) and the six products
  *              down to order 2^-16 (FP32-level error).  Needs an even nrhs.
  *
- * Kernels.  FMM_C128 always runs the streaming kernels (one workgroup per
+ * Kernels.  FMM_C128 and FMM_C64 run the streaming kernels (one workgroup per
  * (group, polarisation, right-hand side), factors streamed from HBM once per
  * right-hand side; 64, 128, 256 or 512 threads by the mean item size, or as tuned;
  * the environment variable TUCKFMM_STREAM_THREADS, read at upload, fixes the
- * default).  FMM_C64 runs the streaming kernels for an odd nrhs or
- * nrhs < 8 and the FP32 matrix-core products otherwise, unless fmm_tucker_tune chose
+ * default) for an odd nrhs or nrhs < 8, and the matrix-core products otherwise (FP64
+ * MFMA for FMM_C128, FP32 MFMA for FMM_C64), unless fmm_tucker_tune chose
  * differently for that nrhs.  The matrix-core path computes every contraction of
  * Section II.C as one grouped complex GEMM over all (group, polarisation) items for a
  * chunk of right-hand sides (factors read once per chunk); it needs 16-byte aligned

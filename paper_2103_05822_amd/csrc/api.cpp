@@ -73,7 +73,8 @@ int pack_elems(fmm_prec p) { return p == FMM_C128 ? 1 : 2; }
 bool prec_valid(int p) { return p >= FMM_C128 && p <= FMM_BF16X3; }
 bool prec_is_split(fmm_prec p) { return p == FMM_BF16X2 || p == FMM_BF16X3; }
 
-// Smallest even nrhs for which FMM_C64 takes the matrix-core products when untuned.
+// Smallest even nrhs for which FMM_C64 and FMM_C128 take the matrix-core products
+// when untuned.
 constexpr int kMfmaMinRhs = 8;
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -299,7 +300,7 @@ fmm_status lds_check(size_t bytes) {
 // Which kernels run a call with nrhs right-hand sides.
 struct Route {
   bool mfma = false;  // matrix-core products (else the streaming kernels)
-  int variant = 0;    // grouped GEMM arithmetic: 0 FP32, 1 BF16x2, 2 BF16x3
+  int variant = 0;    // grouped GEMM arithmetic: 0 FP32, 1 BF16x2, 2 BF16x3, 3 FP64
   int tile_steps = 0, rhs_chunk = 0;
   int threads = 512;  // streaming kernels' workgroup size
 };
@@ -309,13 +310,13 @@ fmm_status route_of(const PrecSlot& s, fmm_prec prec, int nrhs, Route* r) {
   r->threads = s.threads;
   for (const TuneChoice& t : s.tuned)
     if (t.nrhs == nrhs && t.path == 0 && t.threads) r->threads = t.threads;
-  if (prec == FMM_C128) return FMM_OK;
   if (prec_is_split(prec)) {
     if (nrhs % 2) return fail(FMM_ERR_UNSUPPORTED, "the bf16 split precisions need an even nrhs");
     r->mfma = true;
     r->variant = prec == FMM_BF16X2 ? 1 : 2;
   } else {
     r->mfma = nrhs % 2 == 0 && nrhs >= kMfmaMinRhs;
+    r->variant = prec == FMM_C128 ? 3 : 0;
   }
   for (const TuneChoice& t : s.tuned)
     if (t.nrhs == nrhs) {
@@ -368,8 +369,8 @@ fmm_status run_stage(fmm_tucker_t h, PrecSlot& s, fmm_prec prec, int nrhs, int s
     for (const void* p : {x, (const void*)F, G, (const void*)V})
       if (p && !aligned(p, 16)) return fail(FMM_ERR_ARG, "the matrix-core path needs 16-byte aligned vectors");
     MrhsPlan* mp = nullptr;
-    if ((st = mrhs_get(s, L, nrhs, r.tile_steps, r.rhs_chunk, &mp)) != FMM_OK) return st;
-    return mrhs_run(*mp, s, r.variant, stage, x, F, G, V, hs);
+    if ((st = mrhs_get(s, elem_bytes(prec), L, nrhs, r.tile_steps, r.rhs_chunk, &mp)) != FMM_OK) return st;
+    return mrhs_run(*mp, s, r.variant, elem_bytes(prec), stage, x, F, G, V, hs);
   }
   if ((st = ensure_part(h, s, prec, nrhs)) != FMM_OK) return st;
   if (prec == FMM_C128) {
@@ -720,7 +721,7 @@ extern "C" fmm_status fmm_graph_capture(fmm_tucker_t h, fmm_prec prec, int32_t n
   if ((st = route_of(*s, prec, nrhs, &r)) != FMM_OK) return st;
   if (r.mfma) {
     MrhsPlan* mp = nullptr;
-    if ((st = mrhs_get(*s, h->layout, nrhs, r.tile_steps, r.rhs_chunk, &mp)) != FMM_OK) return st;
+    if ((st = mrhs_get(*s, elem_bytes(prec), h->layout, nrhs, r.tile_steps, r.rhs_chunk, &mp)) != FMM_OK) return st;
   } else if ((st = ensure_part(h, *s, prec, nrhs)) != FMM_OK) {
     return st;
   }
@@ -753,7 +754,7 @@ extern "C" fmm_status fmm_tucker_tune(fmm_tucker_t h, fmm_prec prec, int32_t nrh
   std::vector<TuneChoice> cand;
   if (!prec_is_split(prec))
     for (int nt : {64, 128, 256, 512}) cand.push_back(TuneChoice{nrhs, 0, 0, 0, nt});
-  if (prec != FMM_C128 && nrhs % 2 == 0) {
+  if (nrhs % 2 == 0) {
     std::vector<int> chunks{std::min<int>(nrhs, kMrhsDefaultChunk)};
     if (nrhs > 2 * kMrhsDefaultChunk) chunks.push_back(2 * kMrhsDefaultChunk);
     if (nrhs >= kMrhsDefaultChunk) chunks.push_back(kMrhsDefaultChunk / 2);

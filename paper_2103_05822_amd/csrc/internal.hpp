@@ -110,10 +110,12 @@ struct MrhsHost {
 void mrhs_build_host(const std::vector<TuckItem>& items, const Layout& L, int nrhs, int tile_steps, int rhs_chunk,
                      MrhsHost* out);
 // Plan for (slot, nrhs) with the given knobs (0 = defaults), built on first use.
-fmm_status mrhs_get(PrecSlot& s, const Layout& L, int nrhs, int tile_steps, int rhs_chunk, MrhsPlan** out);
+// elem_bytes: 8 (complex64 slot) or 16 (complex128 slot), the size of a scratch value.
+fmm_status mrhs_get(PrecSlot& s, size_t elem_bytes, const Layout& L, int nrhs, int tile_steps, int rhs_chunk,
+                    MrhsPlan** out);
 // stage: 0 aggregation, 1 disaggregation, 2 both (merged launches).
-fmm_status mrhs_run(const MrhsPlan& p, const PrecSlot& s, int variant, int stage, const void* x, void* F,
-                    const void* G, void* V, hipStream_t st);
+fmm_status mrhs_run(const MrhsPlan& p, const PrecSlot& s, int variant, size_t elem_bytes, int stage, const void* x,
+                    void* F, const void* G, void* V, hipStream_t st);
 void mrhs_free(MrhsPlan& p);
 void mrhs_release(PrecSlot& s);
 

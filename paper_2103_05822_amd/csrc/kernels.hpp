@@ -22,10 +22,12 @@ template <typename T>
 size_t tucker_lds_bytes(const TuckMax& mx);
 
 // Grouped complex GEMM of the multi-RHS path (variant 0: FP32 MFMA, 1: BF16 two-piece
-// split, 2: BF16 three-piece split; FP32 accumulation), one workgroup per tile.
+// split, 2: BF16 three-piece split, all on complex64 data with FP32 accumulation;
+// 3: FP64 MFMA on complex128 data), one workgroup per tile.
 hipError_t launch_cgemm(int variant, const CGemm* probs, const CTile* tiles, int n_tiles, const CGemmBases& b,
                         hipStream_t s);
-hipError_t launch_zero_c64(void* v, int64_t n, hipStream_t s);
+// Zero n complex values of elem_bytes (8 or 16) each.
+hipError_t launch_zero_cplx(size_t elem_bytes, void* v, int64_t n, hipStream_t s);
 // Zero rows[0 .. n_rows) of a row-major array of rows of row_elems complex values of
 // elem_bytes (8 or 16) each.
 hipError_t launch_zero_rows(size_t elem_bytes, void* base, const int32_t* rows, int n_rows, int64_t row_elems,

@@ -31,6 +31,8 @@
 //   2  BF16x3  three pieces v = hi + mid + lo and the six products whose order is at
 //              most 2^-16 (hi*hi, hi*mid, mid*hi, hi*lo, mid*mid, lo*hi): FP32-level
 //              accuracy at six bf16 instructions per product.
+// Variant 3 is the complex128 path: factors, vectors and intermediates in FP64 and
+// v_mfma_f64_16x16x4_f64 on them, with the same tile, pipeline and B expansion.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,6 +45,7 @@ namespace tuckfmm {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kMT = 256;           // threads
@@ -56,10 +59,11 @@ constexpr int kAS = kKC + 2;
 
 __device__ __forceinline__ int64_t col_off(int n, int ni, int shi) { return (int64_t)(n / ni) * shi + n % ni; }
 
-__device__ __forceinline__ float2* base_ptr(const CGemmBases& b, int i) {
+template <typename C2>
+__device__ __forceinline__ C2* base_ptr(const CGemmBases& b, int i) {
   // i is uniform across the workgroup: a select chain, no indexed private array
   void* p = i == 0 ? b.p[0] : i == 1 ? b.p[1] : i == 2 ? b.p[2] : i == 3 ? b.p[3] : i == 4 ? b.p[4] : b.p[5];
-  return static_cast<float2*>(p);
+  return static_cast<C2*>(p);
 }
 
 // ------------------------------------------------------------------ global loads
@@ -72,30 +76,33 @@ __device__ __forceinline__ float2* base_ptr(const CGemmBases& b, int i) {
 // step's tail) is read from a clamp address inside the operand instead and zeroed
 // when the step is written to LDS.  Nothing consumes the loaded values before that
 // point, so the loads stay in flight while the previous step runs on the matrix cores.
+template <typename C2>
 struct Stage {
-  float2 a[4];
-  float2 b[4];
+  C2 a[4];
+  C2 b[4];
   int na, nb;  // number of valid elements (a prefix of the quad)
 };
 
 // Per-thread operand walkers.
+template <typename C2>
 struct Walk {
-  const float2* clampa;  // first element of A
-  const float2* a0;      // the thread's quad at K step 0 (clampa if the row is invalid)
-  const float2* a;       // the quad at the current K step
+  const C2* clampa;  // first element of A
+  const C2* a0;      // the thread's quad at K step 0 (clampa if the row is invalid)
+  const C2* a;       // the quad at the current K step
   int64_t astep;         // pointer advance per K step (0 for an invalid row)
   int aes;               // element stride inside the quad
   int aq;                // K quad index (0..3)
   bool arow;             // row valid
-  const float2* clampb;
-  const float2* b;
+  const C2* clampb;
+  const C2* b;
   int64_t bstep;
   int bes;
   int bq;
   bool bcol;
 };
 
-__device__ __forceinline__ void walk_init(const CGemm& p, const float2* A, const float2* B, int m0, int tid, Walk& w) {
+template <typename C2>
+__device__ __forceinline__ void walk_init(const CGemm& p, const C2* A, const C2* B, int m0, int tid, Walk<C2>& w) {
   const bool kc = p.lda_k == 1;
   const int am = m0 + (kc ? tid / 4 : tid % 64);
   w.aq = kc ? tid % 4 : tid / 64;
@@ -111,7 +118,8 @@ __device__ __forceinline__ void walk_init(const CGemm& p, const float2* A, const
 }
 
 // Points the B walker at column block n0 (K step 0).
-__device__ __forceinline__ void walk_block(const CGemm& p, int n0, int tid, Walk& w) {
+template <typename C2>
+__device__ __forceinline__ void walk_block(const CGemm& p, int n0, int tid, Walk<C2>& w) {
   const int n = n0 + tid % 64;
   w.bcol = n < p.N;
   w.b = w.bcol ? w.clampb + col_off(n, p.b_ni, p.b_shi) + (int64_t)(4 * w.bq) * p.ldb_k : w.clampb;
@@ -122,13 +130,14 @@ __device__ __forceinline__ void walk_block(const CGemm& p, int n0, int tid, Walk
 // AVEC (uniform per product; K-contiguous A with even offset and row stride): A is
 // read as two 16-byte pairs.  A pair whose first element is valid is read whole; at
 // an odd K its second element is the row's zero padding (factor rows are padded to
-// an even length) and is masked.
-template <bool AVEC>
-__device__ __forceinline__ void load_stage(const CGemm& p, int k0, Walk& w, Stage& st) {
+// an even length) and is masked.  (A complex128 element is a 16-byte load by itself.)
+template <bool AVEC, typename C2>
+__device__ __forceinline__ void load_stage(const CGemm& p, int k0, Walk<C2>& w, Stage<C2>& st) {
   const int na = w.arow ? min(4, max(0, p.K - k0 - 4 * w.aq)) : 0;
   const int nb = w.bcol ? min(4, max(0, p.K - k0 - 4 * w.bq)) : 0;
-  const float2* pa = na > 0 ? w.a : w.clampa;
+  const C2* pa = na > 0 ? w.a : w.clampa;
   if constexpr (AVEC) {
+    static_assert(sizeof(C2) == 8, "paired loads are for complex64");
     const float4 u = *reinterpret_cast<const float4*>(pa);
     const float4 v = *reinterpret_cast<const float4*>(pa + (na > 2 ? 2 : 0));
     st.a[0] = make_float2(u.x, u.y);
@@ -139,7 +148,7 @@ __device__ __forceinline__ void load_stage(const CGemm& p, int k0, Walk& w, Stag
 #pragma unroll
     for (int e = 0; e < 4; ++e) st.a[e] = pa[e < na ? e * w.aes : 0];
   }
-  const float2* pb = nb > 0 ? w.b : w.clampb;
+  const C2* pb = nb > 0 ? w.b : w.clampb;
 #pragma unroll
   for (int e = 0; e < 4; ++e) st.b[e] = pb[e < nb ? e * w.bes : 0];
   st.na = na;
@@ -150,14 +159,16 @@ __device__ __forceinline__ void load_stage(const CGemm& p, int k0, Walk& w, Stag
 
 // Element e of the stage's A (B) values with invalid elements zeroed and the
 // conjugation flag applied -- the point where the loads are waited for.
-__device__ __forceinline__ float2 a_val(const CGemm& p, const Stage& st, int e) {
-  float2 v = e < st.na ? st.a[e] : make_float2(0.f, 0.f);
+template <typename C2>
+__device__ __forceinline__ C2 a_val(const CGemm& p, const Stage<C2>& st, int e) {
+  C2 v = e < st.na ? st.a[e] : czero<C2>();
   if (p.flags & kConjA) v.y = -v.y;
   return v;
 }
 
-__device__ __forceinline__ float2 b_val(const CGemm& p, const Stage& st, int e) {
-  float2 v = e < st.nb ? st.b[e] : make_float2(0.f, 0.f);
+template <typename C2>
+__device__ __forceinline__ C2 b_val(const CGemm& p, const Stage<C2>& st, int e) {
+  C2 v = e < st.nb ? st.b[e] : czero<C2>();
   if (p.flags & kConjB) v.y = -v.y;
   return v;
 }
@@ -184,7 +195,7 @@ struct LdsF32 {
   float2 b[kKC * kXS];
 };
 
-__device__ __forceinline__ void store_f32(const CGemm& p, const Stage& st, LdsF32& L, int tid) {
+__device__ __forceinline__ void store_f32(const CGemm& p, const Stage<float2>& st, LdsF32& L, int tid) {
   int m, kq;
   a_slot(p, tid, m, kq);
   float2* da = &L.a[m * kAS + 4 * kq];
@@ -231,6 +242,60 @@ __device__ __forceinline__ void mma_f32(const LdsF32& L, int w, int lane, floatx
   }
 }
 
+// ------------------------------------------------------------------- FP64 variant
+// The FP32 layout with double2 values (52 KB of LDS).  v_mfma_f64_16x16x4_f64 takes
+// its operands in the lane layout of the FP32 instruction (A row l % 16, B column
+// l % 16, K index l / 16), so the real K permutation and the B reads are those of
+// mma_f32; only the accumulator layout differs (see the epilogue).
+struct LdsF64 {
+  double2 a[kBM * kAS];
+  double2 b[kKC * kXS];
+};
+
+__device__ __forceinline__ void store_f64(const CGemm& p, const Stage<double2>& st, LdsF64& L, int tid) {
+  int m, kq;
+  a_slot(p, tid, m, kq);
+  double2* da = &L.a[m * kAS + 4 * kq];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) da[e] = a_val(p, st, e);
+  const int nn = tid % 64, kb = 4 * (tid / 64);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const double2 v = b_val(p, st, e);
+    double2* db = &L.b[(kb + e) * kXS + 2 * nn];
+    db[0] = make_double2(v.x, -v.y);
+    db[1] = make_double2(v.y, v.x);
+  }
+}
+
+__device__ __forceinline__ void mma_f64(const LdsF64& L, int w, int lane, doublex4 (&acc)[kNT]) {
+  const int mi = lane % 16, kb = lane / 16;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const double2* pa = &L.a[(16 * w + mi) * kAS + 8 * h + 2 * kb];
+    const double2 a0 = pa[0], a1 = pa[1];
+    const double av[4] = {a0.x, a0.y, a1.x, a1.y};
+#pragma unroll
+    for (int t0 = 0; t0 < kNT; t0 += kNT / 2) {
+      double2 b0[kNT / 2], b1[kNT / 2];
+#pragma unroll
+      for (int u = 0; u < kNT / 2; ++u) {
+        const int col = 16 * (t0 + u) + mi;
+        b0[u] = L.b[(8 * h + 2 * kb) * kXS + col];
+        b1[u] = L.b[(8 * h + 2 * kb + 1) * kXS + col];
+      }
+#pragma unroll
+      for (int u = 0; u < kNT / 2; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0], b0[u].x, acc[t0 + u], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < kNT / 2; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1], b0[u].y, acc[t0 + u], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < kNT / 2; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[2], b1[u].x, acc[t0 + u], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < kNT / 2; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[3], b1[u].y, acc[t0 + u], 0, 0, 0);
+    }
+  }
+}
+
 // ------------------------------------------------------------------- BF16 variants
 // LDS holds the operands pre-split: A as [piece][row][32 real K] and
 // the expanded B as [piece][real column][32 real K], bf16, rows padded to 80 bytes
@@ -259,7 +324,7 @@ __device__ __forceinline__ void split(float v, __bf16 (&pc)[NP]) {
 __device__ __forceinline__ __bf16 bneg(__bf16 x) { return -x; }
 
 template <int NP>
-__device__ __forceinline__ void store_bf16(const CGemm& p, const Stage& st, LdsBf16<NP>& L, int tid) {
+__device__ __forceinline__ void store_bf16(const CGemm& p, const Stage<float2>& st, LdsBf16<NP>& L, int tid) {
   {
     int m, kq;
     a_slot(p, tid, m, kq);
@@ -340,24 +405,28 @@ __device__ __forceinline__ void mma_bf16(const LdsBf16<NP>& L, int w, int lane, 
 }
 
 // ------------------------------------------------------------------- epilogue
-// Lane (ni, g) holds real rows 4g + i (i = 0..3) of real column 16t + ni.  Lanes ni
-// and ni ^ 1 hold the real and imaginary parts of one complex column: after one
-// exchange the even lane owns rows 4g, 4g + 1 and the odd lane rows 4g + 2, 4g + 3 as
-// complex values.
-__device__ __forceinline__ void epilogue(const CGemm& p, float2* Cp, int m0, int n0, int w, int lane,
-                                         const floatx4 (&acc)[kNT]) {
+// Accumulator register i of lane (ni, g) holds real column 16t + ni of real row
+//   4g + i   (FP32 instruction),   4i + g   (FP64 instruction).
+// Lanes ni and ni ^ 1 hold the real and imaginary parts of one complex column: after
+// one exchange the even lane owns the rows of registers 0, 1 and the odd lane those
+// of registers 2, 3 as complex values.
+template <typename C2, typename ACC>
+__device__ __forceinline__ void epilogue(const CGemm& p, C2* Cp, int m0, int n0, int w, int lane,
+                                         const ACC (&acc)[kNT]) {
+  using R = decltype(C2{}.x);
+  constexpr bool kF64 = sizeof(R) == 8;
   const int ni = lane % 16, g = lane / 16;
   const bool odd = ni & 1;
   const bool conj_out = p.flags & kConjC, atomic = p.flags & kAtomicC;
 #pragma unroll
   for (int t = 0; t < kNT; ++t) {
-    const float s0 = odd ? acc[t][0] : acc[t][2];
-    const float s1 = odd ? acc[t][1] : acc[t][3];
-    const float r0 = __shfl_xor(s0, 1);
-    const float r1 = __shfl_xor(s1, 1);
-    // even lane: (acc0, r0), (acc1, r1) for rows 4g, 4g + 1; odd: (r0, acc2), (r1, acc3)
-    float2 c0 = odd ? make_float2(r0, acc[t][2]) : make_float2(acc[t][0], r0);
-    float2 c1 = odd ? make_float2(r1, acc[t][3]) : make_float2(acc[t][1], r1);
+    const R s0 = odd ? acc[t][0] : acc[t][2];
+    const R s1 = odd ? acc[t][1] : acc[t][3];
+    const R r0 = __shfl_xor(s0, 1);
+    const R r1 = __shfl_xor(s1, 1);
+    // even lane: (acc0, r0), (acc1, r1) for registers 0, 1; odd: (r0, acc2), (r1, acc3)
+    C2 c0 = odd ? C2{r0, acc[t][2]} : C2{acc[t][0], r0};
+    C2 c1 = odd ? C2{r1, acc[t][3]} : C2{acc[t][1], r1};
     if (conj_out) {
       c0.y = -c0.y;
       c1.y = -c1.y;
@@ -365,13 +434,13 @@ __device__ __forceinline__ void epilogue(const CGemm& p, float2* Cp, int m0, int
     const int n = n0 + 8 * t + ni / 2;
     if (n >= p.N) continue;
     const int64_t coff = p.c + col_off(n, p.c_ni, p.c_shi);
-    const int mb = m0 + 16 * w + 4 * g + (odd ? 2 : 0);
+    const int reg0 = odd ? 2 : 0;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const int m = mb + i;
+      const int m = m0 + 16 * w + (kF64 ? 4 * (reg0 + i) + g : 4 * g + reg0 + i);
       if (m >= p.M) continue;
-      float2* dst = Cp + coff + (int64_t)m * p.ldc_m;
-      const float2 c = i ? c1 : c0;
+      C2* dst = Cp + coff + (int64_t)m * p.ldc_m;
+      const C2 c = i ? c1 : c0;
       if (atomic) {
         atomicAdd(&dst->x, c.x);
         atomicAdd(&dst->y, c.y);
@@ -384,28 +453,44 @@ __device__ __forceinline__ void epilogue(const CGemm& p, float2* Cp, int m0, int
 
 // ------------------------------------------------------------------- kernel
 
+// Per-variant types: LDS stage, complex element, accumulator.
 template <int VARIANT>
-struct LdsOf {
-  using type = LdsBf16<VARIANT + 1>;
+struct VarOf {
+  using lds = LdsBf16<VARIANT + 1>;
+  using c2 = float2;
+  using acc = floatx4;
 };
 template <>
-struct LdsOf<0> {
-  using type = LdsF32;
+struct VarOf<0> {
+  using lds = LdsF32;
+  using c2 = float2;
+  using acc = floatx4;
+};
+template <>
+struct VarOf<3> {
+  using lds = LdsF64;
+  using c2 = double2;
+  using acc = doublex4;
 };
 
 template <int VARIANT>
-__device__ __forceinline__ void store_stage(const CGemm& p, const Stage& st, typename LdsOf<VARIANT>::type& L, int tid) {
+__device__ __forceinline__ void store_stage(const CGemm& p, const Stage<typename VarOf<VARIANT>::c2>& st,
+                                            typename VarOf<VARIANT>::lds& L, int tid) {
   if constexpr (VARIANT == 0)
     store_f32(p, st, L, tid);
+  else if constexpr (VARIANT == 3)
+    store_f64(p, st, L, tid);
   else
     store_bf16<VARIANT + 1>(p, st, L, tid);
 }
 
 template <int VARIANT>
-__device__ __forceinline__ void mma_stage(const typename LdsOf<VARIANT>::type& L, int w, int lane,
-                                          floatx4 (&acc)[kNT]) {
+__device__ __forceinline__ void mma_stage(const typename VarOf<VARIANT>::lds& L, int w, int lane,
+                                          typename VarOf<VARIANT>::acc (&acc)[kNT]) {
   if constexpr (VARIANT == 0)
     mma_f32(L, w, lane, acc);
+  else if constexpr (VARIANT == 3)
+    mma_f64(L, w, lane, acc);
   else
     mma_bf16<VARIANT + 1>(L, w, lane, acc);
 }
@@ -418,20 +503,23 @@ __device__ __forceinline__ void mma_stage(const typename LdsOf<VARIANT>::type& L
 // often well below the 64-row tile) still loads, stores and meets every barrier, but
 // issues no matrix-core work, leaving the matrix cores to the other wavefronts.
 template <int VARIANT, bool AVEC, bool ACTIVE>
-__device__ __forceinline__ void run_tile(const CGemm& p, const CTile& tl, const float2* A, const float2* B, float2* Cp,
-                                         typename LdsOf<VARIANT>::type& L) {
+__device__ __forceinline__ void run_tile(const CGemm& p, const CTile& tl, const typename VarOf<VARIANT>::c2* A,
+                                         const typename VarOf<VARIANT>::c2* B, typename VarOf<VARIANT>::c2* Cp,
+                                         typename VarOf<VARIANT>::lds& L) {
+  using C2 = typename VarOf<VARIANT>::c2;
+  using ACC = typename VarOf<VARIANT>::acc;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int nsteps = (p.K + kKC - 1) / kKC;
 
-  floatx4 acc[kNT];
+  ACC acc[kNT];
   if constexpr (ACTIVE) {
 #pragma unroll
-    for (int t = 0; t < kNT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < kNT; ++t) acc[t] = ACC{0, 0, 0, 0};
   }
-  Walk wk;
+  Walk<C2> wk;
   walk_init(p, A, B, tl.m0, tid, wk);
   walk_block(p, tl.n0, tid, wk);
-  Stage st;
+  Stage<C2> st;
   load_stage<AVEC>(p, 0, wk, st);
   store_stage<VARIANT>(p, st, L, tid);
   __syncthreads();
@@ -461,7 +549,7 @@ __device__ __forceinline__ void run_tile(const CGemm& p, const CTile& tl, const 
     if (n0 >= tl.n1) break;
     if constexpr (ACTIVE) {
 #pragma unroll
-      for (int t = 0; t < kNT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int t = 0; t < kNT; ++t) acc[t] = ACC{0, 0, 0, 0};
     }
   }
 }
@@ -469,27 +557,35 @@ __device__ __forceinline__ void run_tile(const CGemm& p, const CTile& tl, const 
 template <int VARIANT>
 __global__ __launch_bounds__(kMT) void cgemm_kernel(const CGemm* __restrict__ probs, const CTile* __restrict__ tiles,
                                                     CGemmBases bases) {
-  using Lds = typename LdsOf<VARIANT>::type;
+  using Lds = typename VarOf<VARIANT>::lds;
+  using C2 = typename VarOf<VARIANT>::c2;
   __shared__ __align__(16) Lds L;
   const CTile tl = tiles[blockIdx.x];
   const CGemm p = probs[tl.prob];
-  const float2* A = base_ptr(bases, p.abase);
-  const float2* B = base_ptr(bases, p.bbase);
-  float2* Cp = base_ptr(bases, p.cbase);
-  // 16-byte A loads: K-contiguous A with an even offset and row stride; the branch
-  // on the wavefront's rows is uniform per wavefront
-  const bool avec = p.lda_k == 1 && !((p.a | p.lda_m) & 1);
+  const C2* A = base_ptr<C2>(bases, p.abase);
+  const C2* B = base_ptr<C2>(bases, p.bbase);
+  C2* Cp = base_ptr<C2>(bases, p.cbase);
+  // paired 16-byte A loads (complex64): K-contiguous A with an even offset and row
+  // stride; the branch on the wavefront's rows is uniform per wavefront
   const bool active = tl.m0 + 16 * (int)(threadIdx.x >> 6) < p.M;
-  if (avec) {
-    if (active)
-      run_tile<VARIANT, true, true>(p, tl, A, B, Cp, L);
-    else
-      run_tile<VARIANT, true, false>(p, tl, A, B, Cp, L);
-  } else {
+  if constexpr (VARIANT == 3) {
     if (active)
       run_tile<VARIANT, false, true>(p, tl, A, B, Cp, L);
     else
       run_tile<VARIANT, false, false>(p, tl, A, B, Cp, L);
+  } else {
+    const bool avec = p.lda_k == 1 && !((p.a | p.lda_m) & 1);
+    if (avec) {
+      if (active)
+        run_tile<VARIANT, true, true>(p, tl, A, B, Cp, L);
+      else
+        run_tile<VARIANT, true, false>(p, tl, A, B, Cp, L);
+    } else {
+      if (active)
+        run_tile<VARIANT, false, true>(p, tl, A, B, Cp, L);
+      else
+        run_tile<VARIANT, false, false>(p, tl, A, B, Cp, L);
+    }
   }
 }
 
@@ -509,15 +605,20 @@ hipError_t launch_cgemm(int variant, const CGemm* probs, const CTile* tiles, int
     hipLaunchKernelGGL(cgemm_kernel<1>, dim3(n_tiles), dim3(kMT), 0, s, probs, tiles, b);
   else if (variant == 2)
     hipLaunchKernelGGL(cgemm_kernel<2>, dim3(n_tiles), dim3(kMT), 0, s, probs, tiles, b);
+  else if (variant == 3)
+    hipLaunchKernelGGL(cgemm_kernel<3>, dim3(n_tiles), dim3(kMT), 0, s, probs, tiles, b);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t launch_zero_c64(void* v, int64_t n, hipStream_t s) {
+hipError_t launch_zero_cplx(size_t elem_bytes, void* v, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(mrhs_zero_kernel<float2>, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<float2*>(v), n);
+  if (elem_bytes == 16)
+    hipLaunchKernelGGL(mrhs_zero_kernel<double2>, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<double2*>(v), n);
+  else
+    hipLaunchKernelGGL(mrhs_zero_kernel<float2>, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<float2*>(v), n);
   return hipGetLastError();
 }
 

@@ -265,7 +265,8 @@ void mrhs_build_host(const std::vector<TuckItem>& items, const Layout& L, int nr
   }
 }
 
-fmm_status mrhs_get(PrecSlot& s, const Layout& L, int nrhs, int tile_steps, int rhs_chunk, MrhsPlan** out) {
+fmm_status mrhs_get(PrecSlot& s, size_t elem_bytes, const Layout& L, int nrhs, int tile_steps, int rhs_chunk,
+                    MrhsPlan** out) {
   if (tile_steps <= 0) tile_steps = kMrhsDefaultSteps;
   if (rhs_chunk <= 0) rhs_chunk = kMrhsDefaultChunk;
   if (nrhs % 2 || rhs_chunk % 2) return fail(FMM_ERR_UNSUPPORTED, "the matrix-core path needs an even nrhs");
@@ -284,7 +285,7 @@ fmm_status mrhs_get(PrecSlot& s, const Layout& L, int nrhs, int tile_steps, int 
     for (int k = 0; k < 3; ++k)
       for (int j = 0; j < 4; ++j) table_bytes += align256(h.lists[k][j].size() * sizeof(CTile));
   }
-  const size_t scratch_bytes = (size_t)host.scratch_elems * 8;
+  const size_t scratch_bytes = (size_t)host.scratch_elems * elem_bytes;
 
   // one device allocation: tables, then scratch
   MrhsPlan p;
@@ -332,8 +333,8 @@ fmm_status mrhs_get(PrecSlot& s, const Layout& L, int nrhs, int tile_steps, int 
   return FMM_OK;
 }
 
-fmm_status mrhs_run(const MrhsPlan& p, const PrecSlot& s, int variant, int stage, const void* x, void* F,
-                    const void* G, void* V, hipStream_t st) {
+fmm_status mrhs_run(const MrhsPlan& p, const PrecSlot& s, int variant, size_t elem_bytes, int stage, const void* x,
+                    void* F, const void* G, void* V, hipStream_t st) {
   CGemmBases b{};
   b.p[kBaseFactors] = const_cast<void*>(s.plan.factors);
   b.p[kBaseScratch] = p.scratch;
@@ -341,7 +342,7 @@ fmm_status mrhs_run(const MrhsPlan& p, const PrecSlot& s, int variant, int stage
   b.p[kBaseF] = F;
   b.p[kBaseG] = const_cast<void*>(G);
   b.p[kBaseV] = V;
-  if (stage != 0) TFMM_HIP(launch_zero_c64(V, s.plan.n_basis * p.nrhs, st));
+  if (stage != 0) TFMM_HIP(launch_zero_cplx(elem_bytes, V, s.plan.n_basis * p.nrhs, st));
   for (const MrhsChunk& ch : p.chunks)
     for (int j = 0; j < 4; ++j) TFMM_HIP(launch_cgemm(variant, ch.probs, ch.tiles[stage][j], ch.n_tiles[stage][j], b, st));
   return FMM_OK;

@@ -1,11 +1,14 @@
 """GPU parity of the multi-right-hand-side (matrix-core) path against the FP64 oracle.
 
 The path runs each contraction of the Tucker aggregation / disaggregation as a grouped
-complex GEMM on the MFMA units: FP32 (FMM_C64 with an even nrhs >= 8), or with the
-operands split into bf16 pieces (FMM_BF16X2: hi + lo, FMM_BF16X3: hi + mid + lo).
+complex GEMM on the MFMA units: FP64 (FMM_C128 with an even nrhs >= 8), FP32 (FMM_C64
+with an even nrhs >= 8), or with the operands split into bf16 pieces (FMM_BF16X2:
+hi + lo, FMM_BF16X3: hi + mid + lo).
 
 Tolerances, relative L2 over all outputs and max error relative to the largest
 reference entry:
+  - FP64: 1e-11, the bound of the FP64 streaming kernels (unit roundoff 1.1e-16 over
+    sums of a few thousand terms, with margin).
   - FP32 and BF16x3: 1e-5, the single-precision target of the method (sums of a few
     thousand terms with unit roundoff 6e-8).
   - BF16x2: each operand v = hi + lo carries a representation error below 2^-17 |v|
@@ -29,9 +32,10 @@ pytestmark = pytest.mark.gpu
 T = pytest.importorskip("paper_2103_05822_amd")
 
 C64 = np.complex64
-TOL = {T.FMM_C64: (1e-5, 1e-5), T.FMM_BF16X2: (4e-5, 1e-4), T.FMM_BF16X3: (1e-5, 1e-5)}
-PRECS = [T.FMM_C64, T.FMM_BF16X2, T.FMM_BF16X3]
-PIDS = ["c64", "bf16x2", "bf16x3"]
+TOL = {T.FMM_C128: (1e-11, 1e-11), T.FMM_C64: (1e-5, 1e-5), T.FMM_BF16X2: (4e-5, 1e-4), T.FMM_BF16X3: (1e-5, 1e-5)}
+CDT = {T.FMM_C128: np.complex128, T.FMM_C64: C64, T.FMM_BF16X2: C64, T.FMM_BF16X3: C64}
+PRECS = [T.FMM_C128, T.FMM_C64, T.FMM_BF16X2, T.FMM_BF16X3]
+PIDS = ["c128", "c64", "bf16x2", "bf16x3"]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -130,10 +134,10 @@ def test_mrhs_ragged_layout(prec, rank_mode, nrhs):
     v_ref = pr.disaggregate_all("tucker", tuck, lay.offsets, gin)
     H = Handle(lay, tuck, prec)
     try:
-        F = dev(np.zeros(f_ref.shape, C64))
-        V = dev(np.zeros(v_ref.shape, C64))
-        T.fmm_tucker_aggregate(H.h, prec, nrhs, dev(x, C64), F)
-        T.fmm_tucker_disaggregate(H.h, prec, nrhs, dev(gin, C64), V)
+        F = dev(np.zeros(f_ref.shape, CDT[prec]))
+        V = dev(np.zeros(v_ref.shape, CDT[prec]))
+        T.fmm_tucker_aggregate(H.h, prec, nrhs, dev(x, CDT[prec]), F)
+        T.fmm_tucker_disaggregate(H.h, prec, nrhs, dev(gin, CDT[prec]), V)
         check(prec, host(F), host(V), f_ref, v_ref)
     finally:
         H.close()
@@ -150,14 +154,14 @@ def test_mrhs_paper_grid(prec):
     v_ref = pr.disaggregate_all("tucker", tuck, lay.offsets, gin)
     H = Handle(lay, tuck, prec)
     try:
-        xd, gd = dev(x, C64), dev(gin, C64)
-        F = dev(np.zeros(f_ref.shape, C64))
-        V = dev(np.zeros(v_ref.shape, C64))
+        xd, gd = dev(x, CDT[prec]), dev(gin, CDT[prec])
+        F = dev(np.zeros(f_ref.shape, CDT[prec]))
+        V = dev(np.zeros(v_ref.shape, CDT[prec]))
         T.fmm_tucker_pass(H.h, prec, nrhs, xd, F, gd, V)
         Fp, Vp = host(F), host(V)
         check(prec, Fp, Vp, f_ref, v_ref)
-        F2 = dev(np.zeros(f_ref.shape, C64))
-        V2 = dev(np.zeros(v_ref.shape, C64))
+        F2 = dev(np.zeros(f_ref.shape, CDT[prec]))
+        V2 = dev(np.zeros(v_ref.shape, CDT[prec]))
         T.fmm_tucker_aggregate(H.h, prec, nrhs, xd, F2)
         T.fmm_tucker_disaggregate(H.h, prec, nrhs, gd, V2)
         # the merged pass runs the same tiles with the same arithmetic: bitwise equal
@@ -167,29 +171,32 @@ def test_mrhs_paper_grid(prec):
         H.close()
 
 
-def test_mrhs_matches_streaming_fp32():
-    """FMM_C64 with 8 RHS (matrix cores) against the same precision's streaming kernels
-    (odd nrhs = 7 on the first seven columns)."""
+@pytest.mark.parametrize("prec", [T.FMM_C128, T.FMM_C64], ids=["c128", "c64"])
+def test_mrhs_matches_streaming(prec):
+    """8 RHS (matrix cores) against the same precision's streaming kernels (odd nrhs = 7
+    on the first seven columns)."""
     lay = ragged_layout(7, 13)
     tuck = random_tucker(lay, 77)
     x, gin = inputs(lay, 8, 8)
-    banner("mrhs vs streaming c64")
-    H = Handle(lay, tuck, T.FMM_C64)
+    banner("mrhs vs streaming prec=%d" % prec)
+    cd = CDT[prec]
+    H = Handle(lay, tuck, prec)
     try:
-        F8 = dev(np.zeros((lay.n_groups, 2, lay.n_dir, 8), C64))
-        V8 = dev(np.zeros((lay.n_basis, 8), C64))
-        T.fmm_tucker_pass(H.h, T.FMM_C64, 8, dev(x, C64), F8, dev(gin, C64), V8)
-        F7 = dev(np.zeros((lay.n_groups, 2, lay.n_dir, 7), C64))
-        V7 = dev(np.zeros((lay.n_basis, 7), C64))
-        T.fmm_tucker_pass(H.h, T.FMM_C64, 7, dev(x[:, :7], C64), F7, dev(gin[..., :7], C64), V7)
+        F8 = dev(np.zeros((lay.n_groups, 2, lay.n_dir, 8), cd))
+        V8 = dev(np.zeros((lay.n_basis, 8), cd))
+        T.fmm_tucker_pass(H.h, prec, 8, dev(x, cd), F8, dev(gin, cd), V8)
+        F7 = dev(np.zeros((lay.n_groups, 2, lay.n_dir, 7), cd))
+        V7 = dev(np.zeros((lay.n_basis, 7), cd))
+        T.fmm_tucker_pass(H.h, prec, 7, dev(x[:, :7], cd), F7, dev(gin[..., :7], cd), V7)
         a, b = host(F8)[..., :7], host(F7)
         c, d = host(V8)[..., :7], host(V7)
-        assert l2_rel(a, b) < 1e-5 and l2_rel(c, d) < 1e-5
+        tol = TOL[prec][0]
+        assert l2_rel(a, b) < tol and l2_rel(c, d) < tol
     finally:
         H.close()
 
 
-@pytest.mark.parametrize("prec", [T.FMM_C64, T.FMM_BF16X2], ids=["c64", "bf16x2"])
+@pytest.mark.parametrize("prec", [T.FMM_C128, T.FMM_C64, T.FMM_BF16X2], ids=["c128", "c64", "bf16x2"])
 def test_mrhs_graph_replays(prec):
     """The captured pass (zero kernel + grouped launches) replayed several times, with
     eager work and synchronisations between replays; every replay equals the eager pass."""
@@ -201,9 +208,9 @@ def test_mrhs_graph_replays(prec):
     banner("mrhs graph prec=%d" % prec)
     H = Handle(lay, tuck, prec)
     try:
-        xd, gd = dev(x, C64), dev(gin, C64)
-        F = dev(np.zeros((lay.n_groups, 2, lay.n_dir, nrhs), C64))
-        V = dev(np.zeros((lay.n_basis, nrhs), C64))
+        xd, gd = dev(x, CDT[prec]), dev(gin, CDT[prec])
+        F = dev(np.zeros((lay.n_groups, 2, lay.n_dir, nrhs), CDT[prec]))
+        V = dev(np.zeros((lay.n_basis, nrhs), CDT[prec]))
         T.fmm_tucker_pass(H.h, prec, nrhs, xd, F, gd, V)
         Fe, Ve = host(F), host(V)
         s = torch.cuda.Stream()
@@ -221,7 +228,7 @@ def test_mrhs_graph_replays(prec):
         H.close()
 
 
-@pytest.mark.parametrize("prec", [T.FMM_C64, T.FMM_BF16X3], ids=["c64", "bf16x3"])
+@pytest.mark.parametrize("prec", [T.FMM_C128, T.FMM_C64, T.FMM_BF16X3], ids=["c128", "c64", "bf16x3"])
 def test_mrhs_tune(prec):
     """The autotuner picks a configuration; later calls with that nrhs use it and stay
     within tolerance."""
@@ -233,13 +240,13 @@ def test_mrhs_tune(prec):
     banner("mrhs tune prec=%d" % prec)
     H = Handle(lay, tuck, prec)
     try:
-        xd, gd = dev(x, C64), dev(gin, C64)
-        F = dev(np.zeros(f_ref.shape, C64))
-        V = dev(np.zeros(v_ref.shape, C64))
+        xd, gd = dev(x, CDT[prec]), dev(gin, CDT[prec])
+        F = dev(np.zeros(f_ref.shape, CDT[prec]))
+        V = dev(np.zeros(v_ref.shape, CDT[prec]))
         r = T.fmm_tucker_tune(H.h, prec, nrhs, xd, F, gd, V)
         print("  tuned:", r, flush=True)
         assert r["path"] in (0, 1) and r["ms"] > 0
-        if prec != T.FMM_C64:
+        if prec in (T.FMM_BF16X2, T.FMM_BF16X3):
             assert r["path"] == 1
         F.zero_()
         V.zero_()
@@ -299,9 +306,9 @@ def test_mrhs_svd_factors(prec, rank_mode, nrhs):
     v_ref = pr.disaggregate_all("svd", svd, lay.offsets, gin)
     H = Handle(lay, tuck, prec)
     try:
-        F = dev(np.zeros(f_ref.shape, C64))
-        V = dev(np.zeros(v_ref.shape, C64))
-        T.fmm_tucker_pass(H.h, prec, nrhs, dev(x, C64), F, dev(gin, C64), V)
+        F = dev(np.zeros(f_ref.shape, CDT[prec]))
+        V = dev(np.zeros(v_ref.shape, CDT[prec]))
+        T.fmm_tucker_pass(H.h, prec, nrhs, dev(x, CDT[prec]), F, dev(gin, CDT[prec]), V)
         check(prec, host(F), host(V), f_ref, v_ref)
     finally:
         H.close()
@@ -321,9 +328,9 @@ def test_mrhs_svd_and_tucker_groups_in_one_pass(prec):
     v_ref = pr.disaggregate_all("tucker", tuck, lay.offsets, gin)
     H = Handle(lay, tuck, prec)
     try:
-        F = dev(np.zeros(f_ref.shape, C64))
-        V = dev(np.zeros(v_ref.shape, C64))
-        T.fmm_tucker_pass(H.h, prec, nrhs, dev(x, C64), F, dev(gin, C64), V)
+        F = dev(np.zeros(f_ref.shape, CDT[prec]))
+        V = dev(np.zeros(v_ref.shape, CDT[prec]))
+        T.fmm_tucker_pass(H.h, prec, nrhs, dev(x, CDT[prec]), F, dev(gin, CDT[prec]), V)
         check(prec, host(F), host(V), f_ref, v_ref)
     finally:
         H.close()
