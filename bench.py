@@ -56,7 +56,7 @@ def parse():
     p.add_argument("--no-dense", action="store_true", help="Tucker stages only (profiling runs)")
     p.add_argument("--nrhs", type=int, default=None,
                    help="right-hand sides of the multi-RHS section (default: the workload's, else 64; 0: skip)")
-    p.add_argument("--mrhs-precs", default="c64,bf16x2,bf16x3",
+    p.add_argument("--mrhs-precs", default="c128,c64,bf16x2,bf16x3",
                    help="precisions of the multi-RHS section (c128, c64, bf16x2, bf16x3)")
     p.add_argument("--no-tune", action="store_true",
                    help="multi-RHS section: default kernel choice instead of the autotuner (profiling runs)")
