@@ -251,6 +251,19 @@ def main():
         stages += [("dense_agg_f64", lambda: T.fmm_dense_aggregate(dplan, T.FMM_C128, dense, 1, x64, F64)),
                    ("dense_disagg_f64", lambda: T.fmm_dense_disaggregate(dplan, T.FMM_C128, dense, 1, g64, V64))]
 
+    # first launch of each stage, alone and before the warm-up: device time and host
+    # wall time to completion (the graph's first replay includes its upload)
+    first_ms = {}
+    for name, fn in stages:
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        tw = time.perf_counter()
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        first_ms[name] = {"gpu": round(a.elapsed_time(b), 4), "wall": round((time.perf_counter() - tw) * 1e3, 4)}
+
     # ---------------------------------------------------------------- timed region
     for _ in range(args.warmup):
         for _, fn in stages:
@@ -324,6 +337,7 @@ def main():
                    "gamma": w.gamma, "nrhs": 1, "tucker_storage": "complex64", "dense_storage": "complex128"},
         "tucker_pass_ms": round(tucker_ms, 4),
         "stage_ms": {k: round(v, 4) for k, v in ms.items()},
+        "first_launch_ms": first_ms,
         "stage_GBps": {k: round(v, 1) for k, v in gbs.items()},
         "roofline": {"bound": "hbm", "kernel": "tucker_pass_kernel<float> (+ V zeroing)", "achieved": round(gbs[dom], 1),
                      "peak": HBM_PEAK_GBS,
@@ -721,16 +735,19 @@ def oracle_checks(args, w, verts, tris, lay, x, gin, F32h, V32h, F64h, V64h, mr_
         if nbytes >= 2e9:
             break
     nbytes *= 2   # aggregation and disaggregation each read the factors once
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        for g, pair in tgroups:
-            lo, hi = int(P.offsets[g]), int(P.offsets[g + 1])
-            pr.tucker_aggregate(pair, x[lo:hi])
-            pr.tucker_disaggregate(pair, gin[g])
-        reps += 1
-        if time.perf_counter() - t0 > args.cpu_seconds:
-            break
-    dt = (time.perf_counter() - t0) / reps
+
+    def timed_passes(budget):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            for g, pair in tgroups:
+                lo, hi = int(P.offsets[g]), int(P.offsets[g + 1])
+                pr.tucker_aggregate(pair, x[lo:hi])
+                pr.tucker_disaggregate(pair, gin[g])
+            reps += 1
+            if time.perf_counter() - t0 > budget:
+                return reps, (time.perf_counter() - t0) / reps
+
+    reps, dt = timed_passes(args.cpu_seconds)
     try:
         from threadpoolctl import threadpool_info
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
@@ -743,6 +760,17 @@ def oracle_checks(args, w, verts, tris, lay, x, gin, F32h, V32h, F64h, V64h, mr_
                                      "groups), %d passes in %.1f s" %
                                      (tgroups[-1][0], nbytes / 2 / 1e9, rt_m, rp_m, rb_frac, reps, reps * dt)}
     log("cpu baseline: %s" % out["cpu_baseline"])
+    # the same sample on one BLAS thread
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:
+        threadpool_limits = None
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            reps1, dt1 = timed_passes(args.cpu_seconds / 2)
+        out["cpu_baseline_1thread"] = {"value": round(nbytes / dt1 / 1e9, 3), "unit": "GB/s", "cores": 1,
+                                       "kind": "oracle", "passes": reps1}
+        log("cpu baseline, one thread: %s" % out["cpu_baseline_1thread"])
     return out
 
 

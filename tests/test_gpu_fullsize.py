@@ -3,12 +3,13 @@ sphere (939,870 RWG, 1034 groups, 38 x 75 grid, gamma = 1e-6, 64 RHS), the 20-la
 batching sphere at its smallest and largest boxes (0.5 and 4 lambda, 64 RHS) and the
 45-lambda sphere (2,301,870 RWG, gamma = 1e-5, 32 RHS).  Far-fields are filled and
 compressed on the GPU group chunk by group chunk, the FP32 pass is replayed from a
-captured graph and the BF16x2 matrix-core pass runs at the workload's RHS count; both
-are checked against the oracle's dense FP64 products on sampled groups (the largest
-and three seeded draws), which the oracle computes one group at a time.
+captured graph and the BF16x2 and FP64 matrix-core passes run at the workload's RHS
+count; all are checked against the oracle's dense FP64 products on sampled groups (the
+largest and three seeded draws), which the oracle computes one group at a time.
 
 Bound: the compression error gamma ||A||_F ||x|| per tensor plus the arithmetic's
-(FP32: 1e-5 relative; BF16x2: 4e-5 relative, as in the multi-RHS parity tests).
+(FP32: 1e-5 relative; BF16x2: 4e-5 relative, as in the multi-RHS parity tests; FP64:
+1e-10 relative).
 """
 import numpy as np
 import pytest
@@ -94,6 +95,23 @@ def test_full_size_sampled_groups(w, R, n_basis, n_groups):
                           torch.from_numpy(gr).to("cuda", torch.complex64), Vr)
         torch.cuda.synchronize()
         offs = lay.offsets
+        nb = np.diff(offs)
+        sample = sorted({int(np.argmax(nb))} | set(int(g) for g in synth.rng(4).choice(G, size=3, replace=False)))
+        bf = {g: (Fr[g].cpu().numpy(), Vr[int(offs[g]):int(offs[g + 1])].cpu().numpy()) for g in sample}
+        del Fr, Vr, ar2
+        torch.cuda.empty_cache()
+
+        banner("full size %s: FP64 matrix-core pass, %d right-hand sides" % (w.name, R))
+        _, nbytes = T.fmm_tucker_storage_bytes(h, T.FMM_C128)
+        ar3 = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        T.fmm_tucker_upload(h, T.FMM_C128, ar3)
+        Fd = torch.empty((G, 2, nd, R), dtype=torch.complex128, device="cuda")
+        Vd = torch.empty((N, R), dtype=torch.complex128, device="cuda")
+        T.fmm_tucker_pass(h, T.FMM_C128, R, torch.from_numpy(xr.astype(np.complex128)).to("cuda"), Fd,
+                          torch.from_numpy(gr.astype(np.complex128)).to("cuda"), Vd)
+        torch.cuda.synchronize()
+        fp64 = {g: (Fd[g].cpu().numpy(), Vd[int(offs[g]):int(offs[g + 1])].cpu().numpy()) for g in sample}
+        del Fd, Vd, ar3
     finally:
         if h:
             T.fmm_tucker_destroy(h)
@@ -102,8 +120,7 @@ def test_full_size_sampled_groups(w, R, n_basis, n_groups):
     banner("full size %s: oracle on sampled groups" % w.name)
     P = geo.Problem(v, t, w.origin, w.box, w.boxes_per_axis, w.n_theta, w.n_phi)
     assert np.array_equal(P.offsets, offs)
-    nb = P.group_sizes()
-    sample = sorted({int(np.argmax(nb))} | set(int(g) for g in synth.rng(4).choice(G, size=3, replace=False)))
+    assert np.array_equal(P.group_sizes(), nb)
     for g in sample:
         lo, hi = int(offs[g]), int(offs[g + 1])
         blk = ff.farfield_group(P, g)
@@ -117,11 +134,12 @@ def test_full_size_sampled_groups(w, R, n_basis, n_groups):
         assert np.linalg.norm(V1[lo:hi] - vd) <= vbound, g
         fr = pr.dense_aggregate(blk, xr[lo:hi].astype(np.complex128))
         vr = pr.dense_disaggregate(blk, gr[g].astype(np.complex128))
-        Fg, Vg = Fr[g].cpu().numpy(), Vr[lo:hi].cpu().numpy()
-        for a in range(2):
-            bound = w.gamma * na[a] * np.linalg.norm(xr[lo:hi]) + 4e-5 * np.linalg.norm(fr[a])
-            assert np.linalg.norm(Fg[a] - fr[a]) <= bound, (g, a)
-        vbound = sum(w.gamma * na[a] * np.linalg.norm(gr[g, a]) for a in range(2)) + 4e-5 * np.linalg.norm(vr)
-        assert np.linalg.norm(Vg - vr) <= vbound, g
-        print("  group %d (n_beta %d): F err %.2e, V err %.2e, BF16x2 F err %.2e" %
-              (g, hi - lo, pr.rel_err(F1[g], fd), pr.rel_err(V1[lo:hi], vd), pr.rel_err(Fg, fr)), flush=True)
+        for tag, (Fg, Vg), rel in (("bf16x2", bf[g], 4e-5), ("fp64", fp64[g], 1e-10)):
+            for a in range(2):
+                bound = w.gamma * na[a] * np.linalg.norm(xr[lo:hi]) + rel * np.linalg.norm(fr[a])
+                assert np.linalg.norm(Fg[a] - fr[a]) <= bound, (tag, g, a)
+            vbound = sum(w.gamma * na[a] * np.linalg.norm(gr[g, a]) for a in range(2)) + rel * np.linalg.norm(vr)
+            assert np.linalg.norm(Vg - vr) <= vbound, (tag, g)
+        print("  group %d (n_beta %d): F err %.2e, V err %.2e, BF16x2 F err %.2e, FP64 F err %.2e" %
+              (g, hi - lo, pr.rel_err(F1[g], fd), pr.rel_err(V1[lo:hi], vd), pr.rel_err(bf[g][0], fr),
+               pr.rel_err(fp64[g][0], fr)), flush=True)
