@@ -66,7 +66,7 @@ typedef enum {
  * (group, polarisation, right-hand side), factors streamed from HBM once per
  * right-hand side; 64, 128, 256 or 512 threads by the mean item size, or as tuned;
  * the environment variable TUCKFMM_STREAM_THREADS, read at upload, fixes the
- * default) for an odd nrhs or nrhs < 8, and the matrix-core products otherwise (FP64
+ * default) for an odd nrhs, and the matrix-core products for an even nrhs (FP64
  * MFMA for FMM_C128, FP32 MFMA for FMM_C64), unless fmm_tucker_tune chose
  * differently for that nrhs.  The matrix-core path computes every contraction of
  * Section II.C as one grouped complex GEMM over all (group, polarisation) items for a

@@ -212,32 +212,36 @@ __device__ __forceinline__ void store_f32(const CGemm& p, const Stage<float2>& s
 
 // Lane (mi, kb) of wavefront w: rows 16w + mi.  The real K index of instruction
 // (h, s) is 16h + 4kb + s (a permutation of the step's 32 real indices, applied
-// identically to A and B); B column lane mi covers real column 16t + mi.  (The MFMA
-// sequence is straight-line code: a branch around it would make the compiler move
-// the accumulators between register files.)
-__device__ __forceinline__ void mma_f32(const LdsF32& L, int w, int lane, floatx4 (&acc)[kNT]) {
+// identically to A and B); B column lane mi covers real column 16t + mi.  Only the
+// NTE accumulators (16 real columns each) that hold columns of the product run: a
+// product of N complex columns needs ceil(N / 8).  (The MFMA sequence is
+// straight-line code: a branch around it would make the compiler move the
+// accumulators between register files.)
+template <int NTE>
+__device__ __forceinline__ void mma_f32(const LdsF32& L, int w, int lane, floatx4 (&acc)[NTE]) {
   const int mi = lane % 16, kb = lane / 16;
+  constexpr int kG = NTE < 4 ? NTE : 4;  // accumulators per group of independent MFMAs
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const float4 a = *reinterpret_cast<const float4*>(&L.a[(16 * w + mi) * kAS + 8 * h + 2 * kb]);
     const float av[4] = {a.x, a.y, a.z, a.w};
 #pragma unroll
-    for (int t0 = 0; t0 < kNT; t0 += kNT / 2) {  // two halves: four independent accumulators each
-      float2 b0[kNT / 2], b1[kNT / 2];
+    for (int t0 = 0; t0 < NTE; t0 += kG) {
+      float2 b0[kG], b1[kG];
 #pragma unroll
-      for (int u = 0; u < kNT / 2; ++u) {
+      for (int u = 0; u < kG; ++u) {
         const int col = 16 * (t0 + u) + mi;  // = 2 (complex column) + q
         b0[u] = L.b[(8 * h + 2 * kb) * kXS + col];
         b1[u] = L.b[(8 * h + 2 * kb + 1) * kXS + col];
       }
 #pragma unroll
-      for (int u = 0; u < kNT / 2; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0], b0[u].x, acc[t0 + u], 0, 0, 0);
+      for (int u = 0; u < kG; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0], b0[u].x, acc[t0 + u], 0, 0, 0);
 #pragma unroll
-      for (int u = 0; u < kNT / 2; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[1], b0[u].y, acc[t0 + u], 0, 0, 0);
+      for (int u = 0; u < kG; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[1], b0[u].y, acc[t0 + u], 0, 0, 0);
 #pragma unroll
-      for (int u = 0; u < kNT / 2; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2], b1[u].x, acc[t0 + u], 0, 0, 0);
+      for (int u = 0; u < kG; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2], b1[u].x, acc[t0 + u], 0, 0, 0);
 #pragma unroll
-      for (int u = 0; u < kNT / 2; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[3], b1[u].y, acc[t0 + u], 0, 0, 0);
+      for (int u = 0; u < kG; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[3], b1[u].y, acc[t0 + u], 0, 0, 0);
     }
   }
 }
@@ -268,30 +272,32 @@ __device__ __forceinline__ void store_f64(const CGemm& p, const Stage<double2>& 
   }
 }
 
-__device__ __forceinline__ void mma_f64(const LdsF64& L, int w, int lane, doublex4 (&acc)[kNT]) {
+template <int NTE>
+__device__ __forceinline__ void mma_f64(const LdsF64& L, int w, int lane, doublex4 (&acc)[NTE]) {
   const int mi = lane % 16, kb = lane / 16;
+  constexpr int kG = NTE < 4 ? NTE : 4;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const double2* pa = &L.a[(16 * w + mi) * kAS + 8 * h + 2 * kb];
     const double2 a0 = pa[0], a1 = pa[1];
     const double av[4] = {a0.x, a0.y, a1.x, a1.y};
 #pragma unroll
-    for (int t0 = 0; t0 < kNT; t0 += kNT / 2) {
-      double2 b0[kNT / 2], b1[kNT / 2];
+    for (int t0 = 0; t0 < NTE; t0 += kG) {
+      double2 b0[kG], b1[kG];
 #pragma unroll
-      for (int u = 0; u < kNT / 2; ++u) {
+      for (int u = 0; u < kG; ++u) {
         const int col = 16 * (t0 + u) + mi;
         b0[u] = L.b[(8 * h + 2 * kb) * kXS + col];
         b1[u] = L.b[(8 * h + 2 * kb + 1) * kXS + col];
       }
 #pragma unroll
-      for (int u = 0; u < kNT / 2; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0], b0[u].x, acc[t0 + u], 0, 0, 0);
+      for (int u = 0; u < kG; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0], b0[u].x, acc[t0 + u], 0, 0, 0);
 #pragma unroll
-      for (int u = 0; u < kNT / 2; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1], b0[u].y, acc[t0 + u], 0, 0, 0);
+      for (int u = 0; u < kG; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1], b0[u].y, acc[t0 + u], 0, 0, 0);
 #pragma unroll
-      for (int u = 0; u < kNT / 2; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[2], b1[u].x, acc[t0 + u], 0, 0, 0);
+      for (int u = 0; u < kG; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[2], b1[u].x, acc[t0 + u], 0, 0, 0);
 #pragma unroll
-      for (int u = 0; u < kNT / 2; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[3], b1[u].y, acc[t0 + u], 0, 0, 0);
+      for (int u = 0; u < kG; ++u) acc[t0 + u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[3], b1[u].y, acc[t0 + u], 0, 0, 0);
     }
   }
 }
@@ -385,22 +391,29 @@ __device__ __forceinline__ void mma_pair(const bf16x8 (&ap)[NP], const bf16x8 (&
   acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[0], bp[0], acc, 0, 0, 0);
 }
 
-template <int NP>
-__device__ __forceinline__ void mma_bf16(const LdsBf16<NP>& L, int w, int lane, floatx4 (&acc)[kNT]) {
+template <int NP, int NTE>
+__device__ __forceinline__ void mma_bf16(const LdsBf16<NP>& L, int w, int lane, floatx4 (&acc)[NTE]) {
   const int mi = lane % 16, kb = lane / 16;
   bf16x8 ap[NP];
 #pragma unroll
   for (int u = 0; u < NP; ++u) ap[u] = *reinterpret_cast<const bf16x8*>(&L.a[u][(16 * w + mi) * kPR + 8 * kb]);
+  if constexpr (NTE == 1) {
+    bf16x8 b0[NP];
 #pragma unroll
-  for (int t = 0; t < kNT; t += 2) {
-    bf16x8 b0[NP], b1[NP];
+    for (int u = 0; u < NP; ++u) b0[u] = *reinterpret_cast<const bf16x8*>(&L.b[u][mi * kPR + 8 * kb]);
+    mma_pair<NP>(ap, b0, acc[0]);
+  } else {
 #pragma unroll
-    for (int u = 0; u < NP; ++u) {
-      b0[u] = *reinterpret_cast<const bf16x8*>(&L.b[u][(16 * t + mi) * kPR + 8 * kb]);
-      b1[u] = *reinterpret_cast<const bf16x8*>(&L.b[u][(16 * (t + 1) + mi) * kPR + 8 * kb]);
+    for (int t = 0; t < NTE; t += 2) {
+      bf16x8 b0[NP], b1[NP];
+#pragma unroll
+      for (int u = 0; u < NP; ++u) {
+        b0[u] = *reinterpret_cast<const bf16x8*>(&L.b[u][(16 * t + mi) * kPR + 8 * kb]);
+        b1[u] = *reinterpret_cast<const bf16x8*>(&L.b[u][(16 * (t + 1) + mi) * kPR + 8 * kb]);
+      }
+      mma_pair<NP>(ap, b0, acc[t]);
+      mma_pair<NP>(ap, b1, acc[t + 1]);
     }
-    mma_pair<NP>(ap, b0, acc[t]);
-    mma_pair<NP>(ap, b1, acc[t + 1]);
   }
 }
 
@@ -410,16 +423,16 @@ __device__ __forceinline__ void mma_bf16(const LdsBf16<NP>& L, int w, int lane, 
 // Lanes ni and ni ^ 1 hold the real and imaginary parts of one complex column: after
 // one exchange the even lane owns the rows of registers 0, 1 and the odd lane those
 // of registers 2, 3 as complex values.
-template <typename C2, typename ACC>
+template <typename C2, typename ACC, int NTE>
 __device__ __forceinline__ void epilogue(const CGemm& p, C2* Cp, int m0, int n0, int w, int lane,
-                                         const ACC (&acc)[kNT]) {
+                                         const ACC (&acc)[NTE]) {
   using R = decltype(C2{}.x);
   constexpr bool kF64 = sizeof(R) == 8;
   const int ni = lane % 16, g = lane / 16;
   const bool odd = ni & 1;
   const bool conj_out = p.flags & kConjC, atomic = p.flags & kAtomicC;
 #pragma unroll
-  for (int t = 0; t < kNT; ++t) {
+  for (int t = 0; t < NTE; ++t) {
     const R s0 = odd ? acc[t][0] : acc[t][2];
     const R s1 = odd ? acc[t][1] : acc[t][3];
     const R r0 = __shfl_xor(s0, 1);
@@ -492,15 +505,15 @@ __device__ __forceinline__ void store_stage(const CGemm& p, const Stage<typename
     store_bf16<VARIANT + 1>(p, st, L, tid);
 }
 
-template <int VARIANT>
+template <int VARIANT, int NTE>
 __device__ __forceinline__ void mma_stage(const typename VarOf<VARIANT>::lds& L, int w, int lane,
-                                          typename VarOf<VARIANT>::acc (&acc)[kNT]) {
+                                          typename VarOf<VARIANT>::acc (&acc)[NTE]) {
   if constexpr (VARIANT == 0)
-    mma_f32(L, w, lane, acc);
+    mma_f32<NTE>(L, w, lane, acc);
   else if constexpr (VARIANT == 3)
-    mma_f64(L, w, lane, acc);
+    mma_f64<NTE>(L, w, lane, acc);
   else
-    mma_bf16<VARIANT + 1>(L, w, lane, acc);
+    mma_bf16<VARIANT + 1, NTE>(L, w, lane, acc);
 }
 
 // One tile: column blocks n0 = tl.n0, tl.n0 + 64, ... below tl.n1, each a full K
@@ -509,8 +522,11 @@ __device__ __forceinline__ void mma_stage(const typename VarOf<VARIANT>::lds& L,
 // written to LDS after it.  A wavefront whose 16 rows lie past the problem's M
 // (ACTIVE = false: the angular products have M = r_theta, r_phi, n_theta or n_phi,
 // often well below the 64-row tile) still loads, stores and meets every barrier, but
-// issues no matrix-core work, leaving the matrix cores to the other wavefronts.
-template <int VARIANT, bool AVEC, bool ACTIVE>
+// issues no matrix-core work, leaving the matrix cores to the other wavefronts.  An
+// active wavefront runs NTE of the eight 16-column accumulators: the products with
+// N = rc columns (the beta and core contractions, most of the work) need only
+// ceil(rc / 8) of them when fewer than 64 right-hand sides share a chunk.
+template <int VARIANT, bool AVEC, bool ACTIVE, int NTE>
 __device__ __forceinline__ void run_tile(const CGemm& p, const CTile& tl, const typename VarOf<VARIANT>::c2* A,
                                          const typename VarOf<VARIANT>::c2* B, typename VarOf<VARIANT>::c2* Cp,
                                          typename VarOf<VARIANT>::lds& L) {
@@ -519,10 +535,10 @@ __device__ __forceinline__ void run_tile(const CGemm& p, const CTile& tl, const 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int nsteps = (p.K + kKC - 1) / kKC;
 
-  ACC acc[kNT];
+  ACC acc[NTE];
   if constexpr (ACTIVE) {
 #pragma unroll
-    for (int t = 0; t < kNT; ++t) acc[t] = ACC{0, 0, 0, 0};
+    for (int t = 0; t < NTE; ++t) acc[t] = ACC{0, 0, 0, 0};
   }
   Walk<C2> wk;
   walk_init(p, A, B, tl.m0, tid, wk);
@@ -545,7 +561,7 @@ __device__ __forceinline__ void run_tile(const CGemm& p, const CTile& tl, const 
         if (ns == 0) walk_block(p, nn0, tid, wk);
         load_stage<AVEC>(p, ns * kKC, wk, st);
       }
-      if constexpr (ACTIVE) mma_stage<VARIANT>(L, w, lane, acc);
+      if constexpr (ACTIVE) mma_stage<VARIANT, NTE>(L, w, lane, acc);
       if (more) {
         __syncthreads();  // every wavefront is done reading the step
         store_stage<VARIANT>(p, st, L, tid);
@@ -557,9 +573,27 @@ __device__ __forceinline__ void run_tile(const CGemm& p, const CTile& tl, const 
     if (n0 >= tl.n1) break;
     if constexpr (ACTIVE) {
 #pragma unroll
-      for (int t = 0; t < kNT; ++t) acc[t] = ACC{0, 0, 0, 0};
+      for (int t = 0; t < NTE; ++t) acc[t] = ACC{0, 0, 0, 0};
     }
   }
+}
+
+// The wavefront's rows (uniform per wavefront) and the product's width (uniform per
+// workgroup) select the instantiation.
+template <int VARIANT, bool AVEC>
+__device__ __forceinline__ void run_tile_of(const CGemm& p, const CTile& tl, const typename VarOf<VARIANT>::c2* A,
+                                            const typename VarOf<VARIANT>::c2* B, typename VarOf<VARIANT>::c2* Cp,
+                                            typename VarOf<VARIANT>::lds& L) {
+  if (tl.m0 + 16 * (int)(threadIdx.x >> 6) >= p.M)
+    run_tile<VARIANT, AVEC, false, 1>(p, tl, A, B, Cp, L);
+  else if (p.N <= 8)
+    run_tile<VARIANT, AVEC, true, 1>(p, tl, A, B, Cp, L);
+  else if (p.N <= 16)
+    run_tile<VARIANT, AVEC, true, 2>(p, tl, A, B, Cp, L);
+  else if (p.N <= 32)
+    run_tile<VARIANT, AVEC, true, 4>(p, tl, A, B, Cp, L);
+  else
+    run_tile<VARIANT, AVEC, true, kNT>(p, tl, A, B, Cp, L);
 }
 
 template <int VARIANT>
@@ -574,26 +608,14 @@ __global__ __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(VarOf<VARIA
   const C2* B = base_ptr<C2>(bases, p.bbase);
   C2* Cp = base_ptr<C2>(bases, p.cbase);
   // paired 16-byte A loads (complex64): K-contiguous A with an even offset and row
-  // stride; the branch on the wavefront's rows is uniform per wavefront
-  const bool active = tl.m0 + 16 * (int)(threadIdx.x >> 6) < p.M;
+  // stride
   if constexpr (VARIANT == 3) {
-    if (active)
-      run_tile<VARIANT, false, true>(p, tl, A, B, Cp, L);
-    else
-      run_tile<VARIANT, false, false>(p, tl, A, B, Cp, L);
+    run_tile_of<VARIANT, false>(p, tl, A, B, Cp, L);
   } else {
-    const bool avec = p.lda_k == 1 && !((p.a | p.lda_m) & 1);
-    if (avec) {
-      if (active)
-        run_tile<VARIANT, true, true>(p, tl, A, B, Cp, L);
-      else
-        run_tile<VARIANT, true, false>(p, tl, A, B, Cp, L);
-    } else {
-      if (active)
-        run_tile<VARIANT, false, true>(p, tl, A, B, Cp, L);
-      else
-        run_tile<VARIANT, false, false>(p, tl, A, B, Cp, L);
-    }
+    if (p.lda_k == 1 && !((p.a | p.lda_m) & 1))
+      run_tile_of<VARIANT, true>(p, tl, A, B, Cp, L);
+    else
+      run_tile_of<VARIANT, false>(p, tl, A, B, Cp, L);
   }
 }
 

@@ -1,8 +1,8 @@
 """GPU parity of the multi-right-hand-side (matrix-core) path against the FP64 oracle.
 
 The path runs each contraction of the Tucker aggregation / disaggregation as a grouped
-complex GEMM on the MFMA units: FP64 (FMM_C128 with an even nrhs >= 8), FP32 (FMM_C64
-with an even nrhs >= 8), or with the operands split into bf16 pieces (FMM_BF16X2:
+complex GEMM on the MFMA units: FP64 (FMM_C128 with an even nrhs), FP32 (FMM_C64
+with an even nrhs), or with the operands split into bf16 pieces (FMM_BF16X2:
 hi + lo, FMM_BF16X3: hi + mid + lo).
 
 Tolerances, relative L2 over all outputs and max error relative to the largest
