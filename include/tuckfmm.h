@@ -62,13 +62,17 @@ typedef enum {
  *   FMM_BF16X3 as FMM_BF16X2 with three pieces (hi + mid + lo) and the six products
  *              down to order 2^-16 (FP32-level error).  Needs an even nrhs.
  *
- * Kernels.  FMM_C128 and FMM_C64 run the streaming kernels (one workgroup per
- * (group, polarisation, right-hand side), factors streamed from HBM once per
- * right-hand side; 64, 128, 256 or 512 threads by the mean item size, or as tuned;
- * the environment variable TUCKFMM_STREAM_THREADS, read at upload, fixes the
- * default) for an odd nrhs, and the matrix-core products for an even nrhs (FP64
- * MFMA for FMM_C128, FP32 MFMA for FMM_C64), unless fmm_tucker_tune chose
- * differently for that nrhs.  The matrix-core path computes every contraction of
+ * Kernels.  The streaming kernels run one workgroup per (group, polarisation,
+ * right-hand side) and stream the factors from HBM once per right-hand side; they take
+ * 64, 128, 256 or 512 threads by the mean item size, or as tuned (the environment
+ * variable TUCKFMM_STREAM_THREADS, read at upload, fixes the default).  Untuned,
+ * FMM_C128 and FMM_C64 run them for an odd nrhs and the matrix-core products (FP64
+ * and FP32 MFMA) for an even nrhs; fmm_tucker_tune may choose differently for an nrhs,
+ * and for FMM_C128 it also offers the matrix cores at an odd nrhs.  FMM_C128 takes
+ * the matrix cores at every nrhs when the layout's largest item does not fit the FP64
+ * streaming kernels' LDS (they keep an item's x_g or core-stage vector and its r_beta
+ * or angular intermediate there: about 10,000 complex128 values on 160 KB).  The
+ * matrix-core path computes every contraction of
  * Section II.C as one grouped complex GEMM over all (group, polarisation) items for a
  * chunk of right-hand sides (factors read once per chunk); it needs 16-byte aligned
  * vectors and keeps library-owned device tables and scratch per nrhs (freed by a new

@@ -299,6 +299,15 @@ fmm_status lds_check(size_t bytes) {
   return FMM_OK;
 }
 
+// Whether the FP64 streaming kernels fit the device's LDS for this slot's largest item.
+bool c128_streams(const PrecSlot& s) {
+  int dev = 0, lim = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return true;  // let the launch path report the device error
+  return tucker_lds_bytes<double>(s.plan.mx) <= (size_t)lim;
+}
+
 // Which kernels run a call with nrhs right-hand sides.
 struct Route {
   bool mfma = false;  // matrix-core products (else the streaming kernels)
@@ -306,6 +315,12 @@ struct Route {
   int tile_steps = 0, rhs_chunk = 0;
   int threads = 512;  // streaming kernels' workgroup size
 };
+
+// The matrix-core path takes complex64 data with an even nrhs only (paired 8-byte
+// values keep its 16-byte accesses aligned); complex128 values are 16-byte accesses by
+// themselves, so FMM_C128 can take any nrhs (when tuned so, or when its items do not
+// fit the streaming kernels).
+bool mfma_allows(fmm_prec prec, int nrhs) { return prec == FMM_C128 || nrhs % 2 == 0; }
 
 fmm_status route_of(const PrecSlot& s, fmm_prec prec, int nrhs, Route* r) {
   *r = Route{};
@@ -326,6 +341,10 @@ fmm_status route_of(const PrecSlot& s, fmm_prec prec, int nrhs, Route* r) {
       r->tile_steps = t.tile_steps;
       r->rhs_chunk = t.rhs_chunk;
     }
+  // FP64 items too large for the streaming kernels' LDS (an item's x_g or core-stage
+  // vector plus its r_beta or angular intermediate, in complex128) run on the matrix
+  // cores at any nrhs
+  if (prec == FMM_C128 && !r->mfma && !c128_streams(s)) r->mfma = true;
   return FMM_OK;
 }
 
@@ -754,9 +773,9 @@ extern "C" fmm_status fmm_tucker_tune(fmm_tucker_t h, fmm_prec prec, int32_t nrh
   // candidates: the streaming kernels (FP64, FP32) and the matrix-core products with
   // several tile sizes and right-hand-side chunks (even nrhs)
   std::vector<TuneChoice> cand;
-  if (!prec_is_split(prec))
+  if (!prec_is_split(prec) && (prec != FMM_C128 || c128_streams(*s)))
     for (int nt : {64, 128, 256, 512}) cand.push_back(TuneChoice{nrhs, 0, 0, 0, nt});
-  if (nrhs % 2 == 0) {
+  if (mfma_allows(prec, nrhs)) {
     std::vector<int> chunks{std::min<int>(nrhs, kMrhsDefaultChunk)};
     if (nrhs > 2 * kMrhsDefaultChunk) chunks.push_back(2 * kMrhsDefaultChunk);
     if (nrhs >= kMrhsDefaultChunk) chunks.push_back(kMrhsDefaultChunk / 2);
@@ -782,6 +801,11 @@ extern "C" fmm_status fmm_tucker_tune(fmm_tucker_t h, fmm_prec prec, int32_t nrh
   for (const TuneChoice& c : cand) {
     s->tuned.assign(1, c);
     st = run_stage(h, *s, prec, nrhs, 2, x, F, G, V, hs);  // warm-up (builds the tables)
+    if (st == FMM_ERR_UNSUPPORTED) {  // a candidate this layout cannot take
+      st = FMM_OK;
+      clear_error();
+      continue;
+    }
     if (st != FMM_OK) break;
     he = hipEventRecord(e0, hs);
     for (int i = 0; i < reps && st == FMM_OK; ++i) st = run_stage(h, *s, prec, nrhs, 2, x, F, G, V, hs);
@@ -800,6 +824,8 @@ extern "C" fmm_status fmm_tucker_tune(fmm_tucker_t h, fmm_prec prec, int32_t nrh
   (void)hipEventDestroy(e1);
   s->tuned = saved;
   if (st == FMM_OK && he != hipSuccess) st = fail(FMM_ERR_DEVICE, "tuning timer: %s", hipGetErrorString(he));
+  if (st == FMM_OK && best < 0.f)
+    st = fail(FMM_ERR_UNSUPPORTED, "no kernel runs precision %d with nrhs %d on this layout", (int)prec, nrhs);
   // free the tables of the losing candidates
   for (auto it = s->mrhs.begin(); it != s->mrhs.end();) {
     const bool old = std::find(before.begin(), before.end(), &*it) != before.end();

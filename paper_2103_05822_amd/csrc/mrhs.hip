@@ -18,7 +18,8 @@
 //
 // Workgroup tile: 64 rows x 64 complex columns (128 real), K in steps of 16 complex
 // values (32 real).  Four wavefronts, each owning 16 rows x 128 real columns = eight
-// 16 x 16 MFMA accumulators.  A workgroup walks its column blocks and K steps as one
+// 16 x 16 MFMA accumulators, of which a product of N < 64 columns runs only the
+// ceil(N / 8) its columns fill.  A workgroup walks its column blocks and K steps as one
 // flat pipeline: the global loads of step s + 1 are in flight while step s runs on the
 // matrix cores from LDS; conjugation, B expansion and the bf16 split happen when a
 // step is written to LDS (single buffered).

@@ -334,3 +334,63 @@ def test_mrhs_svd_and_tucker_groups_in_one_pass(prec):
         check(prec, host(F), host(V), f_ref, v_ref)
     finally:
         H.close()
+
+
+@pytest.mark.parametrize("nrhs", [3, 5])
+def test_mrhs_fp64_odd_nrhs(nrhs):
+    """FMM_C128 at an odd nrhs: the streaming kernels by default, then whatever the
+    autotuner picks (it also offers the matrix cores there, a complex128 value being a
+    16-byte access by itself); ragged groups against the oracle both times."""
+    lay = ragged_layout()
+    banner("mrhs c128 odd nrhs=%d" % nrhs)
+    tuck = random_tucker(lay, 80 + nrhs)
+    x, gin = inputs(lay, nrhs, 12)
+    f_ref = pr.aggregate_all("tucker", tuck, lay.offsets, x)
+    v_ref = pr.disaggregate_all("tucker", tuck, lay.offsets, gin)
+    H = Handle(lay, tuck, T.FMM_C128)
+    try:
+        F = dev(np.zeros(f_ref.shape, np.complex128))
+        V = dev(np.zeros(v_ref.shape, np.complex128))
+        T.fmm_tucker_pass(H.h, T.FMM_C128, nrhs, dev(x, np.complex128), F, dev(gin, np.complex128), V)
+        check(T.FMM_C128, host(F), host(V), f_ref, v_ref)
+        xd, gd = dev(x, np.complex128), dev(gin, np.complex128)
+        r = T.fmm_tucker_tune(H.h, T.FMM_C128, nrhs, xd, F, gd, V)
+        print("  tuned:", r, flush=True)
+        assert r["path"] in (0, 1) and r["ms"] > 0
+        F.zero_()
+        V.zero_()
+        T.fmm_tucker_pass(H.h, T.FMM_C128, nrhs, xd, F, gd, V)
+        check(T.FMM_C128, host(F), host(V), f_ref, v_ref)
+    finally:
+        H.close()
+
+
+def test_fp64_items_beyond_streaming_lds():
+    """A 64 x 127 grid with full angular ranks: an item's core-stage vector and angular
+    intermediate (8128 values each) need 260 KB of complex128 LDS in the FP64
+    streaming kernels, more than a workgroup may take.  FMM_C128 then runs on the
+    matrix cores at every nrhs, 1 included, and the autotuner offers only those;
+    FMM_C64 (130 KB) still streams."""
+    lay = T.Layout(64, 127, np.array([0, 3, 7]))
+    tuck = random_tucker(lay, 85, "full")
+    for prec in (T.FMM_C128, T.FMM_C64):
+        cd = CDT[prec]
+        H = Handle(lay, tuck, prec)
+        try:
+            for nrhs in (1, 3):
+                banner("large-item layout prec=%d nrhs=%d" % (prec, nrhs))
+                x, gin = inputs(lay, nrhs, 13)
+                if nrhs == 1:
+                    x, gin = x[:, 0], gin[..., 0]
+                f_ref = pr.aggregate_all("tucker", tuck, lay.offsets, x)
+                v_ref = pr.disaggregate_all("tucker", tuck, lay.offsets, gin)
+                F = dev(np.zeros(f_ref.shape, cd))
+                V = dev(np.zeros(v_ref.shape, cd))
+                T.fmm_tucker_pass(H.h, prec, nrhs, dev(x, cd), F, dev(gin, cd), V)
+                check(prec, host(F), host(V), f_ref, v_ref)
+            if prec == T.FMM_C128:
+                r = T.fmm_tucker_tune(H.h, prec, 1, dev(x, cd), F, dev(gin, cd), V)
+                print("  tuned:", r, flush=True)
+                assert r["path"] == 1
+        finally:
+            H.close()
