@@ -299,14 +299,6 @@ fmm_status lds_check(size_t bytes) {
   return FMM_OK;
 }
 
-// Whether the FP64 streaming kernels fit the device's LDS for this slot's largest item.
-bool c128_streams(const PrecSlot& s) {
-  int dev = 0, lim = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-    return true;  // let the launch path report the device error
-  return tucker_lds_bytes<double>(s.plan.mx) <= (size_t)lim;
-}
 
 // Which kernels run a call with nrhs right-hand sides.
 struct Route {
@@ -344,7 +336,7 @@ fmm_status route_of(const PrecSlot& s, fmm_prec prec, int nrhs, Route* r) {
   // FP64 items too large for the streaming kernels' LDS (an item's x_g or core-stage
   // vector plus its r_beta or angular intermediate, in complex128) run on the matrix
   // cores at any nrhs
-  if (prec == FMM_C128 && !r->mfma && !c128_streams(s)) r->mfma = true;
+  if (prec == FMM_C128 && !r->mfma && !s.streams) r->mfma = true;
   return FMM_OK;
 }
 
@@ -641,6 +633,8 @@ extern "C" fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* are
   hipStream_t s = static_cast<hipStream_t>(stream);
   TFMM_HIP(hipMemcpyAsync(arena, img.data(), img.size(), hipMemcpyHostToDevice, s));
   TFMM_HIP(hipStreamSynchronize(s));
+  int lds_lim = 0;
+  TFMM_HIP(hipDeviceGetAttribute(&lds_lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
 
   PrecSlot& sl = h->slot[prec];
   drop_graph(h);
@@ -661,6 +655,8 @@ extern "C" fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* are
       if (v == 64 || v == 128 || v == 256 || v == 512) sl.threads = v;
     }
   }
+  sl.streams = (prec == FMM_C128 ? tucker_lds_bytes<double>(P.mx) : tucker_lds_bytes<float>(P.mx)) <=
+               (size_t)lds_lim;
   sl.ready = true;
   sl.arena = static_cast<char*>(arena);
   sl.bytes = bytes;
@@ -773,7 +769,7 @@ extern "C" fmm_status fmm_tucker_tune(fmm_tucker_t h, fmm_prec prec, int32_t nrh
   // candidates: the streaming kernels (FP64, FP32) and the matrix-core products with
   // several tile sizes and right-hand-side chunks (even nrhs)
   std::vector<TuneChoice> cand;
-  if (!prec_is_split(prec) && (prec != FMM_C128 || c128_streams(*s)))
+  if (!prec_is_split(prec) && (prec != FMM_C128 || s->streams))
     for (int nt : {64, 128, 256, 512}) cand.push_back(TuneChoice{nrhs, 0, 0, 0, nt});
   if (mfma_allows(prec, nrhs)) {
     std::vector<int> chunks{std::min<int>(nrhs, kMrhsDefaultChunk)};

@@ -87,6 +87,7 @@ struct PrecSlot {
   TuckPlan plan;          // device pointers into the arena
   std::vector<TuckItem> items;      // host copy of the item table
   int threads = 512;                // default workgroup size of the streaming kernels
+  bool streams = true;              // the streaming kernels' LDS fits the largest item
   std::list<MrhsPlan> mrhs;         // built on first use per (nrhs, knobs); stable addresses
   std::vector<TuneChoice> tuned;
   void* part = nullptr;             // library-owned partial sums of split items (device)
