@@ -299,7 +299,6 @@ fmm_status lds_check(size_t bytes) {
   return FMM_OK;
 }
 
-
 // Which kernels run a call with nrhs right-hand sides.
 struct Route {
   bool mfma = false;  // matrix-core products (else the streaming kernels)
@@ -766,8 +765,9 @@ extern "C" fmm_status fmm_tucker_tune(fmm_tucker_t h, fmm_prec prec, int32_t nrh
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   TFMM_HIP(hipStreamIsCapturing(hs, &cs));
   if (cs != hipStreamCaptureStatusNone) return fail(FMM_ERR_STATE, "cannot tune inside a stream capture");
-  // candidates: the streaming kernels (FP64, FP32) and the matrix-core products with
-  // several tile sizes and right-hand-side chunks (even nrhs)
+  // candidates: the streaming kernels (FP64, FP32; FP64 only where its items fit their
+  // LDS) and the matrix-core products with several tile sizes and right-hand-side
+  // chunks (even nrhs; any nrhs for FP64)
   std::vector<TuneChoice> cand;
   if (!prec_is_split(prec) && (prec != FMM_C128 || s->streams))
     for (int nt : {64, 128, 256, 512}) cand.push_back(TuneChoice{nrhs, 0, 0, 0, nt});
