@@ -771,6 +771,7 @@ def oracle_checks(args, w, verts, tris, lay, x, gin, F32h, V32h, F64h, V64h, mr_
         out["cpu_baseline_1thread"] = {"value": round(nbytes / dt1 / 1e9, 3), "unit": "GB/s", "cores": 1,
                                        "kind": "oracle", "passes": reps1}
         log("cpu baseline, one thread: %s" % out["cpu_baseline_1thread"])
+    out["host_cpu_count"] = os.cpu_count()
     return out
 
 
