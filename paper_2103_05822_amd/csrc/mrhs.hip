@@ -470,9 +470,10 @@ __device__ __forceinline__ void epilogue(const CGemm& p, C2* Cp, int m0, int n0,
 // Per-variant types (LDS stage, complex element, accumulator) and the wavefronts per
 // SIMD the register allocation is held to.  More resident wavefronts hide more of the
 // operand-load latency.  FP32 and BF16x2 fit 4 (up from 3) and BF16x3 fits 3 (up from
-// 2), with the accumulators in VGPRs and no spills: the 64-RHS pass of the 30-lambda
-// sphere takes 5.5%, 5.5% and 9.5% less time.  FP64 would spill at 3 and keeps 2;
-// its new register allocation still saves 4.6%.
+// 2), with the accumulators in VGPRs: the 64-RHS pass of the 30-lambda sphere takes
+// 5.5%, 5.5% and 9.5% less time.  (With the narrow-product instantiations below,
+// BF16x2 spills 7 registers at 4, one reload per K step, which gives back 2%.)  FP64
+// would spill at 3 and keeps 2; its new register allocation still saves 4.6%.
 template <int VARIANT>
 struct VarOf {
   using lds = LdsBf16<VARIANT + 1>;
