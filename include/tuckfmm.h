@@ -67,8 +67,8 @@ typedef enum {
  * 64, 128, 256 or 512 threads by the mean item size, or as tuned (the environment
  * variable TUCKFMM_STREAM_THREADS, read at upload, fixes the default).  Untuned,
  * FMM_C128 and FMM_C64 run them for an odd nrhs and the matrix-core products (FP64
- * and FP32 MFMA) for an even nrhs; fmm_tucker_tune may choose differently for an nrhs,
- * and for FMM_C128 it also offers the matrix cores at an odd nrhs.  FMM_C128 takes
+ * and FP32 MFMA) for an even nrhs; fmm_tucker_tune may choose differently for an nrhs
+ * (it offers both paths at any nrhs for these two precisions).  FMM_C128 takes
  * the matrix cores at every nrhs when the layout's largest item does not fit the FP64
  * streaming kernels' LDS (they keep an item's x_g or core-stage vector and its r_beta
  * or angular intermediate there: about 10,000 complex128 values on 160 KB).  The

@@ -307,11 +307,12 @@ struct Route {
   int threads = 512;  // streaming kernels' workgroup size
 };
 
-// The matrix-core path takes complex64 data with an even nrhs only (paired 8-byte
-// values keep its 16-byte accesses aligned); complex128 values are 16-byte accesses by
-// themselves, so FMM_C128 can take any nrhs (when tuned so, or when its items do not
-// fit the streaming kernels).
-bool mfma_allows(fmm_prec prec, int nrhs) { return prec == FMM_C128 || nrhs % 2 == 0; }
+// Whether the matrix-core path may run nrhs right-hand sides.  Its paired 16-byte
+// loads read factor rows only, and vector operands are loaded and stored one value at
+// a time, so FMM_C64 and FMM_C128 take any nrhs (an odd one when tuned so, or for
+// FMM_C128 when its items do not fit the streaming kernels); the bf16 split
+// precisions are defined for an even nrhs.
+bool mfma_allows(fmm_prec prec, int nrhs) { return !prec_is_split(prec) || nrhs % 2 == 0; }
 
 fmm_status route_of(const PrecSlot& s, fmm_prec prec, int nrhs, Route* r) {
   *r = Route{};
@@ -377,7 +378,7 @@ fmm_status run_stage(fmm_tucker_t h, PrecSlot& s, fmm_prec prec, int nrhs, int s
     TFMM_HIP(launch_zero_rows(elem_bytes(prec), F, s.plan.zero_rows, s.plan.n_zero_rows,
                               (int64_t)L.ndir() * nrhs, hs));
   if (r.mfma) {
-    // 16-byte operand loads: with an even nrhs every row offset keeps this alignment
+    // the vectors' base addresses keep every complex value naturally aligned
     for (const void* p : {x, (const void*)F, G, (const void*)V})
       if (p && !aligned(p, 16)) return fail(FMM_ERR_ARG, "the matrix-core path needs 16-byte aligned vectors");
     MrhsPlan* mp = nullptr;
@@ -767,7 +768,7 @@ extern "C" fmm_status fmm_tucker_tune(fmm_tucker_t h, fmm_prec prec, int32_t nrh
   if (cs != hipStreamCaptureStatusNone) return fail(FMM_ERR_STATE, "cannot tune inside a stream capture");
   // candidates: the streaming kernels (FP64, FP32; FP64 only where its items fit their
   // LDS) and the matrix-core products with several tile sizes and right-hand-side
-  // chunks (even nrhs; any nrhs for FP64)
+  // chunks (any nrhs; an even one for the bf16 split precisions)
   std::vector<TuneChoice> cand;
   if (!prec_is_split(prec) && (prec != FMM_C128 || s->streams))
     for (int nt : {64, 128, 256, 512}) cand.push_back(TuneChoice{nrhs, 0, 0, 0, nt});

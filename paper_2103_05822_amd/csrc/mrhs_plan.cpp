@@ -269,10 +269,8 @@ fmm_status mrhs_get(PrecSlot& s, size_t elem_bytes, const Layout& L, int nrhs, i
                     MrhsPlan** out) {
   if (tile_steps <= 0) tile_steps = kMrhsDefaultSteps;
   if (rhs_chunk <= 0) rhs_chunk = kMrhsDefaultChunk;
-  // complex64 values are loaded in 16-byte pairs where the layout allows; complex128
-  // values are 16-byte loads by themselves
-  if (elem_bytes != 16 && (nrhs % 2 || rhs_chunk % 2))
-    return fail(FMM_ERR_UNSUPPORTED, "the complex64 matrix-core path needs an even nrhs");
+  // (any nrhs: the paired 16-byte loads read factor rows only; the callers keep the
+  // bf16 split precisions to an even nrhs)
   rhs_chunk = std::min(rhs_chunk, nrhs);
   for (auto& p : s.mrhs)
     if (p.nrhs == nrhs && p.tile_steps == tile_steps && p.rhs_chunk == rhs_chunk) {

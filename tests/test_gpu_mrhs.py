@@ -394,3 +394,30 @@ def test_fp64_items_beyond_streaming_lds():
                 assert r["path"] == 1
         finally:
             H.close()
+
+
+@pytest.mark.parametrize("prec", [T.FMM_C128, T.FMM_C64], ids=["c128", "c64"])
+def test_mrhs_tuned_odd_nrhs(prec):
+    """15 right-hand sides on the 38 x 75 grid: the autotuner picks the matrix cores over
+    fifteen streaming passes, and the tuned pass at that odd nrhs matches the oracle."""
+    lay, tuck = paper_grid_tucker(seed=35)
+    nrhs = 15
+    x, gin = inputs(lay, nrhs, 14)
+    f_ref = pr.aggregate_all("tucker", tuck, lay.offsets, x)
+    v_ref = pr.disaggregate_all("tucker", tuck, lay.offsets, gin)
+    banner("mrhs tuned odd nrhs prec=%d" % prec)
+    cd = CDT[prec]
+    H = Handle(lay, tuck, prec)
+    try:
+        xd, gd = dev(x, cd), dev(gin, cd)
+        F = dev(np.zeros(f_ref.shape, cd))
+        V = dev(np.zeros(v_ref.shape, cd))
+        r = T.fmm_tucker_tune(H.h, prec, nrhs, xd, F, gd, V)
+        print("  tuned:", r, flush=True)
+        assert r["path"] == 1 and r["rhs_chunk"] == nrhs
+        F.zero_()
+        V.zero_()
+        T.fmm_tucker_pass(H.h, prec, nrhs, xd, F, gd, V)
+        check(prec, host(F), host(V), f_ref, v_ref)
+    finally:
+        H.close()
