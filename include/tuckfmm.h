@@ -166,6 +166,26 @@ fmm_status fmm_geometry_boxes(fmm_geometry_t geom, int32_t* boxes_per_axis, int6
 fmm_status fmm_farfield_fill(fmm_geometry_t geom, int32_t first_group, int32_t count,
                              void* farfield, void* stream);
 
+/* Excitation vectors of plane waves, the right-hand side V of eq. (2) (Section II.A):
+ * for incident fields E^i(r) = e_hat_r exp(-j k k_hat_r . r) (unit amplitude, phase
+ * reference at the origin), Galerkin testing with the RWG functions gives
+ *     x[n][r] = < b_n, n x n x E^i_r > = - int_{S_n} b_n(r) . e_hat_r exp(-j k k_hat_r . r) dr
+ * (b_n is tangential, so n x n x E reduces to -E there).  Each triangle uses the same
+ * symmetric 3-point rule as fmm_farfield_fill; the result is the aggregation input
+ * x of eq. (3) for nrhs incident waves at once.
+ *   khat   host double [nrhs][3]  unit propagation directions (|k_hat| within 1e-6
+ *                                 of 1, else FMM_ERR_ARG)
+ *   epol   host double [nrhs][3]  polarisations (orthogonal to k_hat for a physical
+ *                                 wave; used as given)
+ *   prec   FMM_C128: x is complex128; any other precision: complex64 (each part of
+ *          the FP64 sum rounded to the nearest float)
+ *   x      device [N][nrhs], basis functions in group order, naturally aligned.
+ * FP64 arithmetic.  Uploads the geometry to the device on first use and keeps a
+ * small device table of the waves; synchronises the stream before reusing it, then
+ * runs asynchronously.  FMM_ERR_NUMERIC for a non-finite direction or polarisation. */
+fmm_status fmm_planewave_excitation(fmm_geometry_t geom, int32_t nrhs, const double* khat, const double* epol,
+                                    fmm_prec prec, void* x, void* stream);
+
 void fmm_geometry_destroy(fmm_geometry_t geom);
 
 /* ------------------------------------------------------------------ Tucker */
@@ -248,9 +268,18 @@ fmm_status fmm_tucker_layout(fmm_tucker_t h, fmm_layout* out);
 /* Ranks of every tensor: host int32 [n_groups][2][3] = (r_theta, r_phi, r_beta). */
 fmm_status fmm_tucker_ranks(fmm_tucker_t h, int32_t* ranks);
 
-/* Copy the FP64 factors of one (group, polarisation) into host complex128 buffers in
- * the paper's shapes (sizes from fmm_tucker_ranks). */
-fmm_status fmm_tucker_export(fmm_tucker_t h, int32_t group, int32_t alpha, double* core,
+/* Copy the factors of one (group, polarisation) of eq. (6) into host complex128
+ * buffers in the paper's shapes (sizes from fmm_tucker_ranks; any pointer may be NULL).
+ *   as_stored  FMM_C128: the handle's FP64 factors as they are.
+ *              FMM_C64, FMM_BF16X2, FMM_BF16X3: every real and imaginary part rounded
+ *              to the nearest float and widened back, i.e. exactly the complex64
+ *              values an upload of that precision stores (the bf16 pieces of the split
+ *              precisions are formed from these on chip).
+ * With as_stored = the upload's precision, a plain FP64 contraction of the exported
+ * factors (Fig. 2(b), Fig. 3(b)) is the exact result the compute calls approximate:
+ * their difference is the arithmetic error alone, free of the compression error.
+ * FMM_ERR_ARG for a bad group, alpha or precision; FMM_ERR_STATE if unset. */
+fmm_status fmm_tucker_export(fmm_tucker_t h, int32_t group, int32_t alpha, fmm_prec as_stored, double* core,
                              double* u_theta, double* u_phi, double* u_beta);
 
 /* Bytes of stored factors (paper's memory measure, Section III: core + 3 factors of

@@ -18,7 +18,9 @@ speed.  Each function cites the passage of the paper it follows:
   disaggregation (eq. (5), Fig. 3(a)), and the Tucker-format procedures of
   Section II.C (Fig. 2(b) and Fig. 3(b)).
 * :mod:`oracle.boxgrid` -- the spectra on the FMM-FFT box grid (eq. (3), eq. (5)).
+* :mod:`oracle.excitation` -- plane-wave excitation vectors, the right-hand side of
+  eq. (2), which the aggregation takes as its input.
 
 Readings of passages that are silent or garbled are listed in each module.
 """
-from . import geometry, farfield, hosvd, products, boxgrid  # noqa: F401
+from . import geometry, farfield, hosvd, products, boxgrid, excitation  # noqa: F401

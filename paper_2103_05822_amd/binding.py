@@ -20,7 +20,7 @@ __all__ = [
     "FMM_OK", "FMM_C128", "FMM_C64", "FMM_BF16X2", "FMM_BF16X3", "FmmError", "Layout", "exported_symbols",
     "fmm_last_error", "fmm_version", "fmm_device_count",
     "fmm_geometry_build", "fmm_geometry_info", "fmm_geometry_tables", "fmm_geometry_layout", "fmm_geometry_boxes",
-    "fmm_farfield_fill",
+    "fmm_farfield_fill", "fmm_planewave_excitation",
     "fmm_geometry_destroy", "fmm_tucker_create", "fmm_farfield_compress", "fmm_farfield_compress_svd",
     "fmm_tucker_set_group", "fmm_tucker_set_box_grid", "fmm_tucker_save", "fmm_tucker_load",
     "fmm_tucker_layout",
@@ -81,6 +81,7 @@ _SIGS = {
     "fmm_geometry_layout": (_st, [_vp, ctypes.POINTER(fmm_layout)]),
     "fmm_geometry_boxes": (_st, [_vp, _vp, _vp]),
     "fmm_farfield_fill": (_st, [_vp, _i32, _i32, _vp, _vp]),
+    "fmm_planewave_excitation": (_st, [_vp, _i32, _vp, _vp, _st, _vp, _vp]),
     "fmm_geometry_destroy": (None, [_vp]),
     "fmm_tucker_create": (_st, [ctypes.POINTER(fmm_layout), ctypes.POINTER(_vp)]),
     "fmm_farfield_compress": (_st, [ctypes.POINTER(fmm_layout), _vp, _i32, _i32, _f64, _vp, ctypes.POINTER(_vp)]),
@@ -92,7 +93,7 @@ _SIGS = {
     "fmm_tucker_layout": (_st, [_vp, ctypes.POINTER(fmm_layout)]),
     "fmm_tucker_load": (_st, [ctypes.c_char_p, ctypes.POINTER(_vp)]),
     "fmm_tucker_ranks": (_st, [_vp, _vp]),
-    "fmm_tucker_export": (_st, [_vp, _i32, _i32, _vp, _vp, _vp, _vp]),
+    "fmm_tucker_export": (_st, [_vp, _i32, _i32, _st, _vp, _vp, _vp, _vp]),
     "fmm_tucker_storage_bytes": (_st, [_vp, _st, ctypes.POINTER(_sz), ctypes.POINTER(_sz)]),
     "fmm_tucker_upload": (_st, [_vp, _st, _vp, _sz, _vp]),
     "fmm_tucker_aggregate": (_st, [_vp, _st, _i32, _vp, _vp, _vp]),
@@ -237,6 +238,17 @@ def fmm_farfield_fill(geom, first_group, count, farfield, stream=None):
     _check(_lib.fmm_farfield_fill(geom, int(first_group), int(count), _ptr(farfield), _stream(stream)))
 
 
+def fmm_planewave_excitation(geom, khat, epol, prec, x, stream=None):
+    """Excitation vectors of the plane waves (khat, epol: [nrhs, 3] float64 host arrays)
+    into the device tensor x [N, nrhs] (complex128 for FMM_C128, else complex64)."""
+    khat = np.ascontiguousarray(np.atleast_2d(khat), dtype=np.float64)
+    epol = np.ascontiguousarray(np.atleast_2d(epol), dtype=np.float64)
+    if khat.shape != epol.shape or khat.shape[1] != 3:
+        raise ValueError("khat and epol must both be [nrhs, 3]")
+    _check(_lib.fmm_planewave_excitation(geom, int(khat.shape[0]), khat.ctypes.data, epol.ctypes.data, int(prec),
+                                         _ptr(x), _stream(stream)))
+
+
 def fmm_geometry_destroy(geom):
     _lib.fmm_geometry_destroy(geom)
 
@@ -303,14 +315,16 @@ def fmm_tucker_ranks(h, n_groups):
     return r
 
 
-def fmm_tucker_export(h, group, alpha, ranks, n_theta, n_phi, n_beta):
+def fmm_tucker_export(h, group, alpha, ranks, n_theta, n_phi, n_beta, as_stored=FMM_C128):
+    """Factors (core, U^theta, U^phi, U^beta) of one tensor as complex128 arrays;
+    ``as_stored`` = the precision whose stored values to return (FMM_C128: FP64)."""
     rt, rp, rb = (int(v) for v in ranks)
     core = np.empty((rt, rp, rb), np.complex128)
     ut = np.empty((n_theta, rt), np.complex128)
     up = np.empty((n_phi, rp), np.complex128)
     ub = np.empty((n_beta, rb), np.complex128)
-    _check(_lib.fmm_tucker_export(h, int(group), int(alpha), core.ctypes.data, ut.ctypes.data, up.ctypes.data,
-                                  ub.ctypes.data))
+    _check(_lib.fmm_tucker_export(h, int(group), int(alpha), int(as_stored), core.ctypes.data, ut.ctypes.data,
+                                  up.ctypes.data, ub.ctypes.data))
     return core, ut, up, ub
 
 

@@ -547,19 +547,22 @@ extern "C" fmm_status fmm_tucker_ranks(fmm_tucker_t h, int32_t* ranks) {
   return FMM_OK;
 }
 
-extern "C" fmm_status fmm_tucker_export(fmm_tucker_t h, int32_t group, int32_t alpha, double* core,
-                                        double* u_theta, double* u_phi, double* u_beta) {
+extern "C" fmm_status fmm_tucker_export(fmm_tucker_t h, int32_t group, int32_t alpha, fmm_prec as_stored,
+                                        double* core, double* u_theta, double* u_phi, double* u_beta) {
   clear_error();
   if (!h) return fail(FMM_ERR_ARG, "handle is NULL");
   if (group < 0 || group >= h->layout.n_groups || (alpha != 0 && alpha != 1))
     return fail(FMM_ERR_ARG, "group/alpha out of range");
+  if (!prec_valid(as_stored)) return fail(FMM_ERR_ARG, "bad precision %d", (int)as_stored);
   const TensorFactors& tf = h->t[2 * (size_t)group + alpha];
   if (!tf.set()) return fail(FMM_ERR_STATE, "factors of group %d polarisation %d are not set", group, alpha);
-  auto give = [](const std::vector<cd>& v, double* p) {
+  // the complex64 arenas hold each part rounded to the nearest float (pack_tensor)
+  const bool narrow = as_stored != FMM_C128;
+  auto give = [narrow](const std::vector<cd>& v, double* p) {
     if (!p) return;
     for (size_t i = 0; i < v.size(); ++i) {
-      p[2 * i] = v[i].real();
-      p[2 * i + 1] = v[i].imag();
+      p[2 * i] = narrow ? (double)(float)v[i].real() : v[i].real();
+      p[2 * i + 1] = narrow ? (double)(float)v[i].imag() : v[i].imag();
     }
   };
   give(tf.core, core);

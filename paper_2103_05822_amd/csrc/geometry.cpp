@@ -271,7 +271,36 @@ void row_data(const fmm_geometry_s* G, int64_t n, const double* c, double* out) 
     }
   }
   out[36] = G->length[n] / 6.0;
-  out[37] = out[38] = out[39] = 0.0;
+  for (int x = 0; x < 3; ++x) out[37 + x] = c[x];  // the row's phase centre r_v
+}
+
+// Device copies of the per-row quadrature data and the direction table, built on the
+// first device call (and again after a change of device).
+fmm_status ensure_device_rows(fmm_geometry_s* g) {
+  int dev = 0;
+  TFMM_HIP(hipGetDevice(&dev));
+  if (g->d_rowdata != nullptr && g->device == dev) return FMM_OK;
+  if (g->d_rowdata) {
+    (void)hipFree(g->d_rowdata);
+    (void)hipFree(g->d_dirs);
+    g->d_rowdata = nullptr;
+    g->d_dirs = nullptr;
+  }
+  if (g->d_waves) (void)hipFree(g->d_waves);
+  g->d_waves = nullptr;
+  g->waves_cap = 0;
+  const int32_t ng = (int32_t)(g->offsets.size() - 1);
+  const int64_t N = g->offsets.back();
+  std::vector<double> rd((size_t)N * kRowDoubles);
+  for (int32_t gr = 0; gr < ng; ++gr)
+    for (int64_t n = g->offsets[gr]; n < g->offsets[gr + 1]; ++n)
+      row_data(g, n, &g->centers[3 * (size_t)gr], &rd[(size_t)n * kRowDoubles]);
+  TFMM_HIP(hipMalloc(&g->d_rowdata, rd.size() * sizeof(double)));
+  TFMM_HIP(hipMalloc(&g->d_dirs, g->dirs.size() * sizeof(double)));
+  TFMM_HIP(hipMemcpy(g->d_rowdata, rd.data(), rd.size() * sizeof(double), hipMemcpyHostToDevice));
+  TFMM_HIP(hipMemcpy(g->d_dirs, g->dirs.data(), g->dirs.size() * sizeof(double), hipMemcpyHostToDevice));
+  g->device = dev;
+  return FMM_OK;
 }
 
 }  // namespace
@@ -287,26 +316,8 @@ extern "C" fmm_status fmm_farfield_fill(fmm_geometry_t g, int32_t first_group, i
   if (!farfield) return fail(FMM_ERR_ARG, "farfield is NULL");
   if ((uintptr_t)farfield % 16) return fail(FMM_ERR_ARG, "farfield must be 16-byte aligned");
   if (!have_device()) return FMM_ERR_DEVICE;
-  int dev = 0;
-  TFMM_HIP(hipGetDevice(&dev));
-  if (g->d_rowdata == nullptr || g->device != dev) {
-    if (g->d_rowdata) {
-      (void)hipFree(g->d_rowdata);
-      (void)hipFree(g->d_dirs);
-      g->d_rowdata = nullptr;
-      g->d_dirs = nullptr;
-    }
-    const int64_t N = g->offsets.back();
-    std::vector<double> rd((size_t)N * kRowDoubles);
-    for (int32_t gr = 0; gr < ng; ++gr)
-      for (int64_t n = g->offsets[gr]; n < g->offsets[gr + 1]; ++n)
-        row_data(g, n, &g->centers[3 * (size_t)gr], &rd[(size_t)n * kRowDoubles]);
-    TFMM_HIP(hipMalloc(&g->d_rowdata, rd.size() * sizeof(double)));
-    TFMM_HIP(hipMalloc(&g->d_dirs, g->dirs.size() * sizeof(double)));
-    TFMM_HIP(hipMemcpy(g->d_rowdata, rd.data(), rd.size() * sizeof(double), hipMemcpyHostToDevice));
-    TFMM_HIP(hipMemcpy(g->d_dirs, g->dirs.data(), g->dirs.size() * sizeof(double), hipMemcpyHostToDevice));
-    g->device = dev;
-  }
+  fmm_status st = ensure_device_rows(g);
+  if (st != FMM_OK) return st;
   const int64_t row0 = g->offsets[first_group];
   const int64_t rows = g->offsets[first_group + count] - row0;
   TFMM_HIP(launch_farfield_fill(g->d_rowdata + row0 * kRowDoubles, rows, g->d_dirs, g->n_theta * g->n_phi, g->k,
@@ -314,9 +325,52 @@ extern "C" fmm_status fmm_farfield_fill(fmm_geometry_t g, int32_t first_group, i
   return FMM_OK;
 }
 
+extern "C" fmm_status fmm_planewave_excitation(fmm_geometry_t g, int32_t nrhs, const double* khat,
+                                                const double* epol, fmm_prec prec, void* x, void* stream) {
+  clear_error();
+  if (!g) return fail(FMM_ERR_ARG, "geometry is NULL");
+  if (nrhs < 1 || nrhs > 65535) return fail(FMM_ERR_ARG, "nrhs must be in [1, 65535]");
+  if (!khat || !epol) return fail(FMM_ERR_ARG, "khat and epol must be non-NULL");
+  if (prec < FMM_C128 || prec > FMM_BF16X3) return fail(FMM_ERR_ARG, "bad precision %d", (int)prec);
+  const size_t es = prec == FMM_C128 ? 16 : 8;
+  if (!x) return fail(FMM_ERR_ARG, "x is NULL");
+  if ((uintptr_t)x % es) return fail(FMM_ERR_ARG, "x must be %zu-byte aligned", es);
+  std::vector<double> waves((size_t)nrhs * 6);
+  for (int32_t r = 0; r < nrhs; ++r) {
+    double kk = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const double kv = khat[3 * (size_t)r + c], ev = epol[3 * (size_t)r + c];
+      if (!std::isfinite(kv) || !std::isfinite(ev))
+        return fail(FMM_ERR_NUMERIC, "non-finite direction or polarisation of wave %d", r);
+      kk += kv * kv;
+      waves[6 * (size_t)r + c] = kv;
+      waves[6 * (size_t)r + 3 + c] = ev;
+    }
+    if (std::fabs(std::sqrt(kk) - 1.0) > 1e-6) return fail(FMM_ERR_ARG, "direction of wave %d is not a unit vector", r);
+  }
+  if (!have_device()) return FMM_ERR_DEVICE;
+  fmm_status st = ensure_device_rows(g);
+  if (st != FMM_OK) return st;
+  if ((size_t)nrhs > g->waves_cap) {
+    if (g->d_waves) (void)hipFree(g->d_waves);
+    g->d_waves = nullptr;
+    g->waves_cap = 0;
+    TFMM_HIP(hipMalloc(&g->d_waves, waves.size() * sizeof(double)));
+    g->waves_cap = (size_t)nrhs;
+  }
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  // the table is copied before the kernel may read it (a stream-ordered copy from
+  // pageable memory returns once the source has been consumed)
+  TFMM_HIP(hipStreamSynchronize(hs));
+  TFMM_HIP(hipMemcpy(g->d_waves, waves.data(), waves.size() * sizeof(double), hipMemcpyHostToDevice));
+  TFMM_HIP(launch_planewave(g->d_rowdata, g->offsets.back(), g->d_waves, nrhs, g->k, es, x, hs));
+  return FMM_OK;
+}
+
 extern "C" void fmm_geometry_destroy(fmm_geometry_t g) {
   if (!g) return;
   if (g->d_rowdata) (void)hipFree(g->d_rowdata);
   if (g->d_dirs) (void)hipFree(g->d_dirs);
+  if (g->d_waves) (void)hipFree(g->d_waves);
   delete g;
 }

@@ -122,6 +122,7 @@ void mrhs_release(PrecSlot& s);
 
 }  // namespace tuckfmm
 
+
 struct fmm_tucker_s {
   tuckfmm::Layout layout;
   std::vector<tuckfmm::TensorFactors> t;  // [n_groups * 2], index 2g + alpha
@@ -164,4 +165,6 @@ struct fmm_geometry_s {
   int device = -1;
   double* d_rowdata = nullptr;
   double* d_dirs = nullptr;
+  double* d_waves = nullptr;      // plane waves of fmm_planewave_excitation, [cap][6]
+  size_t waves_cap = 0;
 };

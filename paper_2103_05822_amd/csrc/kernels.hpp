@@ -42,9 +42,13 @@ hipError_t launch_dense_disagg(const void* A, const int64_t* offsets, int n_grou
                                int nrhs, const void* G, void* V, hipStream_t s);
 
 // Far-field fill, eq. (4): rowdata [rows][kRowDoubles], dirs [ndir][9].
-constexpr int kRowDoubles = 40;  // 6 points x (rel xyz, rho xyz) + scale + pad
+constexpr int kRowDoubles = 40;  // 6 points x (rel xyz, rho xyz) + scale + box centre
 hipError_t launch_farfield_fill(const double* rowdata, int64_t rows, const double* dirs, int ndir, double k,
                                 void* out, hipStream_t s);
+// Plane-wave excitation of eq. (2): out [rows][nrhs] complex (elem_bytes 8 or 16),
+// waves [nrhs][6] = (k_hat, e_hat) on the device.
+hipError_t launch_planewave(const double* rowdata, int64_t rows, const double* waves, int nrhs, double k,
+                            size_t elem_bytes, void* out, hipStream_t s);
 
 // Precision conversion / packing helpers for setup.
 // Gram matrices of the theta and phi unfoldings of a slab [nb][nt][np] (column-major

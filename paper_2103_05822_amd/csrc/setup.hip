@@ -42,6 +42,39 @@ __global__ __launch_bounds__(256) void farfield_fill_kernel(const double* __rest
   out[(n * 2 + 1) * ndir + i] = make_double2(sc * ap.x, sc * ap.y);
 }
 
+// Plane-wave excitation, the right-hand side of eq. (2): one thread per (basis row n,
+// wave r), x[n][r] = -(l_n / 6) sum_q (e_r . rho_q) exp(-j k k_r . r_q) over the six
+// rule points of the row (rowdata as above; r_q = (r_q - r_v) + r_v with the row's
+// box centre r_v in rowdata[37..39]).  waves: [nrhs][6] = k_hat, e_hat.
+template <typename C>
+__global__ __launch_bounds__(256) void planewave_kernel(const double* __restrict__ rowdata, int64_t rows,
+                                                        const double* __restrict__ waves, int nrhs, double k,
+                                                        C* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= rows * nrhs) return;
+  const int64_t n = e / nrhs;
+  const int r = (int)(e - n * nrhs);
+  const double* rd = rowdata + n * kRowDoubles;
+  const double* w = waves + (int64_t)r * 6;
+  const double kx = w[0], ky = w[1], kz = w[2];
+  const double ex = w[3], ey = w[4], ez = w[5];
+  const double base = rd[37] * kx + rd[38] * ky + rd[39] * kz;  // k_hat . r_v
+  double re = 0.0, im = 0.0;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const double* p = rd + q * 6;
+    const double ph = -k * (base + p[0] * kx + p[1] * ky + p[2] * kz);
+    double sn, cs;
+    sincos(ph, &sn, &cs);
+    const double a = p[3] * ex + p[4] * ey + p[5] * ez;
+    re += a * cs;
+    im += a * sn;
+  }
+  using R = decltype(C{}.x);
+  const double sc = -rd[36];
+  out[e] = C{(R)(sc * re), (R)(sc * im)};
+}
+
 // Copy one polarisation of a group's far-field rows into two contiguous slabs:
 //   out_tp [nb][n_theta][n_phi]   and   out_pt [nb][n_phi][n_theta]
 __global__ __launch_bounds__(256) void gather_slab_kernel(const double2* __restrict__ ff, int64_t row0, int nb,
@@ -233,6 +266,22 @@ hipError_t launch_farfield_fill(const double* rowdata, int64_t rows, const doubl
   dim3 grid((unsigned)rows, (ndir + 255) / 256);
   hipLaunchKernelGGL(farfield_fill_kernel, grid, dim3(256), 0, s, rowdata, dirs, ndir, k,
                      static_cast<double2*>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_planewave(const double* rowdata, int64_t rows, const double* waves, int nrhs, double k,
+                            size_t elem_bytes, void* out, hipStream_t s) {
+  const int64_t total = rows * nrhs;
+  if (total == 0) return hipSuccess;
+  const dim3 grid((unsigned)((total + 255) / 256));
+  if (elem_bytes == 16)
+    hipLaunchKernelGGL(planewave_kernel<double2>, grid, dim3(256), 0, s, rowdata, rows, waves, nrhs, k,
+                       static_cast<double2*>(out));
+  else if (elem_bytes == 8)
+    hipLaunchKernelGGL(planewave_kernel<float2>, grid, dim3(256), 0, s, rowdata, rows, waves, nrhs, k,
+                       static_cast<float2*>(out));
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

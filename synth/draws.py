@@ -24,6 +24,18 @@ def unit_vectors(gen, count):
     return v / np.linalg.norm(v, axis=1, keepdims=True)
 
 
+def planewaves(gen, count):
+    """Incident plane waves for many right-hand sides: propagation directions uniform on
+    the unit sphere (:func:`unit_vectors`) and polarisation theta_hat of each direction,
+    (cos t cos p, cos t sin p, -sin t) with t, p the direction's polar angles.
+    Returns ``(khat [count, 3], epol [count, 3])``."""
+    k = unit_vectors(gen, count)
+    t = np.arccos(np.clip(k[:, 2], -1.0, 1.0))
+    p = np.arctan2(k[:, 1], k[:, 0])
+    e = np.stack([np.cos(t) * np.cos(p), np.cos(t) * np.sin(p), -np.sin(t)], axis=1)
+    return k, e
+
+
 def synthetic_ranks(gen, nb, n_theta, n_phi):
     """Random multilinear ranks (r_theta, r_phi, r_beta) for one tensor of shape
     n_theta x n_phi x nb, each between 1 and its mode size."""

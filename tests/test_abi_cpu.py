@@ -84,6 +84,12 @@ def test_factor_import_export_round_trip_and_storage():
             got = T.fmm_tucker_export(h, g, a, ranks[g, a], 4, 7, nb)
             for x, y in zip(got, f):
                 assert np.array_equal(x, y)
+            # as stored in a complex64 arena: each part rounded to the nearest float
+            for prec in (T.FMM_C64, T.FMM_BF16X2, T.FMM_BF16X3):
+                got = T.fmm_tucker_export(h, g, a, ranks[g, a], 4, 7, nb, as_stored=prec)
+                for x, y in zip(got, f):
+                    assert np.array_equal(x, y.astype(np.complex64).astype(np.complex128))
+                    assert not np.array_equal(x, y)   # random FP64 values are not floats
         fb, ab = T.fmm_tucker_storage_bytes(h, T.FMM_C64)
         assert fb == 8 * es_total and ab >= fb
         fb128, _ = T.fmm_tucker_storage_bytes(h, T.FMM_C128)
@@ -100,6 +106,7 @@ def test_factor_import_export_round_trip_and_storage():
         assert _status(T.fmm_tucker_set_group, h, 0, 0, nan, ut, up, ub) == -5
         assert _status(T.fmm_tucker_upload, h, T.FMM_C64, 0, ab, 0) == -1   # NULL arena
         assert _status(T.fmm_tucker_aggregate, h, 9, 1, 0, 0) == -1         # bad precision
+        assert _status(T.fmm_tucker_export, h, 0, 0, ranks[0, 0], 4, 7, 5, 9) == -1
     finally:
         T.fmm_tucker_destroy(h)
 

@@ -2,14 +2,29 @@
 sphere (939,870 RWG, 1034 groups, 38 x 75 grid, gamma = 1e-6, 64 RHS), the 20-lambda
 batching sphere at its smallest and largest boxes (0.5 and 4 lambda, 64 RHS) and the
 45-lambda sphere (2,301,870 RWG, gamma = 1e-5, 32 RHS).  Far-fields are filled and
-compressed on the GPU group chunk by group chunk, the FP32 pass is replayed from a
-captured graph and the BF16x2 and FP64 matrix-core passes run at the workload's RHS
-count; all are checked against the oracle's dense FP64 products on sampled groups (the
-largest and three seeded draws), which the oracle computes one group at a time.
+compressed on the GPU group chunk by group chunk.  The single-RHS FP32 pass is replayed
+from a captured graph (the launch configuration the bench times); the many-RHS passes
+take plane-wave excitations (eq. (2), computed by the library) and run in FP32, in the
+bf16 three-piece split, in the bf16 two-piece split and in FP64.
 
-Bound: the compression error gamma ||A||_F ||x|| per tensor plus the arithmetic's
-(FP32: 1e-5 relative; BF16x2: 4e-5 relative, as in the multi-RHS parity tests; FP64:
-1e-10 relative).
+Two checks per sampled group (the largest group plus seeded draws; 32 groups on the
+45-lambda sphere):
+
+1. Arithmetic only.  The stored factors of the group are exported as the arena holds
+   them (``as_stored``: complex64-rounded for the FP32 and split paths, FP64 for the
+   FP64 path) and contracted by the oracle's Tucker chain of Fig. 2(b) / Fig. 3(b)
+   in FP64, on the oracle's own inputs (its FP64 plane waves, rounded to complex64
+   where the GPU path takes complex64).  Bounds, element-wise relative to the largest
+   reference entry of the sample and relative L2: 1e-5 for FP32 and BF16x3 (the
+   method's single-precision target), 1e-10 for FP64.  BF16x2 does not reach the
+   1e-5 target (each operand keeps 16 significant bits, so every product carries a
+   relative error near 2^-16); it is held to its own bound, 3e-5 L2 and 1e-4
+   element-wise, below the target.
+2. End to end (second assertion, on the first four sampled groups): the GPU result
+   against the oracle's dense product with the far-fields of eq. (4), within the
+   compression bound gamma ||A||_F ||x|| per tensor plus the arithmetic bound.
+
+The excitation itself is checked against the oracle on the sampled rows.
 """
 import numpy as np
 import pytest
@@ -19,11 +34,15 @@ from synth import workloads as W
 from oracle import geometry as geo
 from oracle import farfield as ff
 from oracle import products as pr
-from gpu_util import banner
+from oracle import excitation as ex
+from gpu_util import banner, max_rel, l2_rel
 
 pytestmark = pytest.mark.gpu
 
 T = pytest.importorskip("paper_2103_05822_amd")
+
+# arithmetic bounds (L2, element-wise relative to the max)
+ARITH = {"c64": (1e-5, 1e-5), "bf16x3": (1e-5, 1e-5), "bf16x2": (3e-5, 1e-4), "c128": (1e-10, 1e-10)}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -34,12 +53,41 @@ def _gpu():
     torch.cuda.set_device(0)
 
 
-CASES = [(W.SPHERE30, 64, 939870, 1034), (W.SPHERE20[0.5], 64, 432000, 7232),
-         (W.SPHERE20[4.0], 64, 432000, 98), (W.SPHERE45, 32, 2301870, 2345)]
+CASES = [(W.SPHERE30, 64, 939870, 1034, 12), (W.SPHERE20[0.5], 64, 432000, 7232, 12),
+         (W.SPHERE20[4.0], 64, 432000, 98, 12), (W.SPHERE45, 32, 2301870, 2345, 32)]
 
 
-@pytest.mark.parametrize("w,R,n_basis,n_groups", CASES, ids=[c[0].name for c in CASES])
-def test_full_size_sampled_groups(w, R, n_basis, n_groups):
+def _pass_at(T, torch, h, prec, dt, R, xd, gd, G, N, nd, sample, offs):
+    """One pass at R right-hand sides; returns {g: (F_g [2, N_dir, R], V_g [n_beta, R])}."""
+    Fr = torch.empty((G, 2, nd, R), dtype=dt, device="cuda")
+    Vr = torch.empty((N, R), dtype=dt, device="cuda")
+    T.fmm_tucker_pass(h, prec, R, xd, Fr, gd, Vr)
+    torch.cuda.synchronize()
+    out = {g: (Fr[g].cpu().numpy(), Vr[int(offs[g]):int(offs[g + 1])].cpu().numpy()) for g in sample}
+    del Fr, Vr
+    return out
+
+
+def _check(tag, got, ref, sample, offs):
+    """Arithmetic check over the sample: concatenated F and V against the oracle's
+    chain, printing each group's error."""
+    tl2, tmax = ARITH[tag]
+    for g in sample:
+        ef = max_rel(got[g][0], ref[g][0])
+        ev = max_rel(got[g][1], ref[g][1])
+        print("    %-6s group %5d (n_beta %4d): F %.2e  V %.2e (max rel)" %
+              (tag, g, int(offs[g + 1] - offs[g]), ef, ev), flush=True)
+    gf = np.concatenate([np.ravel(got[g][0]) for g in sample])
+    rf = np.concatenate([np.ravel(ref[g][0]) for g in sample])
+    gv = np.concatenate([np.ravel(got[g][1]) for g in sample])
+    rv = np.concatenate([np.ravel(ref[g][1]) for g in sample])
+    res = (l2_rel(gf, rf), max_rel(gf, rf), l2_rel(gv, rv), max_rel(gv, rv))
+    print("  %-6s arithmetic: F l2 %.2e max %.2e | V l2 %.2e max %.2e" % ((tag,) + res), flush=True)
+    assert res[0] < tl2 and res[1] < tmax and res[2] < tl2 and res[3] < tmax, (tag, res)
+
+
+@pytest.mark.parametrize("w,R,n_basis,n_groups,n_sample", CASES, ids=[c[0].name for c in CASES])
+def test_full_size_sampled_groups(w, R, n_basis, n_groups, n_sample):
     import torch
     v, t = w.mesh()
     geom = T.fmm_geometry_build(v, t, w.origin, w.box, w.boxes_per_axis, w.k, w.n_theta, w.n_phi)
@@ -48,9 +96,14 @@ def test_full_size_sampled_groups(w, R, n_basis, n_groups):
         lay = T.fmm_geometry_layout(geom)
         N, G, nd = lay.n_basis, lay.n_groups, lay.n_dir
         assert (N, G) == (n_basis, n_groups)
+        offs = lay.offsets
+        nb = np.diff(offs)
+        big = int(np.argmax(nb))
+        draws = [int(g) for g in synth.rng(4).choice(G, size=n_sample, replace=False) if g != big]
+        sample = sorted([big] + draws[:n_sample - 1])
         banner("full size %s: streaming compress of %d groups" % (w.name, G))
-        chunk = 16
-        rows = max(int(lay.offsets[min(G, g0 + chunk)] - lay.offsets[g0]) for g0 in range(0, G, chunk))
+        chunk = 32
+        rows = max(int(offs[min(G, g0 + chunk)] - offs[g0]) for g0 in range(0, G, chunk))
         buf = torch.empty((rows, 2, w.n_theta, w.n_phi), dtype=torch.complex128, device="cuda")
         for g0 in range(0, G, chunk):
             cnt = min(chunk, G - g0)
@@ -58,13 +111,19 @@ def test_full_size_sampled_groups(w, R, n_basis, n_groups):
             h = T.fmm_farfield_compress(lay, buf, g0, cnt, w.gamma, handle=h)
         buf = None
         torch.cuda.empty_cache()
+        ranks = T.fmm_tucker_ranks(h, G)
+        stored = {}
+        for tag, prec in (("c64", T.FMM_C64), ("c128", T.FMM_C128)):
+            stored[tag] = {g: [(f[0], f[1:]) for f in
+                               (T.fmm_tucker_export(h, g, a, ranks[g, a], w.n_theta, w.n_phi, int(nb[g]),
+                                                    as_stored=prec) for a in range(2))] for g in sample}
+
+        banner("full size %s: FP32 pass from a captured graph, 1 RHS" % w.name)
+        x = synth.complex_normal(synth.rng(w.seeds["x"]), N)
+        gin = synth.complex_normal(synth.rng(w.seeds.get("g", 1)), (G, 2, nd))
         _, nbytes = T.fmm_tucker_storage_bytes(h, T.FMM_C64)
         ar = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         T.fmm_tucker_upload(h, T.FMM_C64, ar)
-
-        banner("full size %s: FP32 pass from a captured graph" % w.name)
-        x = synth.complex_normal(synth.rng(w.seeds["x"]), N)
-        gin = synth.complex_normal(synth.rng(w.seeds.get("g", 1)), (G, 2, nd))
         xd = torch.from_numpy(x).to("cuda", torch.complex64)
         gd = torch.from_numpy(gin).to("cuda", torch.complex64)
         F = torch.empty((G, 2, nd), dtype=torch.complex64, device="cuda")
@@ -75,71 +134,82 @@ def test_full_size_sampled_groups(w, R, n_basis, n_groups):
         torch.cuda.synchronize()
         T.fmm_graph_launch(h, s)
         s.synchronize()
-        F1, V1 = F.cpu().numpy(), V.cpu().numpy()
-        del F, V, xd, gd
+        one = {g: (F[g].cpu().numpy(), V[int(offs[g]):int(offs[g + 1])].cpu().numpy()) for g in sample}
+        del F, V, xd, gd, ar
 
-        banner("full size %s: BF16x2 pass, %d right-hand sides" % (w.name, R))
-        # R distinct columns from 8 seeded ones times per-column complex scales (drawing
-        # all R columns of G would take longer than the rest of the test)
+        banner("full size %s: %d plane-wave excitations" % (w.name, R))
+        khat, epol = synth.planewaves(synth.rng(w.seeds["x"] + 200), R)
+        x64d = torch.empty((N, R), dtype=torch.complex128, device="cuda")
+        T.fmm_planewave_excitation(geom, khat, epol, T.FMM_C128, x64d)
+        x32d = torch.empty((N, R), dtype=torch.complex64, device="cuda")
+        T.fmm_planewave_excitation(geom, khat, epol, T.FMM_C64, x32d)
+        torch.cuda.synchronize()
+        xs_gpu = {g: x64d[int(offs[g]):int(offs[g + 1])].cpu().numpy() for g in sample}
+        # R distinct incoming-spectra columns: 8 seeded ones times per-column complex
+        # scales (drawing all R columns of G would take longer than the rest of the test)
         scale = (1.0 + np.arange(R) / R) * np.exp(1j * np.arange(R))
-        xr = synth.complex_normal(synth.rng(w.seeds["x"] + 100), (N, 8), dtype=np.complex64)
-        xr = (np.tile(xr, (1, R // 8)) * scale).astype(np.complex64)
         gr = synth.complex_normal(synth.rng(w.seeds.get("g", 1) + 100), (G, 2, nd, 8), dtype=np.complex64)
         gr = (np.tile(gr, (1, 1, 1, R // 8)) * scale).astype(np.complex64)
-        _, nbytes = T.fmm_tucker_storage_bytes(h, T.FMM_BF16X2)
-        ar2 = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-        T.fmm_tucker_upload(h, T.FMM_BF16X2, ar2)
-        Fr = torch.empty((G, 2, nd, R), dtype=torch.complex64, device="cuda")
-        Vr = torch.empty((N, R), dtype=torch.complex64, device="cuda")
-        T.fmm_tucker_pass(h, T.FMM_BF16X2, R, torch.from_numpy(xr).to("cuda", torch.complex64), Fr,
-                          torch.from_numpy(gr).to("cuda", torch.complex64), Vr)
-        torch.cuda.synchronize()
-        offs = lay.offsets
-        nb = np.diff(offs)
-        sample = sorted({int(np.argmax(nb))} | set(int(g) for g in synth.rng(4).choice(G, size=3, replace=False)))
-        bf = {g: (Fr[g].cpu().numpy(), Vr[int(offs[g]):int(offs[g + 1])].cpu().numpy()) for g in sample}
-        del Fr, Vr, ar2
-        torch.cuda.empty_cache()
-
-        banner("full size %s: FP64 matrix-core pass, %d right-hand sides" % (w.name, R))
-        _, nbytes = T.fmm_tucker_storage_bytes(h, T.FMM_C128)
-        ar3 = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-        T.fmm_tucker_upload(h, T.FMM_C128, ar3)
-        Fd = torch.empty((G, 2, nd, R), dtype=torch.complex128, device="cuda")
-        Vd = torch.empty((N, R), dtype=torch.complex128, device="cuda")
-        T.fmm_tucker_pass(h, T.FMM_C128, R, torch.from_numpy(xr.astype(np.complex128)).to("cuda"), Fd,
-                          torch.from_numpy(gr.astype(np.complex128)).to("cuda"), Vd)
-        torch.cuda.synchronize()
-        fp64 = {g: (Fd[g].cpu().numpy(), Vd[int(offs[g]):int(offs[g + 1])].cpu().numpy()) for g in sample}
-        del Fd, Vd, ar3
+        many = {}
+        for tag, prec in (("c64", T.FMM_C64), ("bf16x3", T.FMM_BF16X3), ("bf16x2", T.FMM_BF16X2),
+                          ("c128", T.FMM_C128)):
+            banner("full size %s: %s pass, %d right-hand sides" % (w.name, tag, R))
+            dt = torch.complex128 if prec == T.FMM_C128 else torch.complex64
+            _, nbytes = T.fmm_tucker_storage_bytes(h, prec)
+            ar = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            T.fmm_tucker_upload(h, prec, ar)
+            gd = torch.from_numpy(gr).to("cuda", dt)
+            many[tag] = _pass_at(T, torch, h, prec, dt, R, x64d if prec == T.FMM_C128 else x32d, gd, G, N, nd,
+                                 sample, offs)
+            del ar, gd
+            torch.cuda.empty_cache()
+        del x64d, x32d
     finally:
         if h:
             T.fmm_tucker_destroy(h)
         T.fmm_geometry_destroy(geom)
 
-    banner("full size %s: oracle on sampled groups" % w.name)
+    banner("full size %s: oracle on %d sampled groups" % (w.name, len(sample)))
     P = geo.Problem(v, t, w.origin, w.box, w.boxes_per_axis, w.n_theta, w.n_phi)
     assert np.array_equal(P.offsets, offs)
     assert np.array_equal(P.group_sizes(), nb)
+    xs, ref1, refR = {}, {}, {"c64": {}, "c128": {}}
     for g in sample:
         lo, hi = int(offs[g]), int(offs[g + 1])
+        xs[g] = ex.planewave_excitation(P, khat, epol, rows=np.arange(lo, hi))
+        assert max_rel(xs_gpu[g], xs[g]) < 1e-12, g
+        x32 = xs[g].astype(np.complex64).astype(np.complex128)   # the complex64 input the FP32 paths take
+        g64 = gr[g].astype(np.complex128)
+        fac32, fac64 = stored["c64"][g], stored["c128"][g]
+        ref1[g] = (pr.tucker_aggregate(fac32, x[lo:hi].astype(np.complex64)),
+                   pr.tucker_disaggregate(fac32, gin[g].astype(np.complex64)))
+        refR["c64"][g] = (pr.tucker_aggregate(fac32, x32), pr.tucker_disaggregate(fac32, g64))
+        refR["c128"][g] = (pr.tucker_aggregate(fac64, xs[g]), pr.tucker_disaggregate(fac64, g64))
+    print("  arithmetic errors against the oracle's Tucker chain on the stored factors:", flush=True)
+    _check("c64", one, ref1, sample, offs)
+    for tag in ("c64", "bf16x3", "bf16x2", "c128"):
+        _check(tag, many[tag], refR["c128" if tag == "c128" else "c64"], sample, offs)
+
+    # end to end against the dense far-fields (compression error included)
+    for g in sample[:4]:
+        lo, hi = int(offs[g]), int(offs[g + 1])
         blk = ff.farfield_group(P, g)
-        fd = pr.dense_aggregate(blk, x[lo:hi])
-        vd = pr.dense_disaggregate(blk, gin[g])
         na = [np.linalg.norm(blk[:, a]) for a in range(2)]
+        fd, vd = pr.dense_aggregate(blk, x[lo:hi]), pr.dense_disaggregate(blk, gin[g])
         for a in range(2):
             bound = w.gamma * na[a] * np.linalg.norm(x[lo:hi]) + 1e-5 * np.linalg.norm(fd[a])
-            assert np.linalg.norm(F1[g, a] - fd[a]) <= bound, (g, a)
+            assert np.linalg.norm(one[g][0][a] - fd[a]) <= bound, (g, a)
         vbound = sum(w.gamma * na[a] * np.linalg.norm(gin[g, a]) for a in range(2)) + 1e-5 * np.linalg.norm(vd)
-        assert np.linalg.norm(V1[lo:hi] - vd) <= vbound, g
-        fr = pr.dense_aggregate(blk, xr[lo:hi].astype(np.complex128))
+        assert np.linalg.norm(one[g][1] - vd) <= vbound, g
+        fr = pr.dense_aggregate(blk, xs[g])
         vr = pr.dense_disaggregate(blk, gr[g].astype(np.complex128))
-        for tag, (Fg, Vg), rel in (("bf16x2", bf[g], 4e-5), ("fp64", fp64[g], 1e-10)):
-            for a in range(2):
-                bound = w.gamma * na[a] * np.linalg.norm(xr[lo:hi]) + rel * np.linalg.norm(fr[a])
-                assert np.linalg.norm(Fg[a] - fr[a]) <= bound, (tag, g, a)
-            vbound = sum(w.gamma * na[a] * np.linalg.norm(gr[g, a]) for a in range(2)) + rel * np.linalg.norm(vr)
-            assert np.linalg.norm(Vg - vr) <= vbound, (tag, g)
-        print("  group %d (n_beta %d): F err %.2e, V err %.2e, BF16x2 F err %.2e, FP64 F err %.2e" %
-              (g, hi - lo, pr.rel_err(F1[g], fd), pr.rel_err(V1[lo:hi], vd), pr.rel_err(bf[g][0], fr),
-               pr.rel_err(fp64[g][0], fr)), flush=True)
+        Fg, Vg = many["c128"][g]
+        for a in range(2):
+            bound = w.gamma * na[a] * np.linalg.norm(xs[g]) + 1e-10 * np.linalg.norm(fr[a])
+            assert np.linalg.norm(Fg[a] - fr[a]) <= bound, ("c128", g, a)
+        vbound = sum(w.gamma * na[a] * np.linalg.norm(gr[g, a]) for a in range(2)) + 1e-10 * np.linalg.norm(vr)
+        assert np.linalg.norm(Vg - vr) <= vbound, ("c128", g)
+        print("  group %d (n_beta %d) end to end: FP32 1-RHS F %.2e V %.2e | FP64 R-RHS F %.2e V %.2e | "
+              "BF16x3 F %.2e" % (g, hi - lo, pr.rel_err(one[g][0], fd), pr.rel_err(one[g][1], vd),
+                                 pr.rel_err(Fg, fr), pr.rel_err(Vg, vr), pr.rel_err(many["bf16x3"][g][0], fr)),
+              flush=True)
