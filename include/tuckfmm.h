@@ -323,6 +323,23 @@ fmm_status fmm_tucker_pass(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const vo
 fmm_status fmm_graph_capture(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F,
                              const void* G, void* V, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): fmm_tucker_pass with the same
+ * arguments, results and errors, computed by the streaming kernels (whatever the
+ * route of fmm_tucker_pass for this nrhs) with the partial sums of split items in a
+ * static device array of 64 MiB per GPU instead of a library allocation.  It calls no
+ * hipMalloc, hipFree or allocating library routine.
+ *   prec  FMM_C128 or FMM_C64 (the bf16 split precisions run only on the matrix-core
+ *         path, whose tables the library allocates: FMM_ERR_UNSUPPORTED; so is a layout
+ *         whose FP64 items exceed the streaming kernels' LDS).
+ * FMM_ERR_SIZE when the split items' partial sums (their r_theta r_phi and n_beta
+ * values per block, per right-hand side) exceed the array: fewer right-hand sides per
+ * call, or no split items, fit.  Every call on one GPU shares that GPU's array, which
+ * keeps the last call's contents (the kernels overwrite every block they read):
+ * calls that overlap on one GPU, from two streams or two threads, race. */
+fmm_status fmm_tucker_pass_noalloc(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F,
+                                   const void* G, void* V, void* stream);
+
 /* Launch the captured pass on `stream`. */
 fmm_status fmm_graph_launch(fmm_tucker_t h, void* stream);
 

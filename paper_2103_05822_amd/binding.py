@@ -25,7 +25,8 @@ __all__ = [
     "fmm_tucker_set_group", "fmm_tucker_set_box_grid", "fmm_tucker_save", "fmm_tucker_load",
     "fmm_tucker_layout",
     "fmm_tucker_ranks", "fmm_tucker_export", "fmm_tucker_storage_bytes", "fmm_tucker_upload",
-    "fmm_tucker_aggregate", "fmm_tucker_disaggregate", "fmm_tucker_pass", "fmm_graph_capture", "fmm_graph_launch",
+    "fmm_tucker_aggregate", "fmm_tucker_disaggregate", "fmm_tucker_pass", "fmm_tucker_pass_noalloc",
+    "fmm_graph_capture", "fmm_graph_launch",
     "fmm_tucker_tune", "fmm_tucker_destroy", "fmm_dense_create", "fmm_dense_aggregate", "fmm_dense_disaggregate",
     "fmm_dense_destroy",
 ]
@@ -99,6 +100,7 @@ _SIGS = {
     "fmm_tucker_aggregate": (_st, [_vp, _st, _i32, _vp, _vp, _vp]),
     "fmm_tucker_disaggregate": (_st, [_vp, _st, _i32, _vp, _vp, _vp]),
     "fmm_tucker_pass": (_st, [_vp, _st, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "fmm_tucker_pass_noalloc": (_st, [_vp, _st, _i32, _vp, _vp, _vp, _vp, _vp]),
     "fmm_graph_capture": (_st, [_vp, _st, _i32, _vp, _vp, _vp, _vp, _vp]),
     "fmm_graph_launch": (_st, [_vp, _vp]),
     "fmm_tucker_tune": (_st, [_vp, _st, _i32, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(fmm_tune_result)]),
@@ -350,6 +352,11 @@ def fmm_tucker_disaggregate(h, prec, nrhs, G, V, stream=None):
 
 def fmm_tucker_pass(h, prec, nrhs, x, F, G, V, stream=None):
     _check(_lib.fmm_tucker_pass(h, int(prec), int(nrhs), _ptr(x), _ptr(F), _ptr(G), _ptr(V), _stream(stream)))
+
+
+def fmm_tucker_pass_noalloc(h, prec, nrhs, x, F, G, V, stream=None):
+    _check(_lib.fmm_tucker_pass_noalloc(h, int(prec), int(nrhs), _ptr(x), _ptr(F), _ptr(G), _ptr(V),
+                                        _stream(stream)))
 
 
 def fmm_graph_capture(h, prec, nrhs, x, F, G, V, stream):

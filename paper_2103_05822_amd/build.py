@@ -17,7 +17,7 @@ BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["api.cpp", "geometry.cpp", "compress.cpp", "mrhs_plan.cpp", "serialize.cpp", "tucker.hip", "dense.hip",
-           "setup.hip", "mrhs.hip"]
+           "setup.hip", "mrhs.hip", "noalloc.hip"]
 
 COMMON = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

@@ -727,6 +727,40 @@ extern "C" fmm_status fmm_tucker_pass(fmm_tucker_t h, fmm_prec prec, int32_t nrh
   return run_stage(h, *s, prec, nrhs, 2, x, F, G, V, static_cast<hipStream_t>(stream));
 }
 
+fmm_status tuckfmm::noalloc_pass(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F, const void* G,
+                                 void* V, hipStream_t hs, void* scratch, size_t scratch_bytes) {
+  PrecSlot* s = nullptr;
+  fmm_status st = pass_checks(h, prec, nrhs, x, F, G, V, &s);
+  if (st != FMM_OK) return st;
+  if (prec_is_split(prec))
+    return fail(FMM_ERR_UNSUPPORTED, "the bf16 split precisions run on the matrix-core path, whose tables the "
+                                     "library allocates; the allocation-free pass takes FMM_C128 or FMM_C64");
+  if (prec == FMM_C128 && !s->streams)
+    return fail(FMM_ERR_UNSUPPORTED, "this layout's FP64 items do not fit the streaming kernels' LDS");
+  Route r;
+  if ((st = route_of(*s, prec, nrhs, &r)) != FMM_OK) return st;
+  const Layout& L = h->layout;
+  TuckPlan pl = s->plan;  // the slot's own partial-sum buffer stays untouched
+  pl.part = nullptr;
+  if (pl.n_splits > 0) {
+    const size_t need = (size_t)pl.part_stride * (size_t)nrhs * elem_bytes(prec);
+    if (need > scratch_bytes)
+      return fail(FMM_ERR_SIZE, "the split items' partial sums need %zu bytes for nrhs = %d, the static scratch "
+                                "holds %zu", need, nrhs, scratch_bytes);
+    pl.part = scratch;
+  }
+  if (s->plan.n_zero_rows > 0)
+    TFMM_HIP(launch_zero_rows(elem_bytes(prec), F, pl.zero_rows, pl.n_zero_rows, (int64_t)L.ndir() * nrhs, hs));
+  if (prec == FMM_C128) {
+    if ((st = lds_check(tucker_lds_bytes<double>(pl.mx))) != FMM_OK) return st;
+    TFMM_HIP(launch_tucker_pass<double>(pl, r.threads, L.n_theta, L.n_phi, nrhs, x, F, G, V, hs));
+  } else {
+    if ((st = lds_check(tucker_lds_bytes<float>(pl.mx))) != FMM_OK) return st;
+    TFMM_HIP(launch_tucker_pass<float>(pl, r.threads, L.n_theta, L.n_phi, nrhs, x, F, G, V, hs));
+  }
+  return FMM_OK;
+}
+
 extern "C" fmm_status fmm_graph_capture(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F,
                                         const void* G, void* V, void* stream) {
   clear_error();

@@ -122,6 +122,14 @@ void mrhs_release(PrecSlot& s);
 
 }  // namespace tuckfmm
 
+struct fmm_tucker_s;
+namespace tuckfmm {
+// The pass of fmm_tucker_pass on the streaming kernels with the split items' partial
+// sums in `scratch` (device memory of scratch_bytes) instead of the handle's buffer:
+// validates, checks the size, launches; allocates nothing.
+fmm_status noalloc_pass(fmm_tucker_s* h, fmm_prec prec, int32_t nrhs, const void* x, void* F, const void* G,
+                        void* V, hipStream_t hs, void* scratch, size_t scratch_bytes);
+}  // namespace tuckfmm
 
 struct fmm_tucker_s {
   tuckfmm::Layout layout;
