@@ -4,8 +4,9 @@ polarisation and zero on the empty boxes; the disaggregation reads the groups' b
 only.  Outputs start as NaN so that an entry the kernels skip shows up, and the
 incoming spectra hold NaN on the empty boxes so that a read of one shows up.
 
-Tolerances as in the other parity tests: FP64 1e-11, FP32 and BF16x3 1e-5, BF16x2
-4e-5 (L2) / 1e-4 (max), relative to the oracle.
+Tolerances as in the other parity tests: FP64 1e-11, FP32 and BF16x3 1e-5 (the
+single-precision target), BF16x2 3e-5 (L2) / 1e-4 (max), its own bound below that
+target, relative to the oracle.
 """
 import numpy as np
 import pytest
@@ -22,7 +23,7 @@ T = pytest.importorskip("paper_2103_05822_amd")
 
 CDT = {T.FMM_C128: np.complex128, T.FMM_C64: np.complex64, T.FMM_BF16X2: np.complex64,
        T.FMM_BF16X3: np.complex64}
-TOL = {T.FMM_C128: (1e-11, 1e-11), T.FMM_C64: (1e-5, 1e-5), T.FMM_BF16X2: (4e-5, 1e-4),
+TOL = {T.FMM_C128: (1e-11, 1e-11), T.FMM_C64: (1e-5, 1e-5), T.FMM_BF16X2: (3e-5, 1e-4),
        T.FMM_BF16X3: (1e-5, 1e-5)}
 DIMS = (3, 4, 5)
 

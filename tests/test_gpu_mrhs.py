@@ -10,13 +10,15 @@ reference entry:
   - FP64: 1e-11, the bound of the FP64 streaming kernels (unit roundoff 1.1e-16 over
     sums of a few thousand terms, with margin).
   - FP32 and BF16x3: 1e-5, the single-precision target of the method (sums of a few
-    thousand terms with unit roundoff 6e-8).
-  - BF16x2: each operand v = hi + lo carries a representation error below 2^-17 |v|
-    (the lo piece rounds the residual to 8 significant bits) and the dropped lo*lo
-    term is below 2^-18 relative, so a product of two split operands is off by at
-    most ~3 2^-18 = 1.1e-5 relative per term; four chained products with
-    independent rounding give about 2 x 1.1e-5 in L2.  The bound used is 4e-5 (L2) and
-    1e-4 (max).
+    thousand terms with unit roundoff 6e-8).  BF16x3 is the split precision that
+    meets it.
+  - BF16x2 (below the 1e-5 target): each operand v = hi + lo keeps 16 significant
+    bits (hi rounds v to 8 bits, lo the residual, so |v - hi - lo| <= 2^-16 |v|), and
+    the dropped lo*lo term is also up to 2^-16 relative, so a product of two split
+    operands can be off by ~3 2^-16 relative per term; with rounding errors of random
+    sign, four chained products give 0.8-0.9e-5 in L2 and 1-2e-5 element-wise at full
+    size.  It is held to its own bound, 3e-5 (L2) and 1e-4 (max), and does not meet
+    the target.
 """
 import numpy as np
 import pytest
@@ -32,7 +34,7 @@ pytestmark = pytest.mark.gpu
 T = pytest.importorskip("paper_2103_05822_amd")
 
 C64 = np.complex64
-TOL = {T.FMM_C128: (1e-11, 1e-11), T.FMM_C64: (1e-5, 1e-5), T.FMM_BF16X2: (4e-5, 1e-4), T.FMM_BF16X3: (1e-5, 1e-5)}
+TOL = {T.FMM_C128: (1e-11, 1e-11), T.FMM_C64: (1e-5, 1e-5), T.FMM_BF16X2: (3e-5, 1e-4), T.FMM_BF16X3: (1e-5, 1e-5)}
 CDT = {T.FMM_C128: np.complex128, T.FMM_C64: C64, T.FMM_BF16X2: C64, T.FMM_BF16X3: C64}
 PRECS = [T.FMM_C128, T.FMM_C64, T.FMM_BF16X2, T.FMM_BF16X3]
 PIDS = ["c128", "c64", "bf16x2", "bf16x3"]
