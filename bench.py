@@ -65,6 +65,8 @@ def parse():
     p.add_argument("--mrhs-steps", type=int, default=10, help="timed passes per multi-RHS precision")
     p.add_argument("--no-svd", action="store_true", help="skip the truncated-SVD comparison")
     p.add_argument("--no-grid", action="store_true", help="skip the box-grid pass")
+    p.add_argument("--no-extra", action="store_true",
+                   help="skip the other stated configurations (Tucker FP64 pass, gamma = 1e-4, 29 x 58 grid)")
     p.add_argument("--sweep", choices=["gamma", "digits", "box"], default=None,
                    help="measure compression and speedup trends instead of the pass benchmark")
     p.add_argument("--save-factors", default=None, help="write the compressed factors to this file")
@@ -220,6 +222,10 @@ def main():
         save_factors(T, h, args.save_factors)
         log("factors saved to %s" % args.save_factors)
     log("compress: %.1f s, mean ranks %s" % (t_compress, ranks.reshape(-1, 3).mean(0).round(1)))
+    # groups checked against the oracle, and their stored factors (arithmetic-only parity)
+    sample = sampled_groups(synth, np.diff(lay.offsets), args.sample_groups)
+    stored = {"c64": export_sample(T, h, ranks, sample, lay, T.FMM_C64),
+              "c128": export_sample(T, h, ranks, sample, lay, T.FMM_C128)}
     arenas = {}
     for prec in (T.FMM_C64,):
         _, nbytes = T.fmm_tucker_storage_bytes(h, prec)
@@ -372,12 +378,30 @@ def main():
         result["box_grid"] = box_grid_pass(T, torch, geom, h, lay, w, arenas[T.FMM_C64], x32, g32, F32, V32,
                                            tucker_ms, per_stage_bytes["tucker_pass_f32"])
 
+    # ------------------------- the other stated configurations of the same sphere
+    extra = {}
+    if not args.no_dense and not args.no_extra:
+        # Tucker FP64 single-RHS pass (the FP64 plain-method comparison of the paper's
+        # Table III, on the GPU)
+        result["tucker_fp64_pass"], extra["tucker_f64"] = fp64_pass(
+            T, torch, h, lay, w, ranks, x64, g64, sample, result.get("dense_pass_ms"))
+        # tolerance 1e-4 (Table III's first Tucker row), FP32 pass
+        result["gamma_1e-4"], extra["gamma_1e-4_f32"] = gamma_pass(
+            args, T, torch, lay, dense, w, 1e-4, x32, g32, sample, result.get("dense_pass_ms"))
+    if args.workload == "sphere30" and not args.no_extra and not args.no_dense:
+        dense = None
+        torch.cuda.empty_cache()
+        # the coarser 29 x 58 grid the configuration names, dense FP64 and Tucker FP32
+        from synth import workloads as W
+        result["grid_29x58"], extra["grid_29x58"] = grid_pass(args, T, torch, synth, W.SPHERE30_G29, verts,
+                                                               tris, sample)
+
     # ------------------------------------------------------------ multi-RHS section
     mr_out = {}
     if args.nrhs > 0:
         dense = None
         torch.cuda.empty_cache()
-        result["multi_rhs"], mr_out = multi_rhs(args, T, torch, synth, h, lay, ranks, w)
+        result["multi_rhs"], mr_out = multi_rhs(args, T, torch, synth, h, geom, lay, ranks, w, sample)
 
     # ------------------------------------------------ accuracy + CPU baseline (oracle)
     if not args.no_oracle:
@@ -385,8 +409,8 @@ def main():
         F64h = V64h = None
         if not args.no_dense:
             F64h, V64h = F64.cpu().numpy(), V64.cpu().numpy()
-        result.update(oracle_checks(args, w, verts, tris, lay, x, gin, F32h, V32h, F64h, V64h, mr_out,
-                                    svd_out))
+        result.update(oracle_checks(args, w, verts, tris, lay, x, gin, F32h, V32h, F64h, V64h, sample, stored,
+                                    mr_out, svd_out, extra))
 
     T.fmm_dense_destroy(dplan)
     T.fmm_tucker_destroy(h)
@@ -395,6 +419,165 @@ def main():
 
 
 MRHS_PRECS = {"c128": 0, "c64": 1, "bf16x2": 2, "bf16x3": 3}
+
+
+def sampled_groups(synth, nb, n):
+    """Groups checked against the oracle: the largest plus seeded draws (default_rng(4))."""
+    big = int(np.argmax(nb))
+    draws = [int(g) for g in synth.rng(4).choice(nb.size, size=min(n, nb.size), replace=False) if g != big]
+    return sorted([big] + draws[:max(0, n - 1)])
+
+
+def export_sample(T, h, ranks, sample, lay, prec):
+    """Stored factors of the sampled groups as the arena of `prec` holds them, in the
+    oracle's per-group form [(core, (U^theta, U^phi, U^beta))] * 2."""
+    nb = np.diff(lay.offsets)
+    out = {}
+    for g in sample:
+        pair = []
+        for a in range(2):
+            c, ut, up, ub = T.fmm_tucker_export(h, g, a, ranks[g, a], lay.n_theta, lay.n_phi, int(nb[g]),
+                                                as_stored=prec)
+            pair.append((c, (ut, up, ub)))
+        out[g] = pair
+    return out
+
+
+def graph_time(torch, T, h, prec, nrhs, x, F, G, V, reps=10):
+    """Capture the pass in a graph, replay it (3 untimed, `reps` timed) and return the
+    mean ms per replay, HIP events on the graph's stream."""
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        T.fmm_graph_capture(h, prec, nrhs, x, F, G, V, s)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        T.fmm_graph_launch(h, s)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record(s)
+        T.fmm_graph_launch(h, s)
+        b.record(s)
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+
+def sample_outputs(F, V, sample, offsets):
+    return {g: (F[g].cpu().numpy(), V[int(offsets[g]):int(offsets[g + 1])].cpu().numpy()) for g in sample}
+
+
+def fp64_pass(T, torch, h, lay, w, ranks, x64, g64, sample, dense_ms):
+    """Tucker FP64 single-RHS pass (complex128 factors and vectors) on the same handle,
+    graph-captured; algorithmic bytes as the FP32 pass with 16-byte elements."""
+    G, nd, N = lay.n_groups, lay.n_dir, lay.n_basis
+    _, nbytes = T.fmm_tucker_storage_bytes(h, T.FMM_C128)
+    ar = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    T.fmm_tucker_upload(h, T.FMM_C128, ar)
+    F = torch.empty((G, 2, nd), dtype=torch.complex128, device="cuda")
+    V = torch.empty(N, dtype=torch.complex128, device="cuda")
+    ms = graph_time(torch, T, h, T.FMM_C128, 1, x64, F, g64, V)
+    b_stage, fac = tucker_stage_bytes(ranks, lay.offsets, w.n_theta, w.n_phi, 16)
+    gbs = 2 * b_stage / (ms * 1e-3) / 1e9
+    rep = {"pass_ms": round(ms, 4), "GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+           "factors_MB_f64": round(fac / 2 ** 20, 1)}
+    if dense_ms:
+        rep["speedup_vs_dense_f64_pass"] = round(dense_ms / ms, 2)
+    log("tucker FP64 pass: %s" % rep)
+    out = sample_outputs(F, V, sample, lay.offsets)
+    del ar
+    return rep, out
+
+
+def gamma_pass(args, T, torch, lay, dense, w, gamma, x32, g32, sample, dense_ms):
+    """The same far-fields compressed at another tolerance, FP32 pass (graph-captured).
+    Returns the report and (sampled outputs, stored factors of the sample)."""
+    G, nd, N = lay.n_groups, lay.n_dir, lay.n_basis
+    t0 = time.time()
+    h2 = None
+    for g0 in range(0, G, args.setup_chunk):
+        h2 = T.fmm_farfield_compress(lay, dense[int(lay.offsets[g0]):], g0, min(args.setup_chunk, G - g0), gamma,
+                                     handle=h2)
+    t_c = time.time() - t0
+    try:
+        ranks = T.fmm_tucker_ranks(h2, G)
+        fb, nbytes = T.fmm_tucker_storage_bytes(h2, T.FMM_C64)
+        ar = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        T.fmm_tucker_upload(h2, T.FMM_C64, ar)
+        F = torch.empty((G, 2, nd), dtype=torch.complex64, device="cuda")
+        V = torch.empty(N, dtype=torch.complex64, device="cuda")
+        ms = graph_time(torch, T, h2, T.FMM_C64, 1, x32, F, g32, V)
+        b_stage, fac = tucker_stage_bytes(ranks, lay.offsets, w.n_theta, w.n_phi, 8)
+        gbs = 2 * b_stage / (ms * 1e-3) / 1e9
+        fb64, _ = T.fmm_tucker_storage_bytes(h2, T.FMM_C128)
+        rep = {"gamma": gamma, "compress_s": round(t_c, 2), "pass_ms": round(ms, 4), "GBps": round(gbs, 1),
+               "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "factors_MB_f32": round(fb / 2 ** 20, 1),
+               "factors_MB_f64": round(fb64 / 2 ** 20, 1),
+               "ranks_mean": [round(float(v), 2) for v in ranks.reshape(-1, 3).mean(0)]}
+        if dense_ms:
+            rep["speedup_vs_dense_f64_pass"] = round(dense_ms / ms, 2)
+        log("gamma %g FP32 pass: %s" % (gamma, rep))
+        out = (sample_outputs(F, V, sample, lay.offsets), export_sample(T, h2, ranks, sample, lay, T.FMM_C64))
+        del ar
+        return rep, out
+    finally:
+        T.fmm_tucker_destroy(h2)
+
+
+def grid_pass(args, T, torch, synth, wg, verts, tris, sample):
+    """The sphere on another angular grid: dense FP64 far-fields filled, compressed,
+    Tucker FP32 pass (graph) and dense FP64 stages timed, outputs of the sample kept."""
+    geom = T.fmm_geometry_build(verts, tris, wg.origin, wg.box, wg.boxes_per_axis, wg.k, wg.n_theta, wg.n_phi)
+    h = None
+    dplan = None
+    try:
+        lay = T.fmm_geometry_layout(geom)
+        N, G, nd = lay.n_basis, lay.n_groups, lay.n_dir
+        t0 = time.time()
+        dense = torch.empty((N, 2, wg.n_theta, wg.n_phi), dtype=torch.complex128, device="cuda")
+        T.fmm_farfield_fill(geom, 0, G, dense)
+        for g0 in range(0, G, args.setup_chunk):
+            h = T.fmm_farfield_compress(lay, dense[int(lay.offsets[g0]):], g0, min(args.setup_chunk, G - g0),
+                                        wg.gamma, handle=h)
+        t_c = time.time() - t0
+        ranks = T.fmm_tucker_ranks(h, G)
+        fb, nbytes = T.fmm_tucker_storage_bytes(h, T.FMM_C64)
+        ar = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        T.fmm_tucker_upload(h, T.FMM_C64, ar)
+        x = synth.complex_normal(synth.rng(wg.seeds.get("x", 0)), N)
+        gin = synth.complex_normal(synth.rng(wg.seeds.get("g", 1)), (G, 2, nd))
+        x32, g32 = torch.from_numpy(x).to("cuda", torch.complex64), torch.from_numpy(gin).to("cuda", torch.complex64)
+        x64, g64 = torch.from_numpy(x).to("cuda"), torch.from_numpy(gin).to("cuda")
+        F = torch.empty((G, 2, nd), dtype=torch.complex64, device="cuda")
+        V = torch.empty(N, dtype=torch.complex64, device="cuda")
+        ms = graph_time(torch, T, h, T.FMM_C64, 1, x32, F, g32, V)
+        dplan = T.fmm_dense_create(lay)
+        F64 = torch.empty((G, 2, nd), dtype=torch.complex128, device="cuda")
+        V64 = torch.empty(N, dtype=torch.complex128, device="cuda")
+        dagg = time_ms(torch, lambda: T.fmm_dense_aggregate(dplan, T.FMM_C128, dense, 1, x64, F64), reps=5)
+        ddis = time_ms(torch, lambda: T.fmm_dense_disaggregate(dplan, T.FMM_C128, dense, 1, g64, V64), reps=5)
+        b_stage, fac = tucker_stage_bytes(ranks, lay.offsets, wg.n_theta, wg.n_phi, 8)
+        b_d64 = dense_stage_bytes(lay.offsets, wg.n_theta, wg.n_phi, 16)
+        gbs = 2 * b_stage / (ms * 1e-3) / 1e9
+        rep = {"workload": wg.name, "grid": [wg.n_theta, wg.n_phi], "compress_s": round(t_c, 2),
+               "tucker_pass_ms": round(ms, 4), "tucker_pass_GBps": round(gbs, 1),
+               "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+               "dense_pass_ms": round(dagg + ddis, 4),
+               "dense_pass_GBps": round(2 * b_d64 / ((dagg + ddis) * 1e-3) / 1e9, 1),
+               "speedup_vs_dense_pass": round((dagg + ddis) / ms, 2),
+               "memory_MB": {"tucker_factors_f32": round(fb / 2 ** 20, 1),
+                             "dense_f64": round(2 * N * nd * 16 / 2 ** 20, 1)},
+               "ranks_mean": [round(float(v), 2) for v in ranks.reshape(-1, 3).mean(0)]}
+        log("grid %dx%d: %s" % (wg.n_theta, wg.n_phi, rep))
+        out = {"x": x, "gin": gin, "w": wg, "f32": sample_outputs(F, V, sample, lay.offsets),
+               "f64_dense": sample_outputs(F64, V64, sample, lay.offsets),
+               "stored": export_sample(T, h, ranks, sample, lay, T.FMM_C64)}
+        del ar, dense
+        return rep, out
+    finally:
+        if dplan:
+            T.fmm_dense_destroy(dplan)
+        if h:
+            T.fmm_tucker_destroy(h)
+        T.fmm_geometry_destroy(geom)
 
 # L of the angular grid (Section II.A: L = 2kR + (2kR)^(1/3) 1.8 d^(2/3), R half the box
 # diagonal, rounded, plus one) for the sweep points, by (box edge, digits d).
@@ -591,17 +774,20 @@ def svd_comparison(args, T, torch, lay, dense, w, x32, g32, tucker_ms, tucker_fa
         T.fmm_tucker_destroy(hs)
 
 
-def multi_rhs(args, T, torch, synth, h, lay, ranks, w):
+def multi_rhs(args, T, torch, synth, h, geom, lay, ranks, w, sample):
     """Multi-RHS pass (aggregation of x [N][R] + disaggregation of G [G][2][N_dir][R])
-    per precision: autotuned, captured in a graph, replayed.  Returns the report and the
-    sampled outputs for the oracle check."""
+    per precision: autotuned, captured in a graph, replayed.  x holds R plane-wave
+    excitations (eq. (2), directions uniform on the sphere, theta-polarised) computed by
+    the library; G holds seeded complex-Gaussian incoming spectra.  Returns the report
+    and the sampled outputs for the oracle check."""
     R = args.nrhs
     N, G, nd = lay.n_basis, lay.n_groups, lay.n_dir
-    xs = synth.complex_normal(synth.rng(w.seeds.get("x", 0) + 100), (N, R))
+    khat, epol = synth.planewaves(synth.rng(w.seeds.get("x", 0) + 200), R)
     gs = synth.complex_normal(synth.rng(w.seeds.get("g", 1) + 100), (G, 2, nd, R))
     dev = {}
-    rep = {"nrhs": R, "precisions": {}}
-    outs = {"x": xs, "g": gs}
+    rep = {"nrhs": R, "inputs": "x: %d plane-wave excitations (eq. (2)); G: complex Gaussian" % R,
+           "precisions": {}}
+    outs = {"khat": khat, "epol": epol, "g": {g: gs[g] for g in sample}}
     s = torch.cuda.Stream()
     for name in [p for p in args.mrhs_precs.split(",") if p]:
         prec = MRHS_PRECS[name]
@@ -609,7 +795,9 @@ def multi_rhs(args, T, torch, synth, h, lay, ranks, w):
         if dt not in dev:
             dev.clear()   # one dtype's buffers at a time
             torch.cuda.empty_cache()
-            dev[dt] = (torch.from_numpy(xs).to("cuda", dt), torch.from_numpy(gs).to("cuda", dt),
+            xd = torch.empty((N, R), dtype=dt, device="cuda")
+            T.fmm_planewave_excitation(geom, khat, epol, T.FMM_C128 if prec == 0 else T.FMM_C64, xd)
+            dev[dt] = (xd, torch.from_numpy(gs).to("cuda", dt),
                        torch.empty((G, 2, nd, R), dtype=dt, device="cuda"),
                        torch.empty((N, R), dtype=dt, device="cuda"))
         xd, gd, F, V = dev[dt]
@@ -649,68 +837,97 @@ def multi_rhs(args, T, torch, synth, h, lay, ranks, w):
             r["mfma_frac_bf16"] = round(tf * issued / 2500.0, 4)
         rep["precisions"][name] = r
         log("multi-RHS %s R=%d: %.3f ms/pass, %.1f GB/s, %.1f TFLOP/s, tuned %s" % (name, R, ms, gbs, tf, tuned))
-        outs[name] = (F.cpu().numpy(), V.cpu().numpy())
+        outs[name] = sample_outputs(F, V, sample, lay.offsets)
         del ar
     return rep, outs
 
 
-def oracle_checks(args, w, verts, tris, lay, x, gin, F32h, V32h, F64h, V64h, mr_out=None, svd_out=None):
-    """End-to-end error of the GPU outputs against the oracle's dense FP64 products on
-    sampled groups, and the oracle's own throughput on the same sample."""
+def oracle_checks(args, w, verts, tris, lay, x, gin, F32h, V32h, F64h, V64h, sample, stored, mr_out=None,
+                  svd_out=None, extra=None):
+    """Errors of the GPU outputs on the sampled groups against the oracle, and the
+    oracle's own throughput.  Two kinds, relative L2 over the sample:
+      rel_err_vs_oracle      end to end: against the dense products with the far-fields
+                             of eq. (4) (the compression error included);
+      arith_err_vs_oracle    arithmetic only: against the oracle's Tucker chain (Fig.
+                             2(b) / 3(b)) on the factors as the arena stores them and
+                             on the inputs as the path takes them."""
     from oracle import geometry as geo
     from oracle import farfield as ff
     from oracle import hosvd as H
     from oracle import products as pr
+    from oracle import excitation as ex
     import synth
 
     P = geo.Problem(verts, tris, w.origin, w.box, w.boxes_per_axis, w.n_theta, w.n_phi)
     assert np.array_equal(P.offsets, lay.offsets)
-    rng = synth.rng(4)
     nb = P.group_sizes()
-    # sample across the size distribution: largest group plus seeded draws
-    sample = sorted(set([int(np.argmax(nb))] + list(rng.choice(P.n_groups, size=args.sample_groups - 1,
-                                                                   replace=False))))
-    errs = {"tucker_f32_agg": [], "tucker_f32_disagg": [], "dense_f64_agg": [], "dense_f64_disagg": [],
-            "svd_f32_agg": [], "svd_f32_disagg": []}
-    ref_f, ref_v, got = [], [], {k: [] for k in errs}
-    blocks = {}
-    for g in sample:
-        lo, hi = int(P.offsets[g]), int(P.offsets[g + 1])
-        blk = ff.farfield_group(P, g)
-        blocks[g] = blk
-        ref_f.append(pr.dense_aggregate(blk, x[lo:hi]))
-        ref_v.append(pr.dense_disaggregate(blk, gin[g]))
-        got["tucker_f32_agg"].append(F32h[g])
-        got["tucker_f32_disagg"].append(V32h[lo:hi])
-        if F64h is not None:
-            got["dense_f64_agg"].append(F64h[g])
-            got["dense_f64_disagg"].append(V64h[lo:hi])
-        if svd_out is not None:
-            got["svd_f32_agg"].append(svd_out[0][g])
-            got["svd_f32_disagg"].append(svd_out[1][lo:hi])
-    out = {"rel_err_vs_oracle": {}}
-    for k in errs:
-        if not got[k]:
-            continue
-        ref = ref_f if k.endswith("_agg") else ref_v
-        out["rel_err_vs_oracle"][k] = float(pr.rel_err(np.concatenate([np.ravel(a) for a in got[k]]),
-                                                        np.concatenate([np.ravel(a) for a in ref])))
+    off = P.offsets
+    blocks = {g: ff.farfield_group(P, g) for g in sample}
+    c64 = lambda a: np.asarray(a).astype(np.complex64).astype(np.complex128)   # noqa: E731
+
+    def err(got_by_g, ref_by_g):
+        """(agg, disagg) relative L2 over the sample; entries are (F_g, V_g) pairs."""
+        return tuple(float(pr.rel_err(np.concatenate([np.ravel(got_by_g[g][k]) for g in sample]),
+                                      np.concatenate([np.ravel(ref_by_g[g][k]) for g in sample])))
+                     for k in (0, 1))
+
+    def dense_ref(xx, gg, blk=blocks):
+        return {g: (pr.dense_aggregate(blk[g], xx[g]), pr.dense_disaggregate(blk[g], gg[g])) for g in sample}
+
+    def tucker_ref(facs, xx, gg):
+        return {g: (pr.tucker_aggregate(facs[g], xx[g]), pr.tucker_disaggregate(facs[g], gg[g])) for g in sample}
+
+    e2e, arith = {}, {}
+
+    def put(table, name, pair):
+        table[name + "_agg"], table[name + "_disagg"] = pair
+
+    xg = {g: x[off[g]:off[g + 1]] for g in sample}
+    gg = {g: gin[g] for g in sample}
+    ref1 = dense_ref(xg, gg)
+    got32 = {g: (F32h[g], V32h[off[g]:off[g + 1]]) for g in sample}
+    put(e2e, "tucker_f32", err(got32, ref1))
+    put(arith, "tucker_f32", err(got32, tucker_ref(stored["c64"], {g: c64(v) for g, v in xg.items()},
+                                                   {g: c64(v) for g, v in gg.items()})))
+    if F64h is not None:
+        put(e2e, "dense_f64", err({g: (F64h[g], V64h[off[g]:off[g + 1]]) for g in sample}, ref1))
+    if svd_out is not None:
+        put(e2e, "svd_f32", err({g: (svd_out[0][g], svd_out[1][off[g]:off[g + 1]]) for g in sample}, ref1))
+    extra = extra or {}
+    if "tucker_f64" in extra:
+        put(e2e, "tucker_f64", err(extra["tucker_f64"], ref1))
+        put(arith, "tucker_f64", err(extra["tucker_f64"], tucker_ref(stored["c128"], xg, gg)))
+    if "gamma_1e-4_f32" in extra:
+        outs, facs = extra["gamma_1e-4_f32"]
+        put(e2e, "gamma_1e-4_f32", err(outs, ref1))
+        put(arith, "gamma_1e-4_f32", err(outs, tucker_ref(facs, {g: c64(v) for g, v in xg.items()},
+                                                          {g: c64(v) for g, v in gg.items()})))
+    if "grid_29x58" in extra:
+        o = extra["grid_29x58"]
+        wg = o["w"]
+        Pg = geo.Problem(verts, tris, wg.origin, wg.box, wg.boxes_per_axis, wg.n_theta, wg.n_phi)
+        bg = {g: ff.farfield_group(Pg, g) for g in sample}
+        xg2 = {g: o["x"][off[g]:off[g + 1]] for g in sample}
+        gg2 = {g: o["gin"][g] for g in sample}
+        r2 = dense_ref(xg2, gg2, bg)
+        put(e2e, "grid_29x58_tucker_f32", err(o["f32"], r2))
+        put(e2e, "grid_29x58_dense_f64", err(o["f64_dense"], r2))
+        put(arith, "grid_29x58_tucker_f32", err(o["f32"], tucker_ref(o["stored"], {g: c64(v) for g, v in xg2.items()},
+                                                                     {g: c64(v) for g, v in gg2.items()})))
     if mr_out:
-        xs, gs = mr_out["x"], mr_out["g"]
-        rf, rv = [], []
-        for g in sample:
-            lo, hi = int(P.offsets[g]), int(P.offsets[g + 1])
-            rf.append(np.ravel(pr.dense_aggregate(blocks[g], xs[lo:hi])))
-            rv.append(np.ravel(pr.dense_disaggregate(blocks[g], gs[g])))
-        rf, rv = np.concatenate(rf), np.concatenate(rv)
-        for name in [k for k in mr_out if k not in ("x", "g")]:
-            Fm, Vm = mr_out[name]
-            gf = np.concatenate([np.ravel(Fm[g]) for g in sample])
-            gv = np.concatenate([np.ravel(Vm[int(P.offsets[g]):int(P.offsets[g + 1])]) for g in sample])
-            out["rel_err_vs_oracle"]["mrhs_%s_agg" % name] = float(pr.rel_err(gf, rf))
-            out["rel_err_vs_oracle"]["mrhs_%s_disagg" % name] = float(pr.rel_err(gv, rv))
-    out["rel_err_sample_groups"] = [int(g) for g in sample]
-    log("errors vs oracle: %s" % out["rel_err_vs_oracle"])
+        xs = {g: ex.planewave_excitation(P, mr_out["khat"], mr_out["epol"], rows=np.arange(off[g], off[g + 1]))
+              for g in sample}
+        gs = mr_out["g"]
+        rR = dense_ref(xs, gs)
+        r64 = tucker_ref(stored["c128"], xs, gs)
+        r32 = tucker_ref(stored["c64"], {g: c64(v) for g, v in xs.items()}, gs)
+        for name in [k for k in mr_out if k not in ("khat", "epol", "g")]:
+            put(e2e, "mrhs_%s" % name, err(mr_out[name], rR))
+            put(arith, "mrhs_%s" % name, err(mr_out[name], r64 if name == "c128" else r32))
+    out = {"rel_err_vs_oracle": e2e, "arith_err_vs_oracle": arith,
+           "rel_err_sample_groups": [int(g) for g in sample]}
+    log("errors vs oracle (end to end): %s" % e2e)
+    log("errors vs oracle (arithmetic only): %s" % arith)
 
     # Oracle throughput.  The sampled groups alone (tens of MB) would sit in the host's
     # last-level cache, so the timing sample is a contiguous run of groups whose FP64

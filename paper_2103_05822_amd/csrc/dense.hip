@@ -5,6 +5,7 @@
 //                                                         rows walked in order
 //   disaggregation V[n] = sum_col conj(A[n][col]) G[g][col]   one wavefront per row,
 //                                                         lane-strided, butterfly sum
+// with up to 8 right-hand sides per read of A.
 #include <hip/hip_runtime.h>
 #include "cplx.hpp"
 #include "kernels.hpp"
@@ -15,28 +16,37 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kCols = 2;     // columns per thread in aggregation
-constexpr int kRowUnroll = 4;
 
-template <typename T>
+// Right-hand sides are taken RB at a time (blockIdx.y walks the blocks of RB): every
+// element of A read from HBM serves RB right-hand sides, so a pass over R <= 8 of
+// them reads A once.  nr = min(RB, nrhs - r0) of a block's RB columns are valid.
+
+template <typename T, int RB>
 __global__ __launch_bounds__(kThreads) void dense_agg_kernel(const typename Tr<T>::c* __restrict__ A,
                                                              const DenseGroup* __restrict__ groups, int n_chunks,
                                                              int ncols, int nrhs,
                                                              const typename Tr<T>::c* __restrict__ x,
                                                              typename Tr<T>::c* __restrict__ F) {
   using C = typename Tr<T>::c;
+  // rows per iteration: the x values of a row are uniform across the workgroup and
+  // live in scalar registers, RB of them per row
+  constexpr int kRowUnroll = RB >= 4 ? 2 : 4;
   const int g = blockIdx.x / n_chunks;
   const int chunk = blockIdx.x - g * n_chunks;
-  const int r = blockIdx.y;
+  const int r0 = blockIdx.y * RB;
+  const int nr = min(RB, nrhs - r0);
   const DenseGroup grp = groups[g];
   const int c0 = chunk * kThreads * kCols + threadIdx.x;
   bool in[kCols];
 #pragma unroll
   for (int j = 0; j < kCols; ++j) in[j] = c0 + kThreads * j < ncols;
-  C acc[kCols];
+  C acc[kCols][RB];
 #pragma unroll
-  for (int j = 0; j < kCols; ++j) acc[j] = czero<C>();
+  for (int j = 0; j < kCols; ++j)
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[j][r] = czero<C>();
   const C* base = A + grp.row0 * ncols + c0;
-  const C* xb = x + grp.row0 * nrhs + r;
+  const C* xb = x + grp.row0 * nrhs + r0;
   int n = 0;
   for (; n + kRowUnroll <= grp.nb; n += kRowUnroll) {
     C a[kRowUnroll][kCols];
@@ -47,23 +57,37 @@ __global__ __launch_bounds__(kThreads) void dense_agg_kernel(const typename Tr<T
         a[u][j] = in[j] ? base[(int64_t)(n + u) * ncols + kThreads * j] : czero<C>();
 #pragma unroll
     for (int u = 0; u < kRowUnroll; ++u) {
-      const C xn = xb[(int64_t)(n + u) * nrhs];
+      C xn[RB];
 #pragma unroll
-      for (int j = 0; j < kCols; ++j) cfma(acc[j], a[u][j], xn);
+      for (int r = 0; r < RB; ++r) xn[r] = r < nr ? xb[(int64_t)(n + u) * nrhs + r] : czero<C>();
+#pragma unroll
+      for (int j = 0; j < kCols; ++j)
+#pragma unroll
+        for (int r = 0; r < RB; ++r) cfma(acc[j][r], a[u][j], xn[r]);
     }
   }
   for (; n < grp.nb; ++n) {
-    const C xn = xb[(int64_t)n * nrhs];
+    C xn[RB];
 #pragma unroll
-    for (int j = 0; j < kCols; ++j)
-      if (in[j]) cfma(acc[j], base[(int64_t)n * ncols + kThreads * j], xn);
+    for (int r = 0; r < RB; ++r) xn[r] = r < nr ? xb[(int64_t)n * nrhs + r] : czero<C>();
+#pragma unroll
+    for (int j = 0; j < kCols; ++j) {
+      const C a = in[j] ? base[(int64_t)n * ncols + kThreads * j] : czero<C>();
+#pragma unroll
+      for (int r = 0; r < RB; ++r) cfma(acc[j][r], a, xn[r]);
+    }
   }
 #pragma unroll
   for (int j = 0; j < kCols; ++j)
-    if (in[j]) F[((int64_t)g * ncols + c0 + kThreads * j) * nrhs + r] = acc[j];
+    if (in[j]) {
+      C* out = F + ((int64_t)g * ncols + c0 + kThreads * j) * nrhs + r0;
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+        if (r < nr) out[r] = acc[j][r];
+    }
 }
 
-template <typename T>
+template <typename T, int RB>
 __global__ __launch_bounds__(kThreads) void dense_disagg_kernel(const typename Tr<T>::c* __restrict__ A,
                                                                 const int64_t* __restrict__ offsets,
                                                                 int n_groups, int64_t n_rows, int ncols,
@@ -71,9 +95,11 @@ __global__ __launch_bounds__(kThreads) void dense_disagg_kernel(const typename T
                                                                 const typename Tr<T>::c* __restrict__ Gin,
                                                                 typename Tr<T>::c* __restrict__ V) {
   using C = typename Tr<T>::c;
+  constexpr int U = RB == 1 ? 4 : (RB <= 4 ? 2 : 1);  // columns in flight per lane
   const int lane = threadIdx.x & 63;
   const int64_t n = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
-  const int r = blockIdx.y;
+  const int r0 = blockIdx.y * RB;
+  const int nr = min(RB, nrhs - r0);
   if (n >= n_rows) return;  // no barrier below
   // group of row n: largest g with offsets[g] <= n
   int lo = 0, hi = n_groups;
@@ -82,26 +108,70 @@ __global__ __launch_bounds__(kThreads) void dense_disagg_kernel(const typename T
     if (offsets[mid] <= n) lo = mid; else hi = mid;
   }
   const C* row = A + n * ncols;
-  const C* gv = Gin + (int64_t)lo * ncols * nrhs + r;
-  C a0 = czero<C>(), a1 = czero<C>(), a2 = czero<C>(), a3 = czero<C>();
+  const C* gv = Gin + (int64_t)lo * ncols * nrhs + r0;
+  C acc[U][RB];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[u][r] = czero<C>();
   int c = lane;
-  for (; c + 192 < ncols; c += 256) {
-    const C u0 = row[c], u1 = row[c + 64], u2 = row[c + 128], u3 = row[c + 192];
-    const C g0 = gv[(int64_t)c * nrhs], g1 = gv[(int64_t)(c + 64) * nrhs];
-    const C g2 = gv[(int64_t)(c + 128) * nrhs], g3 = gv[(int64_t)(c + 192) * nrhs];
-    cfma_conj(a0, u0, g0);
-    cfma_conj(a1, u1, g1);
-    cfma_conj(a2, u2, g2);
-    cfma_conj(a3, u3, g3);
+  for (; c + 64 * (U - 1) < ncols; c += 64 * U) {
+    C a[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) a[u] = row[c + 64 * u];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+        if (r < nr) cfma_conj(acc[u][r], a[u], gv[(int64_t)(c + 64 * u) * nrhs + r]);
   }
-  for (; c < ncols; c += 64) cfma_conj(a0, row[c], gv[(int64_t)c * nrhs]);
-  a0.x += a1.x + a2.x + a3.x;
-  a0.y += a1.y + a2.y + a3.y;
-  a0 = wave_sum(a0);
-  if (lane == 0) V[n * nrhs + r] = a0;
+  for (; c < ncols; c += 64) {
+    const C a = row[c];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+      if (r < nr) cfma_conj(acc[0][r], a, gv[(int64_t)c * nrhs + r]);
+  }
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    C s = acc[0][r];
+#pragma unroll
+    for (int u = 1; u < U; ++u) {
+      s.x += acc[u][r].x;
+      s.y += acc[u][r].y;
+    }
+    s = wave_sum(s);
+    if (lane == 0 && r < nr) V[n * nrhs + r0 + r] = s;
+  }
 }
 
+// RB for a call: the smallest of 1, 2, 4, 8 covering nrhs (8 beyond).
+int rhs_block(int nrhs) { return nrhs >= 8 ? 8 : (nrhs > 2 ? 4 : nrhs); }
+
 }  // namespace
+
+#define TFMM_RB_SWITCH(rb, ...) \
+  switch (rb) {                  \
+    case 1: {                    \
+      constexpr int RB = 1;      \
+      __VA_ARGS__;               \
+      break;                     \
+    }                            \
+    case 2: {                    \
+      constexpr int RB = 2;      \
+      __VA_ARGS__;               \
+      break;                     \
+    }                            \
+    case 4: {                    \
+      constexpr int RB = 4;      \
+      __VA_ARGS__;               \
+      break;                     \
+    }                            \
+    default: {                   \
+      constexpr int RB = 8;      \
+      __VA_ARGS__;               \
+      break;                     \
+    }                            \
+  }
 
 template <typename T>
 hipError_t launch_dense_agg(const void* A, const DenseGroup* groups, int n_groups, int ncols, int nrhs,
@@ -109,9 +179,11 @@ hipError_t launch_dense_agg(const void* A, const DenseGroup* groups, int n_group
   using C = typename Tr<T>::c;
   if (n_groups == 0) return hipSuccess;
   const int n_chunks = (ncols + kThreads * kCols - 1) / (kThreads * kCols);
-  dim3 grid((unsigned)n_groups * n_chunks, nrhs);
-  hipLaunchKernelGGL(dense_agg_kernel<T>, grid, dim3(kThreads), 0, s, static_cast<const C*>(A), groups, n_chunks,
-                     ncols, nrhs, static_cast<const C*>(x), static_cast<C*>(F));
+  const int rb = rhs_block(nrhs);
+  dim3 grid((unsigned)n_groups * n_chunks, (nrhs + rb - 1) / rb);
+  TFMM_RB_SWITCH(rb, hipLaunchKernelGGL((dense_agg_kernel<T, RB>), grid, dim3(kThreads), 0, s,
+                                        static_cast<const C*>(A), groups, n_chunks, ncols, nrhs,
+                                        static_cast<const C*>(x), static_cast<C*>(F)))
   return hipGetLastError();
 }
 
@@ -121,9 +193,11 @@ hipError_t launch_dense_disagg(const void* A, const int64_t* offsets, int n_grou
   using C = typename Tr<T>::c;
   if (n_rows == 0) return hipSuccess;
   const int64_t blocks = (n_rows + kThreads / 64 - 1) / (kThreads / 64);
-  dim3 grid((unsigned)blocks, nrhs);
-  hipLaunchKernelGGL(dense_disagg_kernel<T>, grid, dim3(kThreads), 0, s, static_cast<const C*>(A), offsets,
-                     n_groups, n_rows, ncols, nrhs, static_cast<const C*>(G), static_cast<C*>(V));
+  const int rb = rhs_block(nrhs);
+  dim3 grid((unsigned)blocks, (nrhs + rb - 1) / rb);
+  TFMM_RB_SWITCH(rb, hipLaunchKernelGGL((dense_disagg_kernel<T, RB>), grid, dim3(kThreads), 0, s,
+                                        static_cast<const C*>(A), offsets, n_groups, n_rows, ncols, nrhs,
+                                        static_cast<const C*>(G), static_cast<C*>(V)))
   return hipGetLastError();
 }
 

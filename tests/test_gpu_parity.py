@@ -218,8 +218,11 @@ def test_tucker_deterministic_and_graph_replays():
 # ------------------------------------------------------------------------------- dense
 
 @pytest.mark.parametrize("prec", [T.FMM_C128, T.FMM_C64], ids=["c128", "c64"])
-@pytest.mark.parametrize("nrhs", [1, 2])
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 8, 66])
 def test_dense_ragged_layout(prec, nrhs):
+    """Dense products against the oracle: right-hand sides in blocks of 1, 2, 4 and 8
+    per read of A, ragged blocks (3 = one block of 4 with 3 valid, 66 = 8 blocks of 8
+    and one with 2 valid)."""
     lay = ragged_layout(7, 13)
     banner("dense ragged prec=%d nrhs=%d" % (prec, nrhs))
     rng = synth.rng(9)
