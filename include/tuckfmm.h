@@ -55,12 +55,16 @@ typedef enum {
 /* Storage / arithmetic precision of a compute path.
  *   FMM_C128   complex128 factors, FP64 arithmetic; x, F, G, V are complex128.
  *   FMM_C64    complex64 factors, FP32 arithmetic; x, F, G, V are complex64.
- *   FMM_BF16X2 complex64 factors and vectors; the products run on the bf16 matrix
- *              cores: every FP32 operand is split into two bf16 pieces (hi + lo) and
+ *   FMM_BF16X2 complex64 vectors; the products run on the bf16 matrix cores: every
+ *              operand is split into two bf16 pieces (hi + lo of its float value) and
  *              each product accumulates hi*hi + hi*lo + lo*hi in FP32 (relative
- *              error of a product about 2^-16).  Needs an even nrhs.
+ *              error of a product about 2^-16).  The arena stores the factors already
+ *              split (4-byte pieces, both orientations of each factor: about twice
+ *              the complex64 arena); intermediates are split by the product that
+ *              writes them.  Needs an even nrhs.
  *   FMM_BF16X3 as FMM_BF16X2 with three pieces (hi + mid + lo) and the six products
- *              down to order 2^-16 (FP32-level error).  Needs an even nrhs.
+ *              down to order 2^-16 (FP32-level error; an arena about three times the
+ *              complex64 one).  Needs an even nrhs.
  *
  * Kernels.  The streaming kernels run one workgroup per (group, polarisation,
  * right-hand side) and stream the factors from HBM once per right-hand side; they take
@@ -74,8 +78,8 @@ typedef enum {
  * or angular intermediate there: about 10,000 complex128 values on 160 KB).  The
  * matrix-core path computes every contraction of
  * Section II.C as one grouped complex GEMM over all (group, polarisation) items for a
- * chunk of right-hand sides (factors read once per chunk); it needs 16-byte aligned
- * vectors and keeps library-owned device tables and scratch per nrhs (freed by a new
+ * chunk of right-hand sides (factors read once per chunk); it keeps library-owned
+ * device tables and scratch per nrhs (freed by a new
  * upload, fmm_tucker_set_group or fmm_tucker_destroy).  Calls of one handle and
  * precision that use the matrix-core path share that scratch: they must not run
  * concurrently on different streams.  In layouts of fewer than 128 (group,
@@ -105,7 +109,8 @@ typedef struct fmm_dense_s* fmm_dense_t;         /* plan of the dense (plain) me
  * valid until the next library call on the same thread. */
 const char* fmm_last_error(void);
 
-/* Library version string, e.g. "tuckfmm 0.1 gfx950". */
+/* Library version string, e.g. "tuckfmm 0.2 gfx950 src 0123456789abcdef" (the last
+ * word: a hash of the kernel sources the library was built from). */
 const char* fmm_version(void);
 
 /* Number of usable HIP devices (0 when no GPU is present).  Never fails. */
@@ -271,10 +276,11 @@ fmm_status fmm_tucker_ranks(fmm_tucker_t h, int32_t* ranks);
 /* Copy the factors of one (group, polarisation) of eq. (6) into host complex128
  * buffers in the paper's shapes (sizes from fmm_tucker_ranks; any pointer may be NULL).
  *   as_stored  FMM_C128: the handle's FP64 factors as they are.
- *              FMM_C64, FMM_BF16X2, FMM_BF16X3: every real and imaginary part rounded
- *              to the nearest float and widened back, i.e. exactly the complex64
- *              values an upload of that precision stores (the bf16 pieces of the split
- *              precisions are formed from these on chip).
+ *              FMM_C64, FMM_BF16X3: every real and imaginary part rounded to the
+ *              nearest float and widened back, the value an upload of FMM_C64 stores
+ *              and the sum of the three bf16 pieces an FMM_BF16X3 upload stores.
+ *              FMM_BF16X2: the sum of the two bf16 pieces of that float (hi = its
+ *              bf16 rounding, lo = the rounding of the rest) an upload stores.
  * With as_stored = the upload's precision, a plain FP64 contraction of the exported
  * factors (Fig. 2(b), Fig. 3(b)) is the exact result the compute calls approximate:
  * their difference is the arithmetic error alone, free of the compression error.
@@ -343,25 +349,41 @@ fmm_status fmm_tucker_pass_noalloc(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, 
 /* Launch the captured pass on `stream`. */
 fmm_status fmm_graph_launch(fmm_tucker_t h, void* stream);
 
-/* Result of fmm_tucker_tune: path 0 = streaming kernels with `threads` (64, 128, 256
- * or 512) per workgroup, 1 = matrix-core products with `tile_steps` K steps per
- * workgroup and `rhs_chunk` right-hand sides per chunk; ms = mean time of one pass of
- * the winner. */
+/* A kernel configuration for one nrhs: path 0 = streaming kernels with `threads` (64,
+ * 128, 256 or 512) per workgroup; path 1 = matrix-core products with `tile_steps` K
+ * steps per workgroup, `rhs_chunk` right-hand sides per chunk and the angular
+ * contraction `order` (0: each item's cheaper order, 1: U^theta first, 2: U^phi first,
+ * for every item); ms = mean time of one pass; from_cache = 1 when fmm_tucker_tune
+ * took the result from its cache file. */
 typedef struct {
   int32_t path;
   int32_t tile_steps;
   int32_t rhs_chunk;
   int32_t threads;
   float ms;
+  int32_t order;
+  int32_t from_cache;
 } fmm_tune_result;
 
 /* Autotuner: times fmm_tucker_pass with these buffers under each candidate
  * configuration for (prec, nrhs) (1 warm-up + 3 timed passes each, HIP events on the
- * stream), keeps the fastest for later calls with this nrhs and reports it in *out
- * (may be NULL).  Overwrites F and V; synchronises the stream; drops a captured graph.
- * Not allowed while the stream is capturing. */
+ * stream): the four streaming workgroup sizes, and on the matrix cores 8, 16 and 32 K
+ * steps per tile, up to three chunk sizes and the three angular orders.  Keeps the
+ * fastest for later calls with this nrhs and reports it in *out (may be NULL).  With
+ * the environment variable TUCKFMM_TUNE_CACHE naming a file, a result stored there
+ * for the same layout shapes (groups, ranks, box grid), precision, nrhs and kernel
+ * sources is applied without timing (F and V are then left untouched), and a new
+ * result is appended to the file.  Otherwise overwrites F and V.  Synchronises the
+ * stream; drops a captured graph.  Not allowed while the stream is capturing. */
 fmm_status fmm_tucker_tune(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F, const void* G,
                            void* V, void* stream, fmm_tune_result* out);
+
+/* Use `choice` (path, tile_steps, rhs_chunk, threads, order; ms and from_cache are
+ * ignored) for later calls of precision `prec` with this nrhs, e.g. a result kept from
+ * an earlier fmm_tucker_tune.  FMM_ERR_ARG for values out of range, FMM_ERR_UNSUPPORTED
+ * for a path the precision or layout cannot take, FMM_ERR_STATE before an upload.
+ * Drops a captured graph; a new upload or set_group forgets the choice. */
+fmm_status fmm_tucker_set_tuned(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const fmm_tune_result* choice);
 
 void fmm_tucker_destroy(fmm_tucker_t h);
 

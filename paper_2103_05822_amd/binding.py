@@ -27,7 +27,8 @@ __all__ = [
     "fmm_tucker_ranks", "fmm_tucker_export", "fmm_tucker_storage_bytes", "fmm_tucker_upload",
     "fmm_tucker_aggregate", "fmm_tucker_disaggregate", "fmm_tucker_pass", "fmm_tucker_pass_noalloc",
     "fmm_graph_capture", "fmm_graph_launch",
-    "fmm_tucker_tune", "fmm_tucker_destroy", "fmm_dense_create", "fmm_dense_aggregate", "fmm_dense_disaggregate",
+    "fmm_tucker_tune", "fmm_tucker_set_tuned", "fmm_tucker_destroy", "fmm_dense_create", "fmm_dense_aggregate",
+    "fmm_dense_disaggregate",
     "fmm_dense_destroy",
 ]
 
@@ -62,7 +63,8 @@ class fmm_layout(ctypes.Structure):
 
 class fmm_tune_result(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("tile_steps", ctypes.c_int32), ("rhs_chunk", ctypes.c_int32),
-                ("threads", ctypes.c_int32), ("ms", ctypes.c_float)]
+                ("threads", ctypes.c_int32), ("ms", ctypes.c_float), ("order", ctypes.c_int32),
+                ("from_cache", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -104,6 +106,7 @@ _SIGS = {
     "fmm_graph_capture": (_st, [_vp, _st, _i32, _vp, _vp, _vp, _vp, _vp]),
     "fmm_graph_launch": (_st, [_vp, _vp]),
     "fmm_tucker_tune": (_st, [_vp, _st, _i32, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(fmm_tune_result)]),
+    "fmm_tucker_set_tuned": (_st, [_vp, _st, _i32, ctypes.POINTER(fmm_tune_result)]),
     "fmm_tucker_destroy": (None, [_vp]),
     "fmm_dense_create": (_st, [ctypes.POINTER(fmm_layout), ctypes.POINTER(_vp)]),
     "fmm_dense_aggregate": (_st, [_vp, _st, _vp, _i32, _vp, _vp, _vp]),
@@ -368,12 +371,18 @@ def fmm_graph_launch(h, stream=None):
 
 
 def fmm_tucker_tune(h, prec, nrhs, x, F, G, V, stream=None):
-    """Returns a dict with the chosen path, tile_steps, rhs_chunk, threads and ms per pass."""
+    """Returns a dict with the chosen path, tile_steps, rhs_chunk, threads, order, ms per
+    pass and from_cache."""
     r = fmm_tune_result()
     _check(_lib.fmm_tucker_tune(h, int(prec), int(nrhs), _ptr(x), _ptr(F), _ptr(G), _ptr(V), _stream(stream),
                                 ctypes.byref(r)))
     return {"path": r.path, "tile_steps": r.tile_steps, "rhs_chunk": r.rhs_chunk, "threads": r.threads,
-            "ms": r.ms}
+            "order": r.order, "ms": r.ms, "from_cache": r.from_cache}
+
+
+def fmm_tucker_set_tuned(h, prec, nrhs, path, tile_steps=0, rhs_chunk=0, threads=0, order=0):
+    r = fmm_tune_result(int(path), int(tile_steps), int(rhs_chunk), int(threads), 0.0, int(order), 0)
+    _check(_lib.fmm_tucker_set_tuned(h, int(prec), int(nrhs), ctypes.byref(r)))
 
 
 def fmm_tucker_destroy(h):

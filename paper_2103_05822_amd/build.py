@@ -29,9 +29,9 @@ COMMON = [
 LIBS = ["-lrocblas", "-lrocsolver"]
 
 
-def _compile(src):
+def _compile(src, defines=()):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *COMMON, *defines, "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd.insert(1, "-x")
         cmd.insert(2, "hip")
@@ -45,11 +45,25 @@ def _compile(src):
     return obj
 
 
+def source_sha():
+    """First 16 hex digits of the SHA-256 of the kernel sources and the header (the
+    library reports it in fmm_version and keys its tuning cache with it)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    with open(os.path.join(ROOT, "include", "tuckfmm.h"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose=False):
     """Compile every source and link the shared library.  Always recompiles."""
     os.makedirs(BUILD, exist_ok=True)
+    defines = ['-DTUCKFMM_SOURCE_SHA="%s"' % source_sha()]
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda src: _compile(src, defines), SOURCES))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, *LIBS]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -11,6 +11,11 @@
 #include "internal.hpp"
 #include "kernels.hpp"
 
+// hash of the kernel sources, set by the build
+#ifndef TUCKFMM_SOURCE_SHA
+#define TUCKFMM_SOURCE_SHA "unknown"
+#endif
+
 namespace tuckfmm {
 
 namespace {
@@ -92,6 +97,8 @@ struct ArenaPlan {
   int64_t part_stride = 0;
   std::vector<int32_t> order, pass, zero_rows;
   TuckMax mx{};
+  int np = 0;                    // split precisions: bf16 pieces per value
+  std::vector<SplitItem> split;  // and their block offsets
 };
 
 // Bytes streamed by one item (U^beta and the core), the key of the work lists.
@@ -125,12 +132,25 @@ fmm_status plan_arena(const fmm_tucker_s* h, fmm_prec prec, ArenaPlan* P) {
   const size_t es = elem_bytes(prec);
   const int E = pack_elems(prec);
   const size_t blk_align = 256;
+  const int np = split_pieces(prec);
+  P->np = np;
   P->items.resize((size_t)2 * G);
+  if (np) P->split.assign((size_t)2 * G, SplitItem{});
   size_t off = 0;  // bytes inside the factor area
   auto block = [&](size_t n_el) {
     const size_t start = off;
     off = align_up(off + n_el * es, blk_align);
     return start;
+  };
+  // split precisions: rows x cols words per plane, rows of a multiple of 4 words
+  // (16-byte loads of four K values), planes and blocks on 256-byte boundaries
+  auto wblock = [&](int rows, int cols) {
+    SplitBlock b;
+    b.ld = (cols + 3) / 4 * 4;
+    b.plane = (int64_t)align_up((size_t)rows * b.ld, 64);
+    b.off = (int64_t)(off / 4);
+    off += (size_t)np * b.plane * 4;
+    return b;
   };
   TuckMax mx{};
   for (int g = 0; g < G; ++g) {
@@ -153,12 +173,33 @@ fmm_status plan_arena(const fmm_tucker_s* h, fmm_prec prec, ArenaPlan* P) {
       const double c_phi = (double)it.rt * L.n_phi * (it.rp + L.n_theta);
       it.theta_first = c_theta <= c_phi ? 1 : 0;
       it.ident = tf.ident ? 1 : 0;
-      it.off_ubt = (int64_t)(block((size_t)it.rb * it.ld_ub) / es);
-      it.off_core = (int64_t)(block((size_t)it.rb * it.ld_c) / es);
-      if (!it.ident) {  // identity angular factors are not stored
-        it.off_ut = (int64_t)(block((size_t)L.n_theta * it.rt) / es);
-        it.off_up = (int64_t)(block((size_t)L.n_phi * it.rp) / es);
-        it.off_upt = (int64_t)(block((size_t)L.n_phi * it.rp) / es);
+      if (np == 0) {
+        it.off_ubt = (int64_t)(block((size_t)it.rb * it.ld_ub) / es);
+        it.off_core = (int64_t)(block((size_t)it.rb * it.ld_c) / es);
+        if (!it.ident) {  // identity angular factors are not stored
+          it.off_ut = (int64_t)(block((size_t)L.n_theta * it.rt) / es);
+          it.off_up = (int64_t)(block((size_t)L.n_phi * it.rp) / es);
+          it.off_upt = (int64_t)(block((size_t)L.n_phi * it.rp) / es);
+        }
+      } else {
+        // split precision: np planes of 4-byte words per block, both orientations
+        SplitItem& sp = P->split[2 * g + a];
+        const int Q = it.rt * it.rp;
+        sp.ubt = wblock(it.rb, it.nb);
+        sp.ub = wblock(it.nb, it.rb);
+        sp.core = wblock(it.rb, Q);
+        sp.coret = wblock(Q, it.rb);
+        if (!it.ident) {
+          sp.ut = wblock(L.n_theta, it.rt);
+          sp.utt = wblock(it.rt, L.n_theta);
+          sp.up = wblock(L.n_phi, it.rp);
+          sp.upt = wblock(it.rp, L.n_phi);
+        }
+        it.off_ubt = sp.ubt.off;
+        it.off_core = sp.core.off;
+        it.off_ut = sp.ut.off;
+        it.off_up = sp.up.off;
+        it.off_upt = sp.upt.off;
       }
       P->items[2 * g + a] = it;
       mx.nb = std::max(mx.nb, it.nb);
@@ -167,9 +208,12 @@ fmm_status plan_arena(const fmm_tucker_s* h, fmm_prec prec, ArenaPlan* P) {
       mx.rb = std::max(mx.rb, it.rb);
       mx.q = std::max(mx.q, it.rt * it.rp);
       if (!it.ident) mx.t3 = std::max(mx.t3, it.theta_first ? L.n_theta * it.rp : it.rt * L.n_phi);
+      // the paper's measure: core + factors once, at the stored bytes per value
+      // (np bf16 pairs of 4 bytes for the split precisions)
+      const size_t vb = np ? (size_t)4 * np : es;
       P->factor_bytes_paper +=
-          it.ident ? es * ((size_t)it.rt * it.rp * it.rb + (size_t)it.nb * it.rb)   // W and U^beta
-                   : es * ((size_t)it.rt * it.rp * it.rb + (size_t)L.n_theta * it.rt + (size_t)L.n_phi * it.rp +
+          it.ident ? vb * ((size_t)it.rt * it.rp * it.rb + (size_t)it.nb * it.rb)   // W and U^beta
+                   : vb * ((size_t)it.rt * it.rp * it.rb + (size_t)L.n_theta * it.rt + (size_t)L.n_phi * it.rp +
                            (size_t)it.nb * it.rb);
     }
   }
@@ -269,6 +313,64 @@ void pack_tensor(const Layout& L, const TensorFactors& tf, const TuckItem& it, S
     for (int c = 0; c < it.rp; ++c) put<S>(upt + 2 * ((size_t)c * np + j), tf.up[(size_t)j * it.rp + c]);
 }
 
+// bf16 of a float, rounded to nearest even (finite values), as a bit pattern.
+uint32_t bf16_rne(float v) {
+  uint32_t u;
+  std::memcpy(&u, &v, 4);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+float bf16_value(uint32_t h) {
+  const uint32_t u = h << 16;
+  float v;
+  std::memcpy(&v, &u, 4);
+  return v;
+}
+// The np bf16 pieces of the float nearest to v: piece j rounds what the earlier pieces
+// leave of it (the kernels' on-chip split, on the same float, gives the same pieces).
+void split_value(double v, int np, uint32_t* pc) {
+  float r = (float)v;
+  for (int j = 0; j < np; ++j) {
+    pc[j] = bf16_rne(r);
+    r -= bf16_value(pc[j]);
+  }
+}
+// Writes element (row, col) of a split block: np words (real piece | imaginary piece << 16).
+void put_split(uint32_t* fac, const SplitBlock& b, int np, int row, int col, const cd& v) {
+  uint32_t re[3], im[3];
+  split_value(v.real(), np, re);
+  split_value(v.imag(), np, im);
+  uint32_t* w = fac + b.off + (int64_t)row * b.ld + col;
+  for (int j = 0; j < np; ++j) w[j * b.plane] = re[j] | (im[j] << 16);
+}
+
+void pack_split(const Layout& L, const TensorFactors& tf, const TuckItem& it, const SplitItem& sp, int np,
+                uint32_t* fac) {
+  const int nt = L.n_theta, npf = L.n_phi, Q = it.rt * it.rp;
+  for (int n = 0; n < it.nb; ++n)
+    for (int b = 0; b < it.rb; ++b) {
+      const cd v = tf.ub[(size_t)n * it.rb + b];
+      put_split(fac, sp.ubt, np, b, n, v);
+      put_split(fac, sp.ub, np, n, b, v);
+    }
+  for (int q = 0; q < Q; ++q)
+    for (int b = 0; b < it.rb; ++b) {
+      const cd v = tf.core[(size_t)q * it.rb + b];  // paper shape [rt][rp][rb], q = a rp + c
+      put_split(fac, sp.core, np, b, q, v);
+      put_split(fac, sp.coret, np, q, b, v);
+    }
+  if (it.ident) return;
+  for (int i = 0; i < nt; ++i)
+    for (int a = 0; a < it.rt; ++a) {
+      put_split(fac, sp.ut, np, i, a, tf.ut[(size_t)i * it.rt + a]);
+      put_split(fac, sp.utt, np, a, i, tf.ut[(size_t)i * it.rt + a]);
+    }
+  for (int j = 0; j < npf; ++j)
+    for (int c = 0; c < it.rp; ++c) {
+      put_split(fac, sp.up, np, j, c, tf.up[(size_t)j * it.rp + c]);
+      put_split(fac, sp.upt, np, c, j, tf.up[(size_t)j * it.rp + c]);
+    }
+}
+
 fmm_status check_vec(const void* p, size_t align, const char* name) {
   if (!p) return fail(FMM_ERR_ARG, "%s is NULL", name);
   if (!aligned(p, align)) return fail(FMM_ERR_ARG, "%s must be %zu-byte aligned", name, align);
@@ -303,7 +405,7 @@ fmm_status lds_check(size_t bytes) {
 struct Route {
   bool mfma = false;  // matrix-core products (else the streaming kernels)
   int variant = 0;    // grouped GEMM arithmetic: 0 FP32, 1 BF16x2, 2 BF16x3, 3 FP64
-  int tile_steps = 0, rhs_chunk = 0;
+  int tile_steps = 0, rhs_chunk = 0, order = 0;
   int threads = 512;  // streaming kernels' workgroup size
 };
 
@@ -332,6 +434,7 @@ fmm_status route_of(const PrecSlot& s, fmm_prec prec, int nrhs, Route* r) {
       r->mfma = t.path == 1;
       r->tile_steps = t.tile_steps;
       r->rhs_chunk = t.rhs_chunk;
+      r->order = t.order;
     }
   // FP64 items too large for the streaming kernels' LDS (an item's x_g or core-stage
   // vector plus its r_beta or angular intermediate, in complex128) run on the matrix
@@ -378,11 +481,11 @@ fmm_status run_stage(fmm_tucker_t h, PrecSlot& s, fmm_prec prec, int nrhs, int s
     TFMM_HIP(launch_zero_rows(elem_bytes(prec), F, s.plan.zero_rows, s.plan.n_zero_rows,
                               (int64_t)L.ndir() * nrhs, hs));
   if (r.mfma) {
-    // the vectors' base addresses keep every complex value naturally aligned
-    for (const void* p : {x, (const void*)F, G, (const void*)V})
-      if (p && !aligned(p, 16)) return fail(FMM_ERR_ARG, "the matrix-core path needs 16-byte aligned vectors");
+    // vector values are loaded and stored one complex value at a time (the paired
+    // 16-byte loads read factor rows only): natural alignment, checked by the callers,
+    // is all the matrix-core path needs
     MrhsPlan* mp = nullptr;
-    if ((st = mrhs_get(s, elem_bytes(prec), L, nrhs, r.tile_steps, r.rhs_chunk, &mp)) != FMM_OK) return st;
+    if ((st = mrhs_get(s, elem_bytes(prec), L, nrhs, r.tile_steps, r.rhs_chunk, r.order, &mp)) != FMM_OK) return st;
     return mrhs_run(*mp, s, r.variant, elem_bytes(prec), stage, x, F, G, V, hs);
   }
   if ((st = ensure_part(h, s, prec, nrhs)) != FMM_OK) return st;
@@ -413,7 +516,7 @@ void drop_graph(fmm_tucker_t h) {
 
 extern "C" const char* fmm_last_error(void) { return tuckfmm::last_error_cstr(); }
 
-extern "C" const char* fmm_version(void) { return "tuckfmm 0.1 gfx950"; }
+extern "C" const char* fmm_version(void) { return "tuckfmm 0.2 gfx950 src " TUCKFMM_SOURCE_SHA; }
 
 extern "C" int32_t fmm_device_count(void) {
   int n = 0;
@@ -556,13 +659,23 @@ extern "C" fmm_status fmm_tucker_export(fmm_tucker_t h, int32_t group, int32_t a
   if (!prec_valid(as_stored)) return fail(FMM_ERR_ARG, "bad precision %d", (int)as_stored);
   const TensorFactors& tf = h->t[2 * (size_t)group + alpha];
   if (!tf.set()) return fail(FMM_ERR_STATE, "factors of group %d polarisation %d are not set", group, alpha);
-  // the complex64 arenas hold each part rounded to the nearest float (pack_tensor)
-  const bool narrow = as_stored != FMM_C128;
-  auto give = [narrow](const std::vector<cd>& v, double* p) {
+  // the complex64 arena holds each part rounded to the nearest float (pack_tensor); the
+  // split arenas hold the bf16 pieces of that float (pack_split): three pieces
+  // reproduce it exactly, two keep its leading 16 bits
+  auto stored = [as_stored](double v) -> double {
+    if (as_stored == FMM_C128) return v;
+    if (as_stored == FMM_BF16X2) {
+      uint32_t pc[2];
+      split_value(v, 2, pc);
+      return (double)bf16_value(pc[0]) + (double)bf16_value(pc[1]);
+    }
+    return (double)(float)v;
+  };
+  auto give = [&stored](const std::vector<cd>& v, double* p) {
     if (!p) return;
     for (size_t i = 0; i < v.size(); ++i) {
-      p[2 * i] = narrow ? (double)(float)v[i].real() : v[i].real();
-      p[2 * i + 1] = narrow ? (double)(float)v[i].imag() : v[i].imag();
+      p[2 * i] = stored(v[i].real());
+      p[2 * i + 1] = stored(v[i].imag());
     }
   };
   give(tf.core, core);
@@ -625,7 +738,9 @@ extern "C" fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* are
   for (unsigned w = 0; w < nthreads; ++w)
     pool.emplace_back([&, w]() {
       for (size_t i = w; i < n_t; i += nthreads) {
-        if (prec == FMM_C128)
+        if (P.np)
+          pack_split(h->layout, h->t[i], P.items[i], P.split[i], P.np, reinterpret_cast<uint32_t*>(fac));
+        else if (prec == FMM_C128)
           pack_tensor<double>(h->layout, h->t[i], P.items[i], reinterpret_cast<double*>(fac));
         else
           pack_tensor<float>(h->layout, h->t[i], P.items[i], reinterpret_cast<float*>(fac));
@@ -644,6 +759,8 @@ extern "C" fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* are
   mrhs_release(sl);
   sl.tuned.clear();
   sl.items = P.items;
+  sl.np = P.np;
+  sl.split = P.split;
   {
     // workgroup size of the streaming kernels from the mean streamed elements per item:
     // small items leave most of a large workgroup idle
@@ -775,7 +892,8 @@ extern "C" fmm_status fmm_graph_capture(fmm_tucker_t h, fmm_prec prec, int32_t n
   if ((st = route_of(*s, prec, nrhs, &r)) != FMM_OK) return st;
   if (r.mfma) {
     MrhsPlan* mp = nullptr;
-    if ((st = mrhs_get(*s, elem_bytes(prec), h->layout, nrhs, r.tile_steps, r.rhs_chunk, &mp)) != FMM_OK) return st;
+    if ((st = mrhs_get(*s, elem_bytes(prec), h->layout, nrhs, r.tile_steps, r.rhs_chunk, r.order, &mp)) != FMM_OK)
+      return st;
   } else if ((st = ensure_part(h, *s, prec, nrhs)) != FMM_OK) {
     return st;
   }
@@ -793,6 +911,123 @@ extern "C" fmm_status fmm_graph_capture(fmm_tucker_t h, fmm_prec prec, int32_t n
   return FMM_OK;
 }
 
+namespace {
+
+// Key of a tuning result: the layout's shapes (groups, ranks, identity flags, box
+// grid) hashed with FNV-1a, the precision, nrhs and the hash of the kernel sources
+// this library was built from.  Factor values do not change the timings.
+uint64_t layout_hash(const fmm_tucker_s* h) {
+  uint64_t v = 1469598103934665603ull;
+  auto mix = [&v](int64_t x) {
+    for (int b = 0; b < 8; ++b) {
+      v ^= (uint64_t)((x >> (8 * b)) & 0xff);
+      v *= 1099511628211ull;
+    }
+  };
+  mix(h->layout.n_theta);
+  mix(h->layout.n_phi);
+  mix(h->layout.n_groups);
+  for (int64_t o : h->layout.offsets) mix(o);
+  for (const TensorFactors& t : h->t) {
+    mix(t.rt);
+    mix(t.rp);
+    mix(t.rb);
+    mix(t.ident ? 1 : 0);
+  }
+  mix(h->n_boxes);
+  for (int64_t b : h->box) mix(b);
+  return v;
+}
+
+// Checks a configuration for (prec, nrhs) on this slot.
+fmm_status check_choice(const PrecSlot& s, fmm_prec prec, int nrhs, const TuneChoice& c) {
+  if (c.path == 0) {
+    if (prec_is_split(prec)) return fail(FMM_ERR_UNSUPPORTED, "the bf16 split precisions have no streaming kernels");
+    if (prec == FMM_C128 && !s.streams)
+      return fail(FMM_ERR_UNSUPPORTED, "this layout's FP64 items do not fit the streaming kernels' LDS");
+    if (c.threads != 64 && c.threads != 128 && c.threads != 256 && c.threads != 512)
+      return fail(FMM_ERR_ARG, "threads must be 64, 128, 256 or 512");
+  } else if (c.path == 1) {
+    if (!mfma_allows(prec, nrhs)) return fail(FMM_ERR_UNSUPPORTED, "the bf16 split precisions need an even nrhs");
+    if (c.tile_steps < 1 || c.tile_steps > 4096) return fail(FMM_ERR_ARG, "tile_steps must be in [1, 4096]");
+    if (c.rhs_chunk < 1) return fail(FMM_ERR_ARG, "rhs_chunk must be >= 1");
+    if (prec_is_split(prec) && c.rhs_chunk % 2 && c.rhs_chunk < nrhs)
+      return fail(FMM_ERR_ARG, "the bf16 split precisions need an even rhs_chunk");
+    if (c.order < 0 || c.order > 2) return fail(FMM_ERR_ARG, "order must be 0, 1 or 2");
+  } else {
+    return fail(FMM_ERR_ARG, "path must be 0 or 1");
+  }
+  return FMM_OK;
+}
+
+void put_choice(PrecSlot& s, const TuneChoice& c) {
+  s.tuned.erase(std::remove_if(s.tuned.begin(), s.tuned.end(), [&](const TuneChoice& t) { return t.nrhs == c.nrhs; }),
+                s.tuned.end());
+  s.tuned.push_back(c);
+}
+
+void fill_result(const TuneChoice& c, int nrhs, float ms, int from_cache, fmm_tune_result* out) {
+  if (!out) return;
+  out->path = c.path;
+  out->tile_steps = c.path == 1 ? c.tile_steps : 0;
+  out->rhs_chunk = c.path == 1 ? std::min(c.rhs_chunk, nrhs) : 0;
+  out->threads = c.path == 0 ? c.threads : 0;
+  out->ms = ms;
+  out->order = c.path == 1 ? c.order : 0;
+  out->from_cache = from_cache;
+}
+
+// Tuning cache (file named by TUCKFMM_TUNE_CACHE): one line per result,
+//   tuckfmm-tune <layout hash> <source hash> <prec> <nrhs> <path> <tile_steps> <rhs_chunk> <threads> <order> <ms>
+bool cache_lookup(const char* path, uint64_t key, fmm_prec prec, int nrhs, TuneChoice* c, float* ms) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    char tag[32], src[64];
+    unsigned long long k = 0;
+    int p = 0, n = 0, pa = 0, ts = 0, rc = 0, th = 0, od = 0;
+    float t = 0.f;
+    if (std::sscanf(line, "%31s %llx %63s %d %d %d %d %d %d %d %f", tag, &k, src, &p, &n, &pa, &ts, &rc, &th, &od,
+                    &t) != 11)
+      continue;
+    if (std::strcmp(tag, "tuckfmm-tune") || k != key || std::strcmp(src, TUCKFMM_SOURCE_SHA) || p != (int)prec ||
+        n != nrhs)
+      continue;
+    *c = TuneChoice{nrhs, pa, ts, rc, th, od};
+    *ms = t;
+    found = true;  // the last matching line wins
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_append(const char* path, uint64_t key, fmm_prec prec, int nrhs, const TuneChoice& c, float ms) {
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;  // the cache is an optimisation: an unwritable file is ignored
+  std::fprintf(f, "tuckfmm-tune %016llx %s %d %d %d %d %d %d %d %.6g\n", (unsigned long long)key, TUCKFMM_SOURCE_SHA,
+               (int)prec, nrhs, c.path, c.tile_steps, c.rhs_chunk, c.threads, c.order, ms);
+  std::fclose(f);
+}
+
+}  // namespace
+
+extern "C" fmm_status fmm_tucker_set_tuned(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const fmm_tune_result* choice) {
+  clear_error();
+  if (!h || !choice) return fail(FMM_ERR_ARG, "handle and choice must be non-NULL");
+  if (!prec_valid(prec)) return fail(FMM_ERR_ARG, "bad precision %d", (int)prec);
+  if (nrhs < 1 || nrhs > 65535) return fail(FMM_ERR_ARG, "nrhs must be in [1, 65535]");
+  PrecSlot& s = h->slot[prec];
+  if (!s.ready) return fail(FMM_ERR_STATE, "precision %d has not been uploaded", (int)prec);
+  const TuneChoice c{nrhs, choice->path, choice->tile_steps, choice->rhs_chunk, choice->threads, choice->order};
+  fmm_status st = check_choice(s, prec, nrhs, c);
+  if (st != FMM_OK) return st;
+  drop_graph(h);
+  put_choice(s, c);
+  return FMM_OK;
+}
+
 extern "C" fmm_status fmm_tucker_tune(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F,
                                       const void* G, void* V, void* stream, fmm_tune_result* out) {
   clear_error();
@@ -803,23 +1038,58 @@ extern "C" fmm_status fmm_tucker_tune(fmm_tucker_t h, fmm_prec prec, int32_t nrh
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   TFMM_HIP(hipStreamIsCapturing(hs, &cs));
   if (cs != hipStreamCaptureStatusNone) return fail(FMM_ERR_STATE, "cannot tune inside a stream capture");
+  const char* cache = std::getenv("TUCKFMM_TUNE_CACHE");
+  if (cache && !*cache) cache = nullptr;
+  const uint64_t key = layout_hash(h);
+  if (cache) {
+    TuneChoice c;
+    float ms = 0.f;
+    if (cache_lookup(cache, key, prec, nrhs, &c, &ms) && check_choice(*s, prec, nrhs, c) == FMM_OK) {
+      drop_graph(h);
+      put_choice(*s, c);
+      fill_result(c, nrhs, ms, 1, out);
+      return FMM_OK;
+    }
+    clear_error();
+  }
   // candidates: the streaming kernels (FP64, FP32; FP64 only where its items fit their
-  // LDS) and the matrix-core products with several tile sizes and right-hand-side
-  // chunks (any nrhs; an even one for the bf16 split precisions)
+  // LDS) and the matrix-core products with several tile sizes, right-hand-side chunks
+  // and angular contraction orders (any nrhs; an even one for the bf16 split
+  // precisions)
   std::vector<TuneChoice> cand;
   if (!prec_is_split(prec) && (prec != FMM_C128 || s->streams))
-    for (int nt : {64, 128, 256, 512}) cand.push_back(TuneChoice{nrhs, 0, 0, 0, nt});
+    for (int nt : {64, 128, 256, 512}) cand.push_back(TuneChoice{nrhs, 0, 0, 0, nt, 0});
   if (mfma_allows(prec, nrhs)) {
     std::vector<int> chunks{std::min<int>(nrhs, kMrhsDefaultChunk)};
     if (nrhs > 2 * kMrhsDefaultChunk) chunks.push_back(2 * kMrhsDefaultChunk);
     if (nrhs >= kMrhsDefaultChunk) chunks.push_back(kMrhsDefaultChunk / 2);
-    for (int ts : {8, 16, 32})
-      for (int rc : chunks) cand.push_back(TuneChoice{nrhs, 1, ts, rc, 0});
+    for (int od : {0, 1, 2})
+      for (int ts : {8, 16, 32})
+        for (int rc : chunks) cand.push_back(TuneChoice{nrhs, 1, ts, rc, 0, od});
   }
   if (cand.empty()) return fail(FMM_ERR_UNSUPPORTED, "no kernels for precision %d with nrhs %d", (int)prec, nrhs);
-  // keep only the tables that existed before and the winner's
+  // tables that existed before the call stay; a candidate's new tables are freed as soon
+  // as a faster one is found, so at most two candidates' scratch is held at a time
   std::vector<const MrhsPlan*> before;
   for (const MrhsPlan& p : s->mrhs) before.push_back(&p);
+  auto is_before = [&](const MrhsPlan* p) { return std::find(before.begin(), before.end(), p) != before.end(); };
+  auto plan_of = [&](const TuneChoice& c) -> MrhsPlan* {
+    if (c.path != 1) return nullptr;
+    for (MrhsPlan& p : s->mrhs)
+      if (p.nrhs == nrhs && p.tile_steps == c.tile_steps && p.rhs_chunk == std::min(c.rhs_chunk, nrhs) &&
+          p.order == c.order)
+        return &p;
+    return nullptr;
+  };
+  auto release = [&](MrhsPlan* p) {
+    if (!p || is_before(p)) return;
+    for (auto it = s->mrhs.begin(); it != s->mrhs.end(); ++it)
+      if (&*it == p) {
+        mrhs_free(*it);
+        s->mrhs.erase(it);
+        return;
+      }
+  };
   const std::vector<TuneChoice> saved = s->tuned;
   drop_graph(h);
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -850,8 +1120,11 @@ extern "C" fmm_status fmm_tucker_tune(fmm_tucker_t h, fmm_prec prec, int32_t nrh
     if (st != FMM_OK || he != hipSuccess) break;
     ms /= reps;
     if (best < 0.f || ms < best) {
+      if (best >= 0.f) release(plan_of(win));
       best = ms;
       win = c;
+    } else {
+      release(plan_of(c));
     }
   }
   (void)hipEventDestroy(e0);
@@ -860,29 +1133,20 @@ extern "C" fmm_status fmm_tucker_tune(fmm_tucker_t h, fmm_prec prec, int32_t nrh
   if (st == FMM_OK && he != hipSuccess) st = fail(FMM_ERR_DEVICE, "tuning timer: %s", hipGetErrorString(he));
   if (st == FMM_OK && best < 0.f)
     st = fail(FMM_ERR_UNSUPPORTED, "no kernel runs precision %d with nrhs %d on this layout", (int)prec, nrhs);
-  // free the tables of the losing candidates
-  for (auto it = s->mrhs.begin(); it != s->mrhs.end();) {
-    const bool old = std::find(before.begin(), before.end(), &*it) != before.end();
-    const bool keep = old || (st == FMM_OK && win.path == 1 && it->nrhs == nrhs && it->tile_steps == win.tile_steps &&
-                              it->rhs_chunk == std::min(win.rhs_chunk, nrhs));
-    if (keep) {
-      ++it;
-    } else {
-      mrhs_free(*it);
-      it = s->mrhs.erase(it);
+  if (st != FMM_OK) {  // keep only the tables that existed before
+    for (auto it = s->mrhs.begin(); it != s->mrhs.end();) {
+      if (is_before(&*it)) {
+        ++it;
+      } else {
+        mrhs_free(*it);
+        it = s->mrhs.erase(it);
+      }
     }
+    return st;
   }
-  if (st != FMM_OK) return st;
-  s->tuned.erase(std::remove_if(s->tuned.begin(), s->tuned.end(), [&](const TuneChoice& t) { return t.nrhs == nrhs; }),
-                 s->tuned.end());
-  s->tuned.push_back(win);
-  if (out) {
-    out->path = win.path;
-    out->tile_steps = win.tile_steps;
-    out->rhs_chunk = win.path == 1 ? std::min(win.rhs_chunk, nrhs) : 0;
-    out->threads = win.path == 0 ? win.threads : 0;
-    out->ms = best;
-  }
+  put_choice(*s, win);
+  if (cache) cache_append(cache, key, prec, nrhs, win, best);
+  fill_result(win, nrhs, best, 0, out);
   return FMM_OK;
 }
 

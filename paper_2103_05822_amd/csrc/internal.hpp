@@ -66,6 +66,7 @@ struct MrhsPlan {
   int nrhs = 0;
   int rhs_chunk = 0;   // columns per chunk
   int tile_steps = 0;  // K steps a workgroup aims to run (column blocks per tile)
+  int order = 0;       // angular contraction order: 0 each item's cheaper, 1 theta first, 2 phi first
   char* dev = nullptr;  // one allocation: problem tables, tile lists, scratch
   size_t dev_bytes = 0;
   char* scratch = nullptr;
@@ -73,10 +74,34 @@ struct MrhsPlan {
   std::vector<MrhsChunk> chunks;
 };
 
+// Arena of a bf16 split precision: every factor block in the orientation in which its
+// product reads it K-contiguously (both orientations of U^beta, the core, U^theta and
+// U^phi), as NP planes of 32-bit words (bf16 pieces of the real and imaginary parts,
+// formed on the host with round-to-nearest-even exactly as the kernels split values
+// on chip).  off and plane (the plane stride) count words from the factor base; rows
+// are ld words, a multiple of 4, zero padded.
+struct SplitBlock {
+  int64_t off = 0, plane = 0;
+  int32_t ld = 0, pad = 0;
+};
+struct SplitItem {
+  SplitBlock ubt;    // [r_beta][.]  (b, n) = U^beta[n][b]
+  SplitBlock ub;     // [n_beta][.]  (n, b)
+  SplitBlock core;   // [r_beta][.]  (b, q), q = theta' r_phi + phi'
+  SplitBlock coret;  // [Q][.]       (q, b)
+  SplitBlock ut;     // [n_theta][.] (i, a) = U^theta[i][a]
+  SplitBlock utt;    // [r_theta][.] (a, i)
+  SplitBlock up;     // [n_phi][.]   (j, c) = U^phi[j][c]
+  SplitBlock upt;    // [r_phi][.]   (c, j)
+};
+// bf16 pieces per value of a precision (0: not a split precision).
+inline int split_pieces(fmm_prec p) { return p == FMM_BF16X2 ? 2 : (p == FMM_BF16X3 ? 3 : 0); }
+
 // Tuned choice for one nrhs: path 0 = streaming kernels (workgroup size `threads`),
-// 1 = matrix-core products.
+// 1 = matrix-core products (K steps per tile, right-hand sides per chunk, angular
+// contraction order).
 struct TuneChoice {
-  int nrhs = 0, path = 0, tile_steps = 0, rhs_chunk = 0, threads = 0;
+  int nrhs = 0, path = 0, tile_steps = 0, rhs_chunk = 0, threads = 0, order = 0;
 };
 
 struct PrecSlot {
@@ -92,6 +117,8 @@ struct PrecSlot {
   std::vector<TuneChoice> tuned;
   void* part = nullptr;             // library-owned partial sums of split items (device)
   size_t part_bytes = 0;
+  int np = 0;                       // bf16 pieces of a split precision's arena (0: complex)
+  std::vector<SplitItem> split;     // its block offsets, per item
 };
 
 // Multi-RHS path (mrhs_plan.cpp).
@@ -108,12 +135,12 @@ struct MrhsHost {
   int64_t scratch_elems = 0;
   std::vector<MrhsHostChunk> chunks;
 };
-void mrhs_build_host(const std::vector<TuckItem>& items, const Layout& L, int nrhs, int tile_steps, int rhs_chunk,
-                     MrhsHost* out);
+void mrhs_build_host(const std::vector<TuckItem>& items, const std::vector<SplitItem>& split, int np,
+                     const Layout& L, int nrhs, int tile_steps, int rhs_chunk, int order, MrhsHost* out);
 // Plan for (slot, nrhs) with the given knobs (0 = defaults), built on first use.
 // elem_bytes: 8 (complex64 slot) or 16 (complex128 slot), the size of a scratch value.
 fmm_status mrhs_get(PrecSlot& s, size_t elem_bytes, const Layout& L, int nrhs, int tile_steps, int rhs_chunk,
-                    MrhsPlan** out);
+                    int order, MrhsPlan** out);
 // stage: 0 aggregation, 1 disaggregation, 2 both (merged launches).
 fmm_status mrhs_run(const MrhsPlan& p, const PrecSlot& s, int variant, size_t elem_bytes, int stage, const void* x,
                     void* F, const void* G, void* V, hipStream_t st);

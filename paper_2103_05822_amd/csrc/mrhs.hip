@@ -37,6 +37,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "cplx.hpp"
 #include "kernels.hpp"
@@ -330,52 +331,128 @@ __device__ __forceinline__ void split(float v, __bf16 (&pc)[NP]) {
 
 __device__ __forceinline__ __bf16 bneg(__bf16 x) { return -x; }
 
-template <int NP>
-__device__ __forceinline__ void store_bf16(const CGemm& p, const Stage<float2>& st, LdsBf16<NP>& L, int tid) {
-  {
-    int m, kq;
-    a_slot(p, tid, m, kq);
-    bf16x8 out[NP];
+// Pre-split operands.  A (a factor) arrives as np words per complex value, four K
+// values per piece in one 16-byte load: the words are already the bf16 pairs the A
+// layout holds.  B arrives either split (an intermediate: np words per value, written
+// by the product that computed it) or as complex64 (x or G: split here, once per
+// staged value).  The expanded B columns of complex column n are, per K value,
+//   real column 2n: (Re b, -Im b) = word ^ 0x80000000 (negates the high half),
+//   real column 2n + 1: (Im b, Re b) = the word's halves swapped;
+// split(-v) = -split(v) (rounding to nearest is symmetric), so the pieces of -Im b are
+// the negated pieces of Im b.
+__device__ __forceinline__ uint32_t bf16_bits(__bf16 h) { return (uint32_t)__builtin_bit_cast(uint16_t, h); }
+__device__ __forceinline__ uint32_t neg_im(uint32_t w) { return w ^ 0x80000000u; }
+__device__ __forceinline__ uint32_t swap_halves(uint32_t w) { return (w >> 16) | (w << 16); }
+
+template <int NP, bool PREB>
+struct StageB16 {
+  uint4 a[NP];          // A: piece u, four K values
+  uint32_t bw[NP][4];   // B split (PREB): piece u of K value e
+  float2 bf[4];         // B complex64 (!PREB)
+  int na, nb;
+};
+
+// Operand walkers of the split path: A is always K-contiguous split words; B is split
+// words (PREB) or complex64.
+template <bool PREB>
+struct WalkB16 {
+  using BT = typename std::conditional<PREB, const uint32_t, const float2>::type;
+  const uint32_t* a;  // the thread's A quad at the current K step (piece 0)
+  bool arow;
+  int aq;
+  BT* clampb;
+  BT* b;
+  int64_t bstep;
+  int bq;
+  bool bcol;
+};
+
+template <bool PREB>
+__device__ __forceinline__ void walk_init_b16(const CGemm& p, const uint32_t* A, const void* B, int m0, int tid,
+                                              WalkB16<PREB>& w) {
+  const int am = m0 + tid / 4;
+  w.aq = tid % 4;
+  w.arow = am < p.M;
+  w.a = A + p.a + (w.arow ? (int64_t)am * p.lda_m + 4 * w.aq : 0);
+  w.clampb = static_cast<typename WalkB16<PREB>::BT*>(B) + p.b;
+  w.bq = tid / 64;
+}
+
+template <bool PREB>
+__device__ __forceinline__ void walk_block_b16(const CGemm& p, const uint32_t* A, int n0, int m0, int tid,
+                                               WalkB16<PREB>& w) {
+  const int n = n0 + tid % 64;
+  w.bcol = n < p.N;
+  w.b = w.bcol ? w.clampb + col_off(n, p.b_ni, p.b_shi) + (int64_t)(4 * w.bq) * p.ldb_k : w.clampb;
+  w.bstep = w.bcol ? (int64_t)kKC * p.ldb_k : 0;
+  const int am = m0 + tid / 4;
+  w.a = A + p.a + (w.arow ? (int64_t)am * p.lda_m + 4 * w.aq : 0);
+}
+
+template <int NP, bool PREB>
+__device__ __forceinline__ void load_stage_b16(const CGemm& p, int k0, WalkB16<PREB>& w, StageB16<NP, PREB>& st) {
+  const int na = w.arow ? min(4, max(0, p.K - k0 - 4 * w.aq)) : 0;
+  const int nb = w.bcol ? min(4, max(0, p.K - k0 - 4 * w.bq)) : 0;
+  // a quad starting inside the K range lies inside its row (rows are padded to four)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const float2 v = a_val(p, st, e);
-      __bf16 re[NP], im[NP];
-      split<NP>(v.x, re);
-      split<NP>(v.y, im);
+  for (int u = 0; u < NP; ++u)
+    st.a[u] = na > 0 ? *reinterpret_cast<const uint4*>(w.a + u * p.ap) : make_uint4(0, 0, 0, 0);
+  if constexpr (PREB) {
 #pragma unroll
-      for (int u = 0; u < NP; ++u) {
-        out[u][2 * e] = re[u];
-        out[u][2 * e + 1] = im[u];
-      }
-    }
+    for (int e = 0; e < 4; ++e)
 #pragma unroll
-    for (int u = 0; u < NP; ++u) *reinterpret_cast<bf16x8*>(&L.a[u][m * kPR + 8 * kq]) = out[u];
+      for (int u = 0; u < NP; ++u) st.bw[u][e] = e < nb ? w.b[e * p.ldb_k + u * p.bp] : 0u;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) st.bf[e] = e < nb ? w.b[e * p.ldb_k] : czero<float2>();
   }
+  st.na = na;
+  st.nb = nb;
+  w.a += kKC;
+  w.b += w.bstep;
+}
+
+template <int NP, bool PREB>
+__device__ __forceinline__ void store_stage_b16(const CGemm& p, const StageB16<NP, PREB>& st, LdsBf16<NP>& L,
+                                                int tid) {
   {
-    // complex b at column n: real column 2n holds (Re b, -Im b) at real K (2k, 2k + 1),
-    // real column 2n + 1 holds (Im b, Re b).  split(-v) = -split(v) (rounding to
-    // nearest is symmetric), so the pieces are split once and negated.
-    const int nn = tid % 64, kq = tid / 64;
-    bf16x8 c0[NP], c1[NP];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const float2 v = b_val(p, st, e);
-      __bf16 re[NP], im[NP];
-      split<NP>(v.x, re);
-      split<NP>(v.y, im);
-#pragma unroll
-      for (int u = 0; u < NP; ++u) {
-        c0[u][2 * e] = re[u];
-        c0[u][2 * e + 1] = bneg(im[u]);
-        c1[u][2 * e] = im[u];
-        c1[u][2 * e + 1] = re[u];
-      }
-    }
+    const int m = tid / 4, kq = tid % 4;
 #pragma unroll
     for (int u = 0; u < NP; ++u) {
-      *reinterpret_cast<bf16x8*>(&L.b[u][(2 * nn) * kPR + 8 * kq]) = c0[u];
-      *reinterpret_cast<bf16x8*>(&L.b[u][(2 * nn + 1) * kPR + 8 * kq]) = c1[u];
+      uint4 v = st.a[u];
+      if (st.na < 4) {  // the K tail: words past K are zero
+        if (st.na < 4) v.w = 0;
+        if (st.na < 3) v.z = 0;
+        if (st.na < 2) v.y = 0;
+      }
+      *reinterpret_cast<uint4*>(&L.a[u][m * kPR + 8 * kq]) = v;
     }
+  }
+  const int nn = tid % 64, kq = tid / 64;
+  uint32_t w[NP][4];
+  if constexpr (PREB) {
+#pragma unroll
+    for (int u = 0; u < NP; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) w[u][e] = st.bw[u][e];
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      float2 v = st.bf[e];
+      if (p.flags & kConjB) v.y = -v.y;
+      __bf16 re[NP], im[NP];
+      split<NP>(v.x, re);
+      split<NP>(v.y, im);
+#pragma unroll
+      for (int u = 0; u < NP; ++u) w[u][e] = bf16_bits(re[u]) | (bf16_bits(im[u]) << 16);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NP; ++u) {
+    const uint4 c0 = make_uint4(neg_im(w[u][0]), neg_im(w[u][1]), neg_im(w[u][2]), neg_im(w[u][3]));
+    const uint4 c1 = make_uint4(swap_halves(w[u][0]), swap_halves(w[u][1]), swap_halves(w[u][2]), swap_halves(w[u][3]));
+    *reinterpret_cast<uint4*>(&L.b[u][(2 * nn) * kPR + 8 * kq]) = c0;
+    *reinterpret_cast<uint4*>(&L.b[u][(2 * nn + 1) * kPR + 8 * kq]) = c1;
   }
 }
 
@@ -424,7 +501,9 @@ __device__ __forceinline__ void mma_bf16(const LdsBf16<NP>& L, int w, int lane, 
 // Lanes ni and ni ^ 1 hold the real and imaginary parts of one complex column: after
 // one exchange the even lane owns the rows of registers 0, 1 and the odd lane those
 // of registers 2, 3 as complex values.
-template <typename C2, typename ACC, int NTE>
+// NPW > 0 (bf16 split precisions, C an intermediate another product reads): each
+// value is written as NPW words (its bf16 pieces) in planes p.cp words apart.
+template <typename C2, typename ACC, int NTE, int NPW = 0>
 __device__ __forceinline__ void epilogue(const CGemm& p, C2* Cp, int m0, int n0, int w, int lane,
                                          const ACC (&acc)[NTE]) {
   using R = decltype(C2{}.x);
@@ -455,7 +534,14 @@ __device__ __forceinline__ void epilogue(const CGemm& p, C2* Cp, int m0, int n0,
       if (m >= p.M) continue;
       C2* dst = Cp + coff + (int64_t)m * p.ldc_m;
       const C2 c = i ? c1 : c0;
-      if (atomic) {
+      if constexpr (NPW > 0) {
+        uint32_t* dw = reinterpret_cast<uint32_t*>(Cp) + coff + (int64_t)m * p.ldc_m;
+        __bf16 re[NPW], im[NPW];
+        split<NPW>((float)c.x, re);
+        split<NPW>((float)c.y, im);
+#pragma unroll
+        for (int u = 0; u < NPW; ++u) dw[u * p.cp] = bf16_bits(re[u]) | (bf16_bits(im[u]) << 16);
+      } else if (atomic) {
         atomicAdd(&dst->x, c.x);
         atomicAdd(&dst->y, c.y);
       } else {
@@ -499,12 +585,11 @@ struct VarOf<3> {
 template <int VARIANT>
 __device__ __forceinline__ void store_stage(const CGemm& p, const Stage<typename VarOf<VARIANT>::c2>& st,
                                             typename VarOf<VARIANT>::lds& L, int tid) {
+  static_assert(VARIANT == 0 || VARIANT == 3, "the bf16 variants stage pre-split operands (run_tile_b16)");
   if constexpr (VARIANT == 0)
     store_f32(p, st, L, tid);
-  else if constexpr (VARIANT == 3)
-    store_f64(p, st, L, tid);
   else
-    store_bf16<VARIANT + 1>(p, st, L, tid);
+    store_f64(p, st, L, tid);
 }
 
 template <int VARIANT, int NTE>
@@ -598,6 +683,76 @@ __device__ __forceinline__ void run_tile_of(const CGemm& p, const CTile& tl, con
     run_tile<VARIANT, AVEC, true, kNT>(p, tl, A, B, Cp, L);
 }
 
+// The bf16 variants: the pipeline of run_tile on pre-split operands.
+template <int VARIANT, bool PREB, bool ACTIVE, int NTE>
+__device__ __forceinline__ void run_tile_b16(const CGemm& p, const CTile& tl, const uint32_t* A, const void* B,
+                                             void* Cp, typename VarOf<VARIANT>::lds& L) {
+  constexpr int NP = VARIANT + 1;
+  using ACC = floatx4;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int nsteps = (p.K + kKC - 1) / kKC;
+
+  ACC acc[NTE];
+  if constexpr (ACTIVE) {
+#pragma unroll
+    for (int t = 0; t < NTE; ++t) acc[t] = ACC{0, 0, 0, 0};
+  }
+  WalkB16<PREB> wk;
+  walk_init_b16<PREB>(p, A, B, tl.m0, tid, wk);
+  walk_block_b16<PREB>(p, A, tl.n0, tl.m0, tid, wk);
+  StageB16<NP, PREB> st;
+  load_stage_b16<NP, PREB>(p, 0, wk, st);
+  store_stage_b16<NP, PREB>(p, st, L, tid);
+  __syncthreads();
+  for (int n0 = tl.n0;;) {
+    for (int s = 0; s < nsteps; ++s) {
+      int nn0 = n0, ns = s + 1;
+      if (ns == nsteps) {
+        ns = 0;
+        nn0 += kBN;
+      }
+      const bool more = nn0 < tl.n1;
+      if (more) {
+        if (ns == 0) walk_block_b16<PREB>(p, A, nn0, tl.m0, tid, wk);
+        load_stage_b16<NP, PREB>(p, ns * kKC, wk, st);
+      }
+      if constexpr (ACTIVE) mma_bf16<NP, NTE>(L, w, lane, acc);
+      if (more) {
+        __syncthreads();  // every wavefront is done reading the step
+        store_stage_b16<NP, PREB>(p, st, L, tid);
+        __syncthreads();
+      }
+    }
+    if constexpr (ACTIVE) {
+      if (p.cp)
+        epilogue<float2, ACC, NTE, NP>(p, static_cast<float2*>(Cp), tl.m0, n0, w, lane, acc);
+      else
+        epilogue<float2, ACC, NTE, 0>(p, static_cast<float2*>(Cp), tl.m0, n0, w, lane, acc);
+    }
+    n0 += kBN;
+    if (n0 >= tl.n1) break;
+    if constexpr (ACTIVE) {
+#pragma unroll
+      for (int t = 0; t < NTE; ++t) acc[t] = ACC{0, 0, 0, 0};
+    }
+  }
+}
+
+template <int VARIANT, bool PREB>
+__device__ __forceinline__ void run_tile_of_b16(const CGemm& p, const CTile& tl, const uint32_t* A, const void* B,
+                                                void* Cp, typename VarOf<VARIANT>::lds& L) {
+  if (tl.m0 + 16 * (int)(threadIdx.x >> 6) >= p.M)
+    run_tile_b16<VARIANT, PREB, false, 1>(p, tl, A, B, Cp, L);
+  else if (p.N <= 8)
+    run_tile_b16<VARIANT, PREB, true, 1>(p, tl, A, B, Cp, L);
+  else if (p.N <= 16)
+    run_tile_b16<VARIANT, PREB, true, 2>(p, tl, A, B, Cp, L);
+  else if (p.N <= 32)
+    run_tile_b16<VARIANT, PREB, true, 4>(p, tl, A, B, Cp, L);
+  else
+    run_tile_b16<VARIANT, PREB, true, kNT>(p, tl, A, B, Cp, L);
+}
+
 template <int VARIANT>
 __global__ __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(VarOf<VARIANT>::waves, 8))) void cgemm_kernel(const CGemm* __restrict__ probs, const CTile* __restrict__ tiles,
                                                     CGemmBases bases) {
@@ -611,7 +766,13 @@ __global__ __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(VarOf<VARIA
   C2* Cp = base_ptr<C2>(bases, p.cbase);
   // paired 16-byte A loads (complex64): K-contiguous A with an even offset and row
   // stride
-  if constexpr (VARIANT == 3) {
+  if constexpr (VARIANT == 1 || VARIANT == 2) {
+    const uint32_t* Aw = base_ptr<const uint32_t>(bases, p.abase);
+    if (p.bp)
+      run_tile_of_b16<VARIANT, true>(p, tl, Aw, B, Cp, L);
+    else
+      run_tile_of_b16<VARIANT, false>(p, tl, Aw, B, Cp, L);
+  } else if constexpr (VARIANT == 3) {
     run_tile_of<VARIANT, false>(p, tl, A, B, Cp, L);
   } else {
     if (p.lda_k == 1 && !((p.a | p.lda_m) & 1))

@@ -40,6 +40,9 @@ namespace {
 // Workgroup size NT (64, 128, 256 or 512 threads, NT / 64 wavefronts) is a template
 // parameter of every phase: one workgroup per item.
 constexpr int kColPacks = 2;  // column packs per thread per chunk in the axpy stages
+// K values per step of the small angular products in the 64- and 128-thread kernels
+// (small items): all of a step's operands are loaded before its multiply-adds.
+constexpr int kSmallKUnroll = 4;
 
 // U^beta^T and the core are read once per pass: non-temporal loads keep these
 // streams from displacing x, G, V and the work tables in the caches.  Measured on
@@ -86,16 +89,66 @@ struct Lds {
   __host__ __device__ size_t bytes() const { return agg_bytes() > dis_bytes() ? agg_bytes() : dis_bytes(); }
 };
 
+// Short rows (npk <= 32 packs): the wavefront splits into 64 / S segments of S lanes,
+// S the smallest power of two >= npk, and each segment takes a row, four rows per
+// segment in flight, so a wavefront works on 4 * 64 / S rows at once instead of four
+// mostly idle ones; the segment's sum is a butterfly over its S lanes.
+template <typename T, bool kNt>
+__device__ __forceinline__ void wave_rowdots_short(const typename Tr<T>::c* rows, int ld, int first, int last,
+                                                   int step, const typename Tr<T>::pack* vec, int npk,
+                                                   typename Tr<T>::c* out, int lane) {
+  using C = typename Tr<T>::c;
+  using P = typename Tr<T>::pack;
+  int S = 1;
+  while (S < npk) S <<= 1;
+  const int G = 64 / S;             // segments (rows) per wavefront
+  const int seg = lane / S, sl = lane - seg * S;
+  const bool act = sl < npk;
+  const P v = act ? vec[sl] : pzero<P>();
+  for (int j0 = 0; first + step * j0 < last; j0 += 4 * G) {
+    P u[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int b = first + step * (j0 + G * i + seg);
+      u[i] = (act && b < last) ? ldnt<kNt>(reinterpret_cast<const P*>(rows + (int64_t)b * ld) + sl) : pzero<P>();
+    }
+    C a[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a[i] = czero<C>();
+      pdot(a[i], u[i], v);
+    }
+    for (int o = S >> 1; o > 0; o >>= 1) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i].x += __shfl_xor(a[i].x, o, 64);
+        a[i].y += __shfl_xor(a[i].y, o, 64);
+      }
+    }
+    if (sl == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int b = first + step * (j0 + G * i + seg);
+        if (b < last) out[b] = a[i];
+      }
+    }
+  }
+}
+
 // out[b] = sum_k rows[b][k] * vec[k] for b = first, first + step, ... < last, one
 // wavefront per row.  Rows are 16-byte aligned with npk packs each; vec is an LDS
 // pack array.  Four rows at a time, two packs per row per iteration: eight 16-byte
-// loads in flight per lane.
+// loads in flight per lane.  Rows of at most 32 packs take the segmented form above.
 template <typename T, bool kNt>
 __device__ __forceinline__ void wave_rowdots(const typename Tr<T>::c* rows, int ld, int first, int last,
                                              int step, const typename Tr<T>::pack* vec, int npk,
                                              typename Tr<T>::c* out, int lane) {
   using C = typename Tr<T>::c;
   using P = typename Tr<T>::pack;
+  if (npk <= 32) {
+    wave_rowdots_short<T, kNt>(rows, ld, first, last, step, vec, npk, out, lane);
+    return;
+  }
   int b = first;
   for (; b + 3 * step < last; b += 4 * step) {
     const P* r[4];
@@ -151,8 +204,51 @@ __device__ __forceinline__ void wave_rowdots(const typename Tr<T>::c* rows, int 
   }
 }
 
+__device__ __forceinline__ float4 shfl_xor_pack(float4 v, int o) {
+  return make_float4(__shfl_xor(v.x, o, 64), __shfl_xor(v.y, o, 64), __shfl_xor(v.z, o, 64), __shfl_xor(v.w, o, 64));
+}
+__device__ __forceinline__ double2 shfl_xor_pack(double2 v, int o) {
+  return make_double2(__shfl_xor(v.x, o, 64), __shfl_xor(v.y, o, 64));
+}
+
+// One wavefront, at most 32 column packs: the lanes split into 64 / S groups of S
+// (S the smallest power of two >= npk); group g walks rows g, g + 64/S, ..., four in
+// flight, and the groups' partial sums meet in a butterfly.  acc[0] of lane p < npk
+// receives pack p (acc[1] is zero).
+template <typename T>
+__device__ __forceinline__ void wave_colaxpy_grouped(const typename Tr<T>::c* rows, int ld, int nrows,
+                                                     const typename Tr<T>::c* coef, int npk, int lane,
+                                                     typename Tr<T>::pack (&acc)[kColPacks]) {
+  using C = typename Tr<T>::c;
+  using P = typename Tr<T>::pack;
+  int S = 1;
+  while (S < npk) S <<= 1;
+  const int G = 64 / S;
+  const int g = lane / S, c = lane - g * S;
+  const bool in = c < npk;
+  P a = pzero<P>();
+  for (int b0 = g; b0 < nrows; b0 += 4 * G) {
+    P u[4];
+    C cf[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int b = b0 + G * i;
+      const bool ok = b < nrows;
+      u[i] = (in && ok) ? reinterpret_cast<const P*>(rows + (int64_t)b * ld)[c] : pzero<P>();
+      cf[i] = ok ? coef[b] : czero<C>();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) paxpy(a, u[i], cf[i]);
+  }
+  for (int o = S; o < 64; o <<= 1) a = padd(a, shfl_xor_pack(a, o));
+  acc[0] = a;
+#pragma unroll
+  for (int j = 1; j < kColPacks; ++j) acc[j] = pzero<P>();
+}
+
 // acc[j] (column packs base + tid + NT j) += sum_b rows[b][.] * coef[b];
-// four rows per iteration.
+// four rows per iteration.  A single wavefront with at most 32 packs takes the
+// grouped form above (acc must then start at zero).
 template <typename T, int NT>
 __device__ __forceinline__ void block_colaxpy(const typename Tr<T>::c* rows, int ld, int nrows,
                                               const typename Tr<T>::c* coef, int npk, int base, int tid,
@@ -160,6 +256,12 @@ __device__ __forceinline__ void block_colaxpy(const typename Tr<T>::c* rows, int
   using C = typename Tr<T>::c;
   using P = typename Tr<T>::pack;
   constexpr bool kNt = NT >= 256;
+  if constexpr (NT == 64) {
+    if (base == 0 && npk <= 32) {
+      wave_colaxpy_grouped<T>(rows, ld, nrows, coef, npk, tid, acc);
+      return;
+    }
+  }
   const int p0 = base + tid;
   bool in[kColPacks];
 #pragma unroll
@@ -202,16 +304,24 @@ __device__ __forceinline__ void tile_product(int M, int N, int K, FA a, FB b, FO
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[u] = czero<C>();
     if (m0 + 3 < M) {
+      // KU values of K per step, all operands loaded before the multiply-adds: with
+      // operands in global memory each step costs about one memory latency
+      constexpr int KU = NT <= 128 ? kSmallKUnroll : 2;
       int k = 0;
-      for (; k + 1 < K; k += 2) {
-        const C b0 = b(k, n), b1 = b(k + 1, n);
+      for (; k + KU - 1 < K; k += KU) {
+        C bv[KU], av[4][KU];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          cfma(acc[u], a(m0 + u, k), b0);
-          cfma(acc[u], a(m0 + u, k + 1), b1);
-        }
+        for (int j = 0; j < KU; ++j) bv[j] = b(k + j, n);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int j = 0; j < KU; ++j) av[u][j] = a(m0 + u, k + j);
+#pragma unroll
+        for (int j = 0; j < KU; ++j)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) cfma(acc[u], av[u][j], bv[j]);
       }
-      if (k < K) {
+      for (; k < K; ++k) {
         const C b0 = b(k, n);
 #pragma unroll
         for (int u = 0; u < 4; ++u) cfma(acc[u], a(m0 + u, k), b0);
@@ -474,13 +584,14 @@ __global__ __launch_bounds__(NT) void tucker_agg_kernel(const typename Tr<T>::c*
                                                         const TuckUnit* __restrict__ units,
                                                         const TuckSplit* __restrict__ splits,
                                                         const int32_t* __restrict__ order, TuckMax mx, int n_theta,
-                                                        int n_phi, int nrhs, const typename Tr<T>::c* __restrict__ x,
+                                                        int n_phi, int nrhs,
+                                                        const typename Tr<T>::c* __restrict__ x,
                                                         typename Tr<T>::c* __restrict__ F, typename Tr<T>::c* part,
                                                         int64_t part_stride) {
   extern __shared__ __align__(16) unsigned char smem[];
   const TuckUnit u = units[order[blockIdx.x]];
-  agg_unit<T, NT>(fac, items, u, splits, Lds<T>(mx), smem, n_theta, n_phi, nrhs, blockIdx.y, x, F, part,
-                  part_stride);
+  agg_unit<T, NT>(fac, items, u, splits, Lds<T>(mx), smem, n_theta, n_phi, nrhs, blockIdx.y, x, F,
+                  part, part_stride);
 }
 
 template <typename T, int NT>
@@ -489,13 +600,14 @@ __global__ __launch_bounds__(NT) void tucker_dis_kernel(const typename Tr<T>::c*
                                                         const TuckUnit* __restrict__ units,
                                                         const TuckSplit* __restrict__ splits,
                                                         const int32_t* __restrict__ order, TuckMax mx, int n_theta,
-                                                        int n_phi, int nrhs, const typename Tr<T>::c* __restrict__ G,
+                                                        int n_phi, int nrhs,
+                                                        const typename Tr<T>::c* __restrict__ G,
                                                         typename Tr<T>::c* __restrict__ V, typename Tr<T>::c* part,
                                                         int64_t part_stride) {
   extern __shared__ __align__(16) unsigned char smem[];
   const TuckUnit u = units[order[blockIdx.x]];
-  dis_unit<T, NT>(fac, items, u, splits, Lds<T>(mx), smem, n_theta, n_phi, nrhs, blockIdx.y, G, V, part,
-                  part_stride);
+  dis_unit<T, NT>(fac, items, u, splits, Lds<T>(mx), smem, n_theta, n_phi, nrhs, blockIdx.y, G, V,
+                  part, part_stride);
 }
 
 // One launch for a whole aggregation + disaggregation pass: work-list entry e is
@@ -508,7 +620,8 @@ __global__ __launch_bounds__(NT) void tucker_pass_kernel(const typename Tr<T>::c
                                                          const TuckUnit* __restrict__ units,
                                                          const TuckSplit* __restrict__ splits,
                                                          const int32_t* __restrict__ list, TuckMax mx, int n_theta,
-                                                         int n_phi, int nrhs, const typename Tr<T>::c* __restrict__ x,
+                                                         int n_phi, int nrhs,
+                                                         const typename Tr<T>::c* __restrict__ x,
                                                          typename Tr<T>::c* __restrict__ F,
                                                          const typename Tr<T>::c* __restrict__ G,
                                                          typename Tr<T>::c* __restrict__ V, typename Tr<T>::c* part,
@@ -706,8 +819,9 @@ hipError_t launch_tucker_pass(const TuckPlan& pl, int threads, int n_theta, int 
   if (e != hipSuccess || pl.n_units == 0) return e;
   TFMM_NT_SWITCH(threads,
                  hipLaunchKernelGGL((tucker_pass_kernel<T, NT>), dim3(2 * pl.n_units, nrhs), dim3(NT),
-                                    Lds<T>(pl.mx).bytes(), s, static_cast<const C*>(pl.factors), pl.items, pl.units,
-                                    pl.splits, pl.pass_list, pl.mx, n_theta, n_phi, nrhs, static_cast<const C*>(x),
+                                    Lds<T>(pl.mx).bytes(), s, static_cast<const C*>(pl.factors), pl.items,
+                                    pl.units, pl.splits, pl.pass_list, pl.mx, n_theta, n_phi, nrhs,
+                                    static_cast<const C*>(x),
                                     static_cast<C*>(F), static_cast<const C*>(G), static_cast<C*>(V),
                                     static_cast<C*>(pl.part), pl.part_stride))
   e = hipGetLastError();

@@ -399,27 +399,92 @@ def test_fp64_items_beyond_streaming_lds():
 
 
 @pytest.mark.parametrize("prec", [T.FMM_C128, T.FMM_C64], ids=["c128", "c64"])
-def test_mrhs_tuned_odd_nrhs(prec):
-    """15 right-hand sides on the 38 x 75 grid: the autotuner picks the matrix cores over
-    fifteen streaming passes, and the tuned pass at that odd nrhs matches the oracle."""
+def test_mrhs_forced_matrix_cores_odd_nrhs(prec):
+    """15 right-hand sides on the 38 x 75 grid, the matrix-core route forced through
+    fmm_tucker_set_tuned (one chunk of 15, each angular order): parity with the oracle
+    at that odd nrhs, on 8-byte-aligned complex64 views (natural alignment only)."""
+    import torch
     lay, tuck = paper_grid_tucker(seed=35)
     nrhs = 15
     x, gin = inputs(lay, nrhs, 14)
     f_ref = pr.aggregate_all("tucker", tuck, lay.offsets, x)
     v_ref = pr.disaggregate_all("tucker", tuck, lay.offsets, gin)
-    banner("mrhs tuned odd nrhs prec=%d" % prec)
     cd = CDT[prec]
     H = Handle(lay, tuck, prec)
     try:
-        xd, gd = dev(x, cd), dev(gin, cd)
-        F = dev(np.zeros(f_ref.shape, cd))
-        V = dev(np.zeros(v_ref.shape, cd))
-        r = T.fmm_tucker_tune(H.h, prec, nrhs, xd, F, gd, V)
-        print("  tuned:", r, flush=True)
-        assert r["path"] == 1 and r["rhs_chunk"] == nrhs
-        F.zero_()
-        V.zero_()
-        T.fmm_tucker_pass(H.h, prec, nrhs, xd, F, gd, V)
-        check(prec, host(F), host(V), f_ref, v_ref)
+        # views one complex value into larger buffers: 8-byte aligned for complex64
+        xb = dev(np.concatenate([np.zeros(1), x.ravel()]).astype(cd))
+        gb = dev(np.concatenate([np.zeros(1), gin.ravel()]).astype(cd))
+        Fb = torch.zeros(1 + f_ref.size, dtype=xb.dtype, device="cuda")
+        Vb = torch.zeros(1 + v_ref.size, dtype=xb.dtype, device="cuda")
+        xd, gd, F, V = xb[1:], gb[1:], Fb[1:], Vb[1:]
+        for order in (0, 1, 2):
+            banner("mrhs forced matrix cores prec=%d nrhs=%d order=%d" % (prec, nrhs, order))
+            T.fmm_tucker_set_tuned(H.h, prec, nrhs, path=1, tile_steps=16, rhs_chunk=nrhs, order=order)
+            F.zero_()
+            V.zero_()
+            T.fmm_tucker_pass(H.h, prec, nrhs, xd, F, gd, V)
+            check(prec, host(F).reshape(f_ref.shape), host(V).reshape(v_ref.shape), f_ref, v_ref)
     finally:
         H.close()
+
+
+def test_set_tuned_validation():
+    lay = ragged_layout()
+    tuck = random_tucker(lay, 5)
+    H = Handle(lay, tuck, T.FMM_BF16X3)
+    try:
+        bad = [dict(path=2), dict(path=1, tile_steps=0, rhs_chunk=4), dict(path=1, tile_steps=16, rhs_chunk=4, order=3),
+               dict(path=1, tile_steps=16, rhs_chunk=3)]   # the splits need even chunks
+        for kw in bad:
+            with pytest.raises(T.FmmError) as e:
+                T.fmm_tucker_set_tuned(H.h, T.FMM_BF16X3, 8, **kw)
+            assert e.value.status == -1, kw
+        with pytest.raises(T.FmmError) as e:   # no streaming kernels for the bf16 splits
+            T.fmm_tucker_set_tuned(H.h, T.FMM_BF16X3, 8, path=0, threads=256)
+        assert e.value.status == -6
+        with pytest.raises(T.FmmError) as e:   # precision not uploaded
+            T.fmm_tucker_set_tuned(H.h, T.FMM_C64, 8, path=0, threads=256)
+        assert e.value.status == -7
+    finally:
+        H.close()
+    H = Handle(lay, tuck, T.FMM_C64)
+    try:
+        with pytest.raises(T.FmmError) as e:   # not a streaming workgroup size
+            T.fmm_tucker_set_tuned(H.h, T.FMM_C64, 8, path=0, threads=96)
+        assert e.value.status == -1
+        T.fmm_tucker_set_tuned(H.h, T.FMM_C64, 8, path=0, threads=128)
+    finally:
+        H.close()
+
+
+def test_tune_cache_file(tmp_path, monkeypatch):
+    """With TUCKFMM_TUNE_CACHE set, a tuning result is appended to the file and a second
+    tune of the same shapes, precision and nrhs takes it from there without timing; the
+    chosen kernels stay within tolerance."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("TUCKFMM_TUNE_CACHE", str(cache))
+    lay = ragged_layout()
+    tuck = random_tucker(lay, 93)
+    nrhs = 6
+    x, gin = inputs(lay, nrhs, 15)
+    f_ref = pr.aggregate_all("tucker", tuck, lay.offsets, x)
+    v_ref = pr.disaggregate_all("tucker", tuck, lay.offsets, gin)
+    banner("tune cache")
+    for round_ in range(2):
+        H = Handle(lay, tuck, T.FMM_C64)
+        try:
+            xd, gd = dev(x, C64), dev(gin, C64)
+            F = dev(np.zeros(f_ref.shape, C64))
+            V = dev(np.zeros(v_ref.shape, C64))
+            r = T.fmm_tucker_tune(H.h, T.FMM_C64, nrhs, xd, F, gd, V)
+            print("  tuned:", r, flush=True)
+            assert r["from_cache"] == round_
+            lines = cache.read_text().splitlines()
+            assert len(lines) == 1 and lines[0].startswith("tuckfmm-tune ")
+            F.zero_()
+            V.zero_()
+            T.fmm_tucker_pass(H.h, T.FMM_C64, nrhs, xd, F, gd, V)
+            check(T.FMM_C64, host(F), host(V), f_ref, v_ref)
+        finally:
+            H.close()
