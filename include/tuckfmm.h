@@ -55,16 +55,12 @@ typedef enum {
 /* Storage / arithmetic precision of a compute path.
  *   FMM_C128   complex128 factors, FP64 arithmetic; x, F, G, V are complex128.
  *   FMM_C64    complex64 factors, FP32 arithmetic; x, F, G, V are complex64.
- *   FMM_BF16X2 complex64 vectors; the products run on the bf16 matrix cores: every
- *              operand is split into two bf16 pieces (hi + lo of its float value) and
- *              each product accumulates hi*hi + hi*lo + lo*hi in FP32 (relative
- *              error of a product about 2^-16).  The arena stores the factors already
- *              split (4-byte pieces, both orientations of each factor: about twice
- *              the complex64 arena); intermediates are split by the product that
- *              writes them.  Needs an even nrhs.
+ *   FMM_BF16X2 complex64 factors and vectors; the products run on the bf16 matrix
+ *              cores: every FP32 operand is split on chip into two bf16 pieces
+ *              (hi + lo) and each product accumulates hi*hi + hi*lo + lo*hi in FP32
+ *              (relative error of a product about 2^-16).  Needs an even nrhs.
  *   FMM_BF16X3 as FMM_BF16X2 with three pieces (hi + mid + lo) and the six products
- *              down to order 2^-16 (FP32-level error; an arena about three times the
- *              complex64 one).  Needs an even nrhs.
+ *              down to order 2^-16 (FP32-level error).  Needs an even nrhs.
  *
  * Kernels.  The streaming kernels run one workgroup per (group, polarisation,
  * right-hand side) and stream the factors from HBM once per right-hand side; they take
@@ -276,11 +272,10 @@ fmm_status fmm_tucker_ranks(fmm_tucker_t h, int32_t* ranks);
 /* Copy the factors of one (group, polarisation) of eq. (6) into host complex128
  * buffers in the paper's shapes (sizes from fmm_tucker_ranks; any pointer may be NULL).
  *   as_stored  FMM_C128: the handle's FP64 factors as they are.
- *              FMM_C64, FMM_BF16X3: every real and imaginary part rounded to the
- *              nearest float and widened back, the value an upload of FMM_C64 stores
- *              and the sum of the three bf16 pieces an FMM_BF16X3 upload stores.
- *              FMM_BF16X2: the sum of the two bf16 pieces of that float (hi = its
- *              bf16 rounding, lo = the rounding of the rest) an upload stores.
+ *              FMM_C64, FMM_BF16X2, FMM_BF16X3: every real and imaginary part rounded
+ *              to the nearest float and widened back, i.e. exactly the complex64
+ *              values an upload of that precision stores (the bf16 pieces of the split
+ *              precisions are formed from these on chip).
  * With as_stored = the upload's precision, a plain FP64 contraction of the exported
  * factors (Fig. 2(b), Fig. 3(b)) is the exact result the compute calls approximate:
  * their difference is the arithmetic error alone, free of the compression error.

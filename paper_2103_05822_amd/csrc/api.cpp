@@ -97,8 +97,6 @@ struct ArenaPlan {
   int64_t part_stride = 0;
   std::vector<int32_t> order, pass, zero_rows;
   TuckMax mx{};
-  int np = 0;                    // split precisions: bf16 pieces per value
-  std::vector<SplitItem> split;  // and their block offsets
 };
 
 // Bytes streamed by one item (U^beta and the core), the key of the work lists.
@@ -132,25 +130,12 @@ fmm_status plan_arena(const fmm_tucker_s* h, fmm_prec prec, ArenaPlan* P) {
   const size_t es = elem_bytes(prec);
   const int E = pack_elems(prec);
   const size_t blk_align = 256;
-  const int np = split_pieces(prec);
-  P->np = np;
   P->items.resize((size_t)2 * G);
-  if (np) P->split.assign((size_t)2 * G, SplitItem{});
   size_t off = 0;  // bytes inside the factor area
   auto block = [&](size_t n_el) {
     const size_t start = off;
     off = align_up(off + n_el * es, blk_align);
     return start;
-  };
-  // split precisions: rows x cols words per plane, rows of a multiple of 4 words
-  // (16-byte loads of four K values), planes and blocks on 256-byte boundaries
-  auto wblock = [&](int rows, int cols) {
-    SplitBlock b;
-    b.ld = (cols + 3) / 4 * 4;
-    b.plane = (int64_t)align_up((size_t)rows * b.ld, 64);
-    b.off = (int64_t)(off / 4);
-    off += (size_t)np * b.plane * 4;
-    return b;
   };
   TuckMax mx{};
   for (int g = 0; g < G; ++g) {
@@ -173,33 +158,12 @@ fmm_status plan_arena(const fmm_tucker_s* h, fmm_prec prec, ArenaPlan* P) {
       const double c_phi = (double)it.rt * L.n_phi * (it.rp + L.n_theta);
       it.theta_first = c_theta <= c_phi ? 1 : 0;
       it.ident = tf.ident ? 1 : 0;
-      if (np == 0) {
-        it.off_ubt = (int64_t)(block((size_t)it.rb * it.ld_ub) / es);
-        it.off_core = (int64_t)(block((size_t)it.rb * it.ld_c) / es);
-        if (!it.ident) {  // identity angular factors are not stored
-          it.off_ut = (int64_t)(block((size_t)L.n_theta * it.rt) / es);
-          it.off_up = (int64_t)(block((size_t)L.n_phi * it.rp) / es);
-          it.off_upt = (int64_t)(block((size_t)L.n_phi * it.rp) / es);
-        }
-      } else {
-        // split precision: np planes of 4-byte words per block, both orientations
-        SplitItem& sp = P->split[2 * g + a];
-        const int Q = it.rt * it.rp;
-        sp.ubt = wblock(it.rb, it.nb);
-        sp.ub = wblock(it.nb, it.rb);
-        sp.core = wblock(it.rb, Q);
-        sp.coret = wblock(Q, it.rb);
-        if (!it.ident) {
-          sp.ut = wblock(L.n_theta, it.rt);
-          sp.utt = wblock(it.rt, L.n_theta);
-          sp.up = wblock(L.n_phi, it.rp);
-          sp.upt = wblock(it.rp, L.n_phi);
-        }
-        it.off_ubt = sp.ubt.off;
-        it.off_core = sp.core.off;
-        it.off_ut = sp.ut.off;
-        it.off_up = sp.up.off;
-        it.off_upt = sp.upt.off;
+      it.off_ubt = (int64_t)(block((size_t)it.rb * it.ld_ub) / es);
+      it.off_core = (int64_t)(block((size_t)it.rb * it.ld_c) / es);
+      if (!it.ident) {  // identity angular factors are not stored
+        it.off_ut = (int64_t)(block((size_t)L.n_theta * it.rt) / es);
+        it.off_up = (int64_t)(block((size_t)L.n_phi * it.rp) / es);
+        it.off_upt = (int64_t)(block((size_t)L.n_phi * it.rp) / es);
       }
       P->items[2 * g + a] = it;
       mx.nb = std::max(mx.nb, it.nb);
@@ -208,12 +172,9 @@ fmm_status plan_arena(const fmm_tucker_s* h, fmm_prec prec, ArenaPlan* P) {
       mx.rb = std::max(mx.rb, it.rb);
       mx.q = std::max(mx.q, it.rt * it.rp);
       if (!it.ident) mx.t3 = std::max(mx.t3, it.theta_first ? L.n_theta * it.rp : it.rt * L.n_phi);
-      // the paper's measure: core + factors once, at the stored bytes per value
-      // (np bf16 pairs of 4 bytes for the split precisions)
-      const size_t vb = np ? (size_t)4 * np : es;
       P->factor_bytes_paper +=
-          it.ident ? vb * ((size_t)it.rt * it.rp * it.rb + (size_t)it.nb * it.rb)   // W and U^beta
-                   : vb * ((size_t)it.rt * it.rp * it.rb + (size_t)L.n_theta * it.rt + (size_t)L.n_phi * it.rp +
+          it.ident ? es * ((size_t)it.rt * it.rp * it.rb + (size_t)it.nb * it.rb)   // W and U^beta
+                   : es * ((size_t)it.rt * it.rp * it.rb + (size_t)L.n_theta * it.rt + (size_t)L.n_phi * it.rp +
                            (size_t)it.nb * it.rb);
     }
   }
@@ -311,64 +272,6 @@ void pack_tensor(const Layout& L, const TensorFactors& tf, const TuckItem& it, S
   S* upt = fac + 2 * it.off_upt;
   for (int j = 0; j < np; ++j)
     for (int c = 0; c < it.rp; ++c) put<S>(upt + 2 * ((size_t)c * np + j), tf.up[(size_t)j * it.rp + c]);
-}
-
-// bf16 of a float, rounded to nearest even (finite values), as a bit pattern.
-uint32_t bf16_rne(float v) {
-  uint32_t u;
-  std::memcpy(&u, &v, 4);
-  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-}
-float bf16_value(uint32_t h) {
-  const uint32_t u = h << 16;
-  float v;
-  std::memcpy(&v, &u, 4);
-  return v;
-}
-// The np bf16 pieces of the float nearest to v: piece j rounds what the earlier pieces
-// leave of it (the kernels' on-chip split, on the same float, gives the same pieces).
-void split_value(double v, int np, uint32_t* pc) {
-  float r = (float)v;
-  for (int j = 0; j < np; ++j) {
-    pc[j] = bf16_rne(r);
-    r -= bf16_value(pc[j]);
-  }
-}
-// Writes element (row, col) of a split block: np words (real piece | imaginary piece << 16).
-void put_split(uint32_t* fac, const SplitBlock& b, int np, int row, int col, const cd& v) {
-  uint32_t re[3], im[3];
-  split_value(v.real(), np, re);
-  split_value(v.imag(), np, im);
-  uint32_t* w = fac + b.off + (int64_t)row * b.ld + col;
-  for (int j = 0; j < np; ++j) w[j * b.plane] = re[j] | (im[j] << 16);
-}
-
-void pack_split(const Layout& L, const TensorFactors& tf, const TuckItem& it, const SplitItem& sp, int np,
-                uint32_t* fac) {
-  const int nt = L.n_theta, npf = L.n_phi, Q = it.rt * it.rp;
-  for (int n = 0; n < it.nb; ++n)
-    for (int b = 0; b < it.rb; ++b) {
-      const cd v = tf.ub[(size_t)n * it.rb + b];
-      put_split(fac, sp.ubt, np, b, n, v);
-      put_split(fac, sp.ub, np, n, b, v);
-    }
-  for (int q = 0; q < Q; ++q)
-    for (int b = 0; b < it.rb; ++b) {
-      const cd v = tf.core[(size_t)q * it.rb + b];  // paper shape [rt][rp][rb], q = a rp + c
-      put_split(fac, sp.core, np, b, q, v);
-      put_split(fac, sp.coret, np, q, b, v);
-    }
-  if (it.ident) return;
-  for (int i = 0; i < nt; ++i)
-    for (int a = 0; a < it.rt; ++a) {
-      put_split(fac, sp.ut, np, i, a, tf.ut[(size_t)i * it.rt + a]);
-      put_split(fac, sp.utt, np, a, i, tf.ut[(size_t)i * it.rt + a]);
-    }
-  for (int j = 0; j < npf; ++j)
-    for (int c = 0; c < it.rp; ++c) {
-      put_split(fac, sp.up, np, j, c, tf.up[(size_t)j * it.rp + c]);
-      put_split(fac, sp.upt, np, c, j, tf.up[(size_t)j * it.rp + c]);
-    }
 }
 
 fmm_status check_vec(const void* p, size_t align, const char* name) {
@@ -659,18 +562,9 @@ extern "C" fmm_status fmm_tucker_export(fmm_tucker_t h, int32_t group, int32_t a
   if (!prec_valid(as_stored)) return fail(FMM_ERR_ARG, "bad precision %d", (int)as_stored);
   const TensorFactors& tf = h->t[2 * (size_t)group + alpha];
   if (!tf.set()) return fail(FMM_ERR_STATE, "factors of group %d polarisation %d are not set", group, alpha);
-  // the complex64 arena holds each part rounded to the nearest float (pack_tensor); the
-  // split arenas hold the bf16 pieces of that float (pack_split): three pieces
-  // reproduce it exactly, two keep its leading 16 bits
-  auto stored = [as_stored](double v) -> double {
-    if (as_stored == FMM_C128) return v;
-    if (as_stored == FMM_BF16X2) {
-      uint32_t pc[2];
-      split_value(v, 2, pc);
-      return (double)bf16_value(pc[0]) + (double)bf16_value(pc[1]);
-    }
-    return (double)(float)v;
-  };
+  // the complex64 arena (every precision but FMM_C128) holds each part rounded to the
+  // nearest float (pack_tensor)
+  auto stored = [as_stored](double v) -> double { return as_stored == FMM_C128 ? v : (double)(float)v; };
   auto give = [&stored](const std::vector<cd>& v, double* p) {
     if (!p) return;
     for (size_t i = 0; i < v.size(); ++i) {
@@ -738,9 +632,7 @@ extern "C" fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* are
   for (unsigned w = 0; w < nthreads; ++w)
     pool.emplace_back([&, w]() {
       for (size_t i = w; i < n_t; i += nthreads) {
-        if (P.np)
-          pack_split(h->layout, h->t[i], P.items[i], P.split[i], P.np, reinterpret_cast<uint32_t*>(fac));
-        else if (prec == FMM_C128)
+        if (prec == FMM_C128)
           pack_tensor<double>(h->layout, h->t[i], P.items[i], reinterpret_cast<double*>(fac));
         else
           pack_tensor<float>(h->layout, h->t[i], P.items[i], reinterpret_cast<float*>(fac));
@@ -759,8 +651,6 @@ extern "C" fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* are
   mrhs_release(sl);
   sl.tuned.clear();
   sl.items = P.items;
-  sl.np = P.np;
-  sl.split = P.split;
   {
     // workgroup size of the streaming kernels from the mean streamed elements per item:
     // small items leave most of a large workgroup idle

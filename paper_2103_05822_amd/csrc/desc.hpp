@@ -91,15 +91,9 @@ struct TuckPlan {
 //   A(m, k) at a + m lda_m + k lda_k
 //   B(k, n) at b + k ldb_k + (n / b_ni) b_shi + n % b_ni
 //   C(m, n) at c + m ldc_m + (n / c_ni) c_shi + n % c_ni
-// In the bf16 split precisions an operand may be stored split: NP planes of 32-bit
-// words (bf16 piece of the real part | bf16 piece of the imaginary part << 16), plane u
-// at the element position plus u times the plane stride ap / bp / cp (in words; 0 =
-// the operand is complex64).  Their factors are always split (and K-contiguous),
-// intermediates are split by the product that writes them, x, G, F and V are not.
 enum : int32_t { kConjA = 1, kConjB = 2, kConjC = 4, kAtomicC = 8 };
 struct CGemm {
   int64_t a, b, c;
-  int64_t ap, bp, cp;
   int32_t abase, bbase, cbase;
   int32_t M, N, K;
   int32_t lda_m, lda_k;
@@ -108,7 +102,7 @@ struct CGemm {
   int32_t flags;
   int32_t pad;
 };
-static_assert(sizeof(CGemm) == 112, "CGemm layout");
+static_assert(sizeof(CGemm) == 88, "CGemm layout");
 
 // Base pointers of a grouped launch: factors, scratch, x, F, G, V.
 enum : int32_t { kBaseFactors = 0, kBaseScratch = 1, kBaseX = 2, kBaseF = 3, kBaseG = 4, kBaseV = 5 };

@@ -74,29 +74,6 @@ struct MrhsPlan {
   std::vector<MrhsChunk> chunks;
 };
 
-// Arena of a bf16 split precision: every factor block in the orientation in which its
-// product reads it K-contiguously (both orientations of U^beta, the core, U^theta and
-// U^phi), as NP planes of 32-bit words (bf16 pieces of the real and imaginary parts,
-// formed on the host with round-to-nearest-even exactly as the kernels split values
-// on chip).  off and plane (the plane stride) count words from the factor base; rows
-// are ld words, a multiple of 4, zero padded.
-struct SplitBlock {
-  int64_t off = 0, plane = 0;
-  int32_t ld = 0, pad = 0;
-};
-struct SplitItem {
-  SplitBlock ubt;    // [r_beta][.]  (b, n) = U^beta[n][b]
-  SplitBlock ub;     // [n_beta][.]  (n, b)
-  SplitBlock core;   // [r_beta][.]  (b, q), q = theta' r_phi + phi'
-  SplitBlock coret;  // [Q][.]       (q, b)
-  SplitBlock ut;     // [n_theta][.] (i, a) = U^theta[i][a]
-  SplitBlock utt;    // [r_theta][.] (a, i)
-  SplitBlock up;     // [n_phi][.]   (j, c) = U^phi[j][c]
-  SplitBlock upt;    // [r_phi][.]   (c, j)
-};
-// bf16 pieces per value of a precision (0: not a split precision).
-inline int split_pieces(fmm_prec p) { return p == FMM_BF16X2 ? 2 : (p == FMM_BF16X3 ? 3 : 0); }
-
 // Tuned choice for one nrhs: path 0 = streaming kernels (workgroup size `threads`),
 // 1 = matrix-core products (K steps per tile, right-hand sides per chunk, angular
 // contraction order).
@@ -117,8 +94,6 @@ struct PrecSlot {
   std::vector<TuneChoice> tuned;
   void* part = nullptr;             // library-owned partial sums of split items (device)
   size_t part_bytes = 0;
-  int np = 0;                       // bf16 pieces of a split precision's arena (0: complex)
-  std::vector<SplitItem> split;     // its block offsets, per item
 };
 
 // Multi-RHS path (mrhs_plan.cpp).
@@ -135,8 +110,8 @@ struct MrhsHost {
   int64_t scratch_elems = 0;
   std::vector<MrhsHostChunk> chunks;
 };
-void mrhs_build_host(const std::vector<TuckItem>& items, const std::vector<SplitItem>& split, int np,
-                     const Layout& L, int nrhs, int tile_steps, int rhs_chunk, int order, MrhsHost* out);
+void mrhs_build_host(const std::vector<TuckItem>& items, const Layout& L, int nrhs, int tile_steps, int rhs_chunk,
+                     int order, MrhsHost* out);
 // Plan for (slot, nrhs) with the given knobs (0 = defaults), built on first use.
 // elem_bytes: 8 (complex64 slot) or 16 (complex128 slot), the size of a scratch value.
 fmm_status mrhs_get(PrecSlot& s, size_t elem_bytes, const Layout& L, int nrhs, int tile_steps, int rhs_chunk,

@@ -10,25 +10,26 @@
 // The descriptors of the products are built on the host (mrhs_plan.cpp); this file
 // holds the kernel.  One launch may mix products of both stages (a pass).
 //
-// A complex product C = A B runs on real MFMA instructions through the identity
-//   [Re C, Im C] = [Re A, Im A] [[Re B, Im B], [-Im B, Re B]]
+// A complex product C = A B runs on real MFMA instructions through the 2 x 2 real
+// expansion of one operand: no arithmetic is wasted (8 real flops per complex
+// multiply-add).  The FP32 and FP64 variants expand B,
+//   [Re C, Im C] = [Re A, Im A] [[Re B, Im B], [-Im B, Re B]],
 // with A read as a real matrix whose columns interleave (Re, Im) -- the stored
-// layout -- and B expanded to the 2 x 2 real blocks: no arithmetic is wasted (8 real
-// flops per complex multiply-add).
+// layout -- and B expanded when a step is written to LDS; the bf16 variants expand A
+// in registers (see their section).
 //
-// Workgroup tile: 64 rows x 64 complex columns (128 real), K in steps of 16 complex
-// values (32 real).  Four wavefronts, each owning 16 rows x 128 real columns = eight
-// 16 x 16 MFMA accumulators, of which a product of N < 64 columns runs only the
-// ceil(N / 8) its columns fill.  A workgroup walks its column blocks and K steps as one
-// flat pipeline: the global loads of step s + 1 are in flight while step s runs on the
-// matrix cores from LDS; conjugation, B expansion and the bf16 split happen when a
-// step is written to LDS (single buffered).
+// Workgroup tile: 64 rows x 64 complex columns, K in steps of 16 complex values (32
+// real).  Four wavefronts, each owning 16 rows of the tile and eight 16 x 16 MFMA
+// accumulators, of which a product of N < 64 columns runs only those its columns
+// fill.  A workgroup walks its column blocks and K steps as one flat pipeline: the
+// global loads of step s + 1 are in flight while step s runs on the matrix cores from
+// LDS (single buffered).
 //
-// Arithmetic variants (factors are stored as complex64 in every variant):
-//   0  FP32    v_mfma_f32_16x16x4_f32 on the FP32 operands;
+// Arithmetic variants (factors, vectors and intermediates are complex64 in all three):
+//   0  FP32    v_mfma_f32_16x16x4_f32;
 //   1  BF16x2  v_mfma_f32_16x16x32_bf16; both operands are split into bf16 pieces
-//              v = hi + lo and each product accumulates hi*hi + hi*lo + lo*hi in FP32
-//              (the dropped lo*lo term is below 2^-16 relative);
+//              v = hi + lo on chip and each product accumulates hi*hi + hi*lo + lo*hi
+//              in FP32 (the dropped lo*lo term is below 2^-16 relative);
 //   2  BF16x3  three pieces v = hi + mid + lo and the six products whose order is at
 //              most 2^-16 (hi*hi, hi*mid, mid*hi, hi*lo, mid*mid, lo*hi): FP32-level
 //              accuracy at six bf16 instructions per product.
@@ -37,7 +38,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <type_traits>
 
 #include "cplx.hpp"
 #include "kernels.hpp"
@@ -54,7 +54,6 @@ constexpr int kMT = 256;           // threads
 constexpr int kBM = 64;            // rows per tile
 constexpr int kBN = 64;            // complex columns per block
 constexpr int kKC = 16;            // complex K per step
-constexpr int kKR = 2 * kKC;       // real K per step
 constexpr int kNT = 2 * kBN / 16;  // 16-column accumulators per wavefront (8)
 // FP32 A LDS row stride (complex): padding keeps 16-byte alignment and spreads banks
 constexpr int kAS = kKC + 2;
@@ -305,16 +304,29 @@ __device__ __forceinline__ void mma_f64(const LdsF64& L, int w, int lane, double
 }
 
 // ------------------------------------------------------------------- BF16 variants
-// LDS holds the operands pre-split: A as [piece][row][32 real K] and
-// the expanded B as [piece][real column][32 real K], bf16, rows padded to 80 bytes
-// (conflict-free 16-byte accesses), so every lane reads its 8 K values of a piece
-// with one 16-byte load.
-constexpr int kPR = kKR + 8;  // bf16 row stride
+// Complex products on bf16 MFMA with the 2 x 2 real expansion on the A side:
+//   real row 2m     (Re a, -Im a) per complex K value    gives  Re c
+//   real row 2m + 1 (Im a,  Re a)                          gives  Im c
+// against B as stored, (Re b, Im b) per complex K value.  Operands are staged in LDS
+// as words holding one complex value's bf16 piece (Re | Im << 16): B words feed the
+// MFMA unchanged, and the words of real A row 2m + q are the staged word with its high
+// half negated (q = 0) or its halves swapped (q = 1), formed in registers after the LDS
+// read; the two lanes of a complex row read the same LDS address.  Compared with
+// expanding B, LDS holds half the B bytes and a wavefront reads 6 instead of 9 16-byte
+// fragments per piece and K step.  The factors and intermediates are complex64 in HBM
+// and are split when a step is written to LDS.
+// LDS per piece: A [64 complex rows][16 words], B [64 complex columns][16 words], rows
+// padded to 20 words.  Wavefront w owns complex rows 16w .. 16w + 15 (two MFMA blocks
+// of 8 complex rows) and the 64 complex columns (four MFMA blocks of 16 columns), of
+// which a product of N < 64 columns runs only the ceil(N / 16) blocks its columns fill
+// (rounded up to 1, 2 or 4).
+constexpr int kWS = kKC + 4;  // word row stride
+constexpr int kNB = kBN / 16;  // 16-column blocks per tile (4)
 
 template <int NP>
 struct LdsBf16 {
-  __bf16 a[NP][kBM * kPR];
-  __bf16 b[NP][2 * kBN * kPR];
+  uint32_t a[NP][kBM * kWS];
+  uint32_t b[NP][kBN * kWS];
 };
 
 // bf16 pieces of v: v ~ pc[0] + pc[1] (+ pc[2]), each the rounding of what is left.
@@ -329,131 +341,45 @@ __device__ __forceinline__ void split(float v, __bf16 (&pc)[NP]) {
   }
 }
 
-__device__ __forceinline__ __bf16 bneg(__bf16 x) { return -x; }
-
-// Pre-split operands.  A (a factor) arrives as np words per complex value, four K
-// values per piece in one 16-byte load: the words are already the bf16 pairs the A
-// layout holds.  B arrives either split (an intermediate: np words per value, written
-// by the product that computed it) or as complex64 (x or G: split here, once per
-// staged value).  The expanded B columns of complex column n are, per K value,
-//   real column 2n: (Re b, -Im b) = word ^ 0x80000000 (negates the high half),
-//   real column 2n + 1: (Im b, Re b) = the word's halves swapped;
-// split(-v) = -split(v) (rounding to nearest is symmetric), so the pieces of -Im b are
-// the negated pieces of Im b.
 __device__ __forceinline__ uint32_t bf16_bits(__bf16 h) { return (uint32_t)__builtin_bit_cast(uint16_t, h); }
-__device__ __forceinline__ uint32_t neg_im(uint32_t w) { return w ^ 0x80000000u; }
-__device__ __forceinline__ uint32_t swap_halves(uint32_t w) { return (w >> 16) | (w << 16); }
 
-template <int NP, bool PREB>
-struct StageB16 {
-  uint4 a[NP];          // A: piece u, four K values
-  uint32_t bw[NP][4];   // B split (PREB): piece u of K value e
-  float2 bf[4];         // B complex64 (!PREB)
-  int na, nb;
-};
-
-// Operand walkers of the split path: A is always K-contiguous split words; B is split
-// words (PREB) or complex64.
-template <bool PREB>
-struct WalkB16 {
-  using BT = typename std::conditional<PREB, const uint32_t, const float2>::type;
-  const uint32_t* a;  // the thread's A quad at the current K step (piece 0)
-  bool arow;
-  int aq;
-  BT* clampb;
-  BT* b;
-  int64_t bstep;
-  int bq;
-  bool bcol;
-};
-
-template <bool PREB>
-__device__ __forceinline__ void walk_init_b16(const CGemm& p, const uint32_t* A, const void* B, int m0, int tid,
-                                              WalkB16<PREB>& w) {
-  const int am = m0 + tid / 4;
-  w.aq = tid % 4;
-  w.arow = am < p.M;
-  w.a = A + p.a + (w.arow ? (int64_t)am * p.lda_m + 4 * w.aq : 0);
-  w.clampb = static_cast<typename WalkB16<PREB>::BT*>(B) + p.b;
-  w.bq = tid / 64;
-}
-
-template <bool PREB>
-__device__ __forceinline__ void walk_block_b16(const CGemm& p, const uint32_t* A, int n0, int m0, int tid,
-                                               WalkB16<PREB>& w) {
-  const int n = n0 + tid % 64;
-  w.bcol = n < p.N;
-  w.b = w.bcol ? w.clampb + col_off(n, p.b_ni, p.b_shi) + (int64_t)(4 * w.bq) * p.ldb_k : w.clampb;
-  w.bstep = w.bcol ? (int64_t)kKC * p.ldb_k : 0;
-  const int am = m0 + tid / 4;
-  w.a = A + p.a + (w.arow ? (int64_t)am * p.lda_m + 4 * w.aq : 0);
-}
-
-template <int NP, bool PREB>
-__device__ __forceinline__ void load_stage_b16(const CGemm& p, int k0, WalkB16<PREB>& w, StageB16<NP, PREB>& st) {
-  const int na = w.arow ? min(4, max(0, p.K - k0 - 4 * w.aq)) : 0;
-  const int nb = w.bcol ? min(4, max(0, p.K - k0 - 4 * w.bq)) : 0;
-  // a quad starting inside the K range lies inside its row (rows are padded to four)
-#pragma unroll
-  for (int u = 0; u < NP; ++u)
-    st.a[u] = na > 0 ? *reinterpret_cast<const uint4*>(w.a + u * p.ap) : make_uint4(0, 0, 0, 0);
-  if constexpr (PREB) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-#pragma unroll
-      for (int u = 0; u < NP; ++u) st.bw[u][e] = e < nb ? w.b[e * p.ldb_k + u * p.bp] : 0u;
-  } else {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) st.bf[e] = e < nb ? w.b[e * p.ldb_k] : czero<float2>();
-  }
-  st.na = na;
-  st.nb = nb;
-  w.a += kKC;
-  w.b += w.bstep;
-}
-
-template <int NP, bool PREB>
-__device__ __forceinline__ void store_stage_b16(const CGemm& p, const StageB16<NP, PREB>& st, LdsBf16<NP>& L,
-                                                int tid) {
+// A and B are loaded by the FP32 variant's walkers and split into bf16 pieces when the
+// step is written to LDS, with the invalid elements zeroed and the conjugation flags
+// applied.
+template <int NP>
+__device__ __forceinline__ void store_stage_b16(const CGemm& p, const Stage<float2>& st, LdsBf16<NP>& L,
+                                                 int tid) {
   {
-    const int m = tid / 4, kq = tid % 4;
-#pragma unroll
-    for (int u = 0; u < NP; ++u) {
-      uint4 v = st.a[u];
-      if (st.na < 4) {  // the K tail: words past K are zero
-        if (st.na < 4) v.w = 0;
-        if (st.na < 3) v.z = 0;
-        if (st.na < 2) v.y = 0;
-      }
-      *reinterpret_cast<uint4*>(&L.a[u][m * kPR + 8 * kq]) = v;
-    }
-  }
-  const int nn = tid % 64, kq = tid / 64;
-  uint32_t w[NP][4];
-  if constexpr (PREB) {
-#pragma unroll
-    for (int u = 0; u < NP; ++u)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) w[u][e] = st.bw[u][e];
-  } else {
+    int m, kq;
+    a_slot(p, tid, m, kq);
+    uint32_t w[NP][4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      float2 v = st.bf[e];
-      if (p.flags & kConjB) v.y = -v.y;
+      const float2 v = a_val(p, st, e);
       __bf16 re[NP], im[NP];
       split<NP>(v.x, re);
       split<NP>(v.y, im);
 #pragma unroll
       for (int u = 0; u < NP; ++u) w[u][e] = bf16_bits(re[u]) | (bf16_bits(im[u]) << 16);
     }
+#pragma unroll
+    for (int u = 0; u < NP; ++u)
+      *reinterpret_cast<uint4*>(&L.a[u][m * kWS + 4 * kq]) = make_uint4(w[u][0], w[u][1], w[u][2], w[u][3]);
+  }
+  const int nn = tid % 64, kq = tid / 64;
+  uint32_t w[NP][4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const float2 v = b_val(p, st, e);
+    __bf16 re[NP], im[NP];
+    split<NP>(v.x, re);
+    split<NP>(v.y, im);
+#pragma unroll
+    for (int u = 0; u < NP; ++u) w[u][e] = bf16_bits(re[u]) | (bf16_bits(im[u]) << 16);
   }
 #pragma unroll
-  for (int u = 0; u < NP; ++u) {
-    const uint4 c0 = make_uint4(neg_im(w[u][0]), neg_im(w[u][1]), neg_im(w[u][2]), neg_im(w[u][3]));
-    const uint4 c1 = make_uint4(swap_halves(w[u][0]), swap_halves(w[u][1]), swap_halves(w[u][2]), swap_halves(w[u][3]));
-    *reinterpret_cast<uint4*>(&L.b[u][(2 * nn) * kPR + 8 * kq]) = c0;
-    *reinterpret_cast<uint4*>(&L.b[u][(2 * nn + 1) * kPR + 8 * kq]) = c1;
-  }
+  for (int u = 0; u < NP; ++u)
+    *reinterpret_cast<uint4*>(&L.b[u][nn * kWS + 4 * kq]) = make_uint4(w[u][0], w[u][1], w[u][2], w[u][3]);
 }
 
 template <int NP>
@@ -469,29 +395,66 @@ __device__ __forceinline__ void mma_pair(const bf16x8 (&ap)[NP], const bf16x8 (&
   acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[0], bp[0], acc, 0, 0, 0);
 }
 
-template <int NP, int NTE>
-__device__ __forceinline__ void mma_bf16(const LdsBf16<NP>& L, int w, int lane, floatx4 (&acc)[NTE]) {
+// Lane (mi, kb) of wavefront w: real A row mi of each 16-row block (complex row
+// 16w + 8rb + mi / 2, part mi & 1), B column 16t + mi, complex K values 4kb .. 4kb + 3
+// (real K 8kb .. 8kb + 7, the same order in A and B).
+template <int NP, int NTB>
+__device__ __forceinline__ void mma_bf16(const LdsBf16<NP>& L, int w, int lane, floatx4 (&acc)[2][NTB]) {
   const int mi = lane % 16, kb = lane / 16;
-  bf16x8 ap[NP];
+  const uint32_t rot = (mi & 1) ? 16u : 0u;            // swap the halves: (Im a, Re a)
+  const uint32_t flip = (mi & 1) ? 0u : 0x80000000u;   // negate the high half: (Re a, -Im a)
+  bf16x8 ap[2][NP];
 #pragma unroll
-  for (int u = 0; u < NP; ++u) ap[u] = *reinterpret_cast<const bf16x8*>(&L.a[u][(16 * w + mi) * kPR + 8 * kb]);
-  if constexpr (NTE == 1) {
-    bf16x8 b0[NP];
+  for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-    for (int u = 0; u < NP; ++u) b0[u] = *reinterpret_cast<const bf16x8*>(&L.b[u][mi * kPR + 8 * kb]);
-    mma_pair<NP>(ap, b0, acc[0]);
-  } else {
-#pragma unroll
-    for (int t = 0; t < NTE; t += 2) {
-      bf16x8 b0[NP], b1[NP];
-#pragma unroll
-      for (int u = 0; u < NP; ++u) {
-        b0[u] = *reinterpret_cast<const bf16x8*>(&L.b[u][(16 * t + mi) * kPR + 8 * kb]);
-        b1[u] = *reinterpret_cast<const bf16x8*>(&L.b[u][(16 * (t + 1) + mi) * kPR + 8 * kb]);
-      }
-      mma_pair<NP>(ap, b0, acc[t]);
-      mma_pair<NP>(ap, b1, acc[t + 1]);
+    for (int u = 0; u < NP; ++u) {
+      uint4 v = *reinterpret_cast<const uint4*>(&L.a[u][(16 * w + 8 * rb + mi / 2) * kWS + 4 * kb]);
+      v.x = __builtin_rotateright32(v.x, rot) ^ flip;
+      v.y = __builtin_rotateright32(v.y, rot) ^ flip;
+      v.z = __builtin_rotateright32(v.z, rot) ^ flip;
+      v.w = __builtin_rotateright32(v.w, rot) ^ flip;
+      ap[rb][u] = __builtin_bit_cast(bf16x8, v);
     }
+#pragma unroll
+  for (int t = 0; t < NTB; ++t) {
+    bf16x8 bp[NP];
+#pragma unroll
+    for (int u = 0; u < NP; ++u)
+      bp[u] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&L.b[u][(16 * t + mi) * kWS + 4 * kb]));
+    mma_pair<NP>(ap[0], bp, acc[0][t]);
+    mma_pair<NP>(ap[1], bp, acc[1][t]);
+  }
+}
+
+// Accumulator register i of lane (ni, g) in block (rb, t) holds real row 4g + i of the
+// block: complex row 16w + 8rb + 2g + i / 2, real part for even i, imaginary for odd,
+// of complex column 16t + ni.  Every lane thus holds whole complex values.
+template <int NTB>
+__device__ __forceinline__ void epilogue_b16(const CGemm& p, float2* Cp, int m0, int n0, int w, int lane,
+                                             const floatx4 (&acc)[2][NTB]) {
+  const int ni = lane % 16, g = lane / 16;
+  const bool conj_out = p.flags & kConjC, atomic = p.flags & kAtomicC;
+#pragma unroll
+  for (int t = 0; t < NTB; ++t) {
+    const int n = n0 + 16 * t + ni;
+    if (n >= p.N) continue;
+    const int64_t coff = p.c + col_off(n, p.c_ni, p.c_shi);
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int m = m0 + 16 * w + 8 * rb + 2 * g + i;
+        if (m >= p.M) continue;
+        float2 c = make_float2(acc[rb][t][2 * i], acc[rb][t][2 * i + 1]);
+        if (conj_out) c.y = -c.y;
+        float2* dst = Cp + coff + (int64_t)m * p.ldc_m;
+        if (atomic) {
+          atomicAdd(&dst->x, c.x);
+          atomicAdd(&dst->y, c.y);
+        } else {
+          *dst = c;
+        }
+      }
   }
 }
 
@@ -501,9 +464,7 @@ __device__ __forceinline__ void mma_bf16(const LdsBf16<NP>& L, int w, int lane, 
 // Lanes ni and ni ^ 1 hold the real and imaginary parts of one complex column: after
 // one exchange the even lane owns the rows of registers 0, 1 and the odd lane those
 // of registers 2, 3 as complex values.
-// NPW > 0 (bf16 split precisions, C an intermediate another product reads): each
-// value is written as NPW words (its bf16 pieces) in planes p.cp words apart.
-template <typename C2, typename ACC, int NTE, int NPW = 0>
+template <typename C2, typename ACC, int NTE>
 __device__ __forceinline__ void epilogue(const CGemm& p, C2* Cp, int m0, int n0, int w, int lane,
                                          const ACC (&acc)[NTE]) {
   using R = decltype(C2{}.x);
@@ -534,14 +495,7 @@ __device__ __forceinline__ void epilogue(const CGemm& p, C2* Cp, int m0, int n0,
       if (m >= p.M) continue;
       C2* dst = Cp + coff + (int64_t)m * p.ldc_m;
       const C2 c = i ? c1 : c0;
-      if constexpr (NPW > 0) {
-        uint32_t* dw = reinterpret_cast<uint32_t*>(Cp) + coff + (int64_t)m * p.ldc_m;
-        __bf16 re[NPW], im[NPW];
-        split<NPW>((float)c.x, re);
-        split<NPW>((float)c.y, im);
-#pragma unroll
-        for (int u = 0; u < NPW; ++u) dw[u * p.cp] = bf16_bits(re[u]) | (bf16_bits(im[u]) << 16);
-      } else if (atomic) {
+      if (atomic) {
         atomicAdd(&dst->x, c.x);
         atomicAdd(&dst->y, c.y);
       } else {
@@ -683,26 +637,27 @@ __device__ __forceinline__ void run_tile_of(const CGemm& p, const CTile& tl, con
     run_tile<VARIANT, AVEC, true, kNT>(p, tl, A, B, Cp, L);
 }
 
-// The bf16 variants: the pipeline of run_tile on pre-split operands.
-template <int VARIANT, bool PREB, bool ACTIVE, int NTE>
-__device__ __forceinline__ void run_tile_b16(const CGemm& p, const CTile& tl, const uint32_t* A, const void* B,
-                                             void* Cp, typename VarOf<VARIANT>::lds& L) {
+// The bf16 variants: the pipeline of run_tile with the split at the LDS store.
+template <int VARIANT, bool AVEC, bool ACTIVE, int NTB>
+__device__ __forceinline__ void run_tile_b16(const CGemm& p, const CTile& tl, const float2* A, const float2* B,
+                                              float2* Cp, typename VarOf<VARIANT>::lds& L) {
   constexpr int NP = VARIANT + 1;
-  using ACC = floatx4;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int nsteps = (p.K + kKC - 1) / kKC;
 
-  ACC acc[NTE];
+  floatx4 acc[2][NTB];
   if constexpr (ACTIVE) {
 #pragma unroll
-    for (int t = 0; t < NTE; ++t) acc[t] = ACC{0, 0, 0, 0};
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int t = 0; t < NTB; ++t) acc[rb][t] = floatx4{0, 0, 0, 0};
   }
-  WalkB16<PREB> wk;
-  walk_init_b16<PREB>(p, A, B, tl.m0, tid, wk);
-  walk_block_b16<PREB>(p, A, tl.n0, tl.m0, tid, wk);
-  StageB16<NP, PREB> st;
-  load_stage_b16<NP, PREB>(p, 0, wk, st);
-  store_stage_b16<NP, PREB>(p, st, L, tid);
+  Walk<float2> wk;
+  walk_init(p, A, B, tl.m0, tid, wk);
+  walk_block(p, tl.n0, tid, wk);
+  Stage<float2> st;
+  load_stage<AVEC>(p, 0, wk, st);
+  store_stage_b16<NP>(p, st, L, tid);
   __syncthreads();
   for (int n0 = tl.n0;;) {
     for (int s = 0; s < nsteps; ++s) {
@@ -713,44 +668,39 @@ __device__ __forceinline__ void run_tile_b16(const CGemm& p, const CTile& tl, co
       }
       const bool more = nn0 < tl.n1;
       if (more) {
-        if (ns == 0) walk_block_b16<PREB>(p, A, nn0, tl.m0, tid, wk);
-        load_stage_b16<NP, PREB>(p, ns * kKC, wk, st);
+        if (ns == 0) walk_block(p, nn0, tid, wk);
+        load_stage<AVEC>(p, ns * kKC, wk, st);
       }
-      if constexpr (ACTIVE) mma_bf16<NP, NTE>(L, w, lane, acc);
+      if constexpr (ACTIVE) mma_bf16<NP, NTB>(L, w, lane, acc);
       if (more) {
         __syncthreads();  // every wavefront is done reading the step
-        store_stage_b16<NP, PREB>(p, st, L, tid);
+        store_stage_b16<NP>(p, st, L, tid);
         __syncthreads();
       }
     }
-    if constexpr (ACTIVE) {
-      if (p.cp)
-        epilogue<float2, ACC, NTE, NP>(p, static_cast<float2*>(Cp), tl.m0, n0, w, lane, acc);
-      else
-        epilogue<float2, ACC, NTE, 0>(p, static_cast<float2*>(Cp), tl.m0, n0, w, lane, acc);
-    }
+    if constexpr (ACTIVE) epilogue_b16<NTB>(p, Cp, tl.m0, n0, w, lane, acc);
     n0 += kBN;
     if (n0 >= tl.n1) break;
     if constexpr (ACTIVE) {
 #pragma unroll
-      for (int t = 0; t < NTE; ++t) acc[t] = ACC{0, 0, 0, 0};
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int t = 0; t < NTB; ++t) acc[rb][t] = floatx4{0, 0, 0, 0};
     }
   }
 }
 
-template <int VARIANT, bool PREB>
-__device__ __forceinline__ void run_tile_of_b16(const CGemm& p, const CTile& tl, const uint32_t* A, const void* B,
-                                                void* Cp, typename VarOf<VARIANT>::lds& L) {
+template <int VARIANT, bool AVEC>
+__device__ __forceinline__ void run_tile_of_b16(const CGemm& p, const CTile& tl, const float2* A, const float2* B,
+                                                 float2* Cp, typename VarOf<VARIANT>::lds& L) {
   if (tl.m0 + 16 * (int)(threadIdx.x >> 6) >= p.M)
-    run_tile_b16<VARIANT, PREB, false, 1>(p, tl, A, B, Cp, L);
-  else if (p.N <= 8)
-    run_tile_b16<VARIANT, PREB, true, 1>(p, tl, A, B, Cp, L);
+    run_tile_b16<VARIANT, AVEC, false, 1>(p, tl, A, B, Cp, L);
   else if (p.N <= 16)
-    run_tile_b16<VARIANT, PREB, true, 2>(p, tl, A, B, Cp, L);
+    run_tile_b16<VARIANT, AVEC, true, 1>(p, tl, A, B, Cp, L);
   else if (p.N <= 32)
-    run_tile_b16<VARIANT, PREB, true, 4>(p, tl, A, B, Cp, L);
+    run_tile_b16<VARIANT, AVEC, true, 2>(p, tl, A, B, Cp, L);
   else
-    run_tile_b16<VARIANT, PREB, true, kNT>(p, tl, A, B, Cp, L);
+    run_tile_b16<VARIANT, AVEC, true, kNB>(p, tl, A, B, Cp, L);
 }
 
 template <int VARIANT>
@@ -767,11 +717,10 @@ __global__ __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(VarOf<VARIA
   // paired 16-byte A loads (complex64): K-contiguous A with an even offset and row
   // stride
   if constexpr (VARIANT == 1 || VARIANT == 2) {
-    const uint32_t* Aw = base_ptr<const uint32_t>(bases, p.abase);
-    if (p.bp)
-      run_tile_of_b16<VARIANT, true>(p, tl, Aw, B, Cp, L);
+    if (p.lda_k == 1 && !((p.a | p.lda_m) & 1))
+      run_tile_of_b16<VARIANT, true>(p, tl, A, B, Cp, L);
     else
-      run_tile_of_b16<VARIANT, false>(p, tl, Aw, B, Cp, L);
+      run_tile_of_b16<VARIANT, false>(p, tl, A, B, Cp, L);
   } else if constexpr (VARIANT == 3) {
     run_tile_of<VARIANT, false>(p, tl, A, B, Cp, L);
   } else {

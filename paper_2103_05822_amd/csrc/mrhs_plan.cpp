@@ -113,40 +113,6 @@ void item_products(const TuckItem& it, const Layout& L, int R, int r0, int rc, c
                      kAtomicC | kConjC);
 }
 
-// Split precisions: every A operand comes from the K-contiguous split block of its
-// factor, and the scratch intermediates are split (plane strides pa / pd of the
-// item's three aggregation / disaggregation blocks); x, G, F and V stay complex64.
-void split_fixup(const TuckItem& it, const SplitItem& sp, const int64_t pa[3], const int64_t pd[3], CGemm out[8]) {
-  auto setA = [](CGemm& g, const SplitBlock& b) {
-    g.a = b.off;
-    g.lda_m = b.ld;
-    g.lda_k = 1;
-    g.ap = b.plane;
-  };
-  setA(out[0], sp.ubt);
-  out[0].cp = pa[0];
-  setA(out[1], sp.coret);
-  out[1].bp = pa[0];
-  if (!it.ident) out[1].cp = pa[1];
-  if (!it.ident) {
-    setA(out[2], it.theta_first ? sp.ut : sp.up);
-    out[2].bp = pa[1];
-    out[2].cp = pa[2];
-    setA(out[3], it.theta_first ? sp.up : sp.ut);
-    out[3].bp = pa[2];
-    setA(out[4], it.theta_first ? sp.upt : sp.utt);
-    out[4].cp = pd[2];
-    setA(out[5], it.theta_first ? sp.utt : sp.upt);
-    out[5].bp = pd[2];
-    out[5].cp = pd[1];
-    out[6].bp = pd[1];
-  }
-  setA(out[6], sp.core);
-  out[6].cp = pd[0];
-  setA(out[7], sp.ub);
-  out[7].bp = pd[0];
-}
-
 struct TileCost {
   CTile t;
   int64_t cost;
@@ -245,8 +211,8 @@ void mrhs_release(PrecSlot& s) {
   s.mrhs.clear();
 }
 
-void mrhs_build_host(const std::vector<TuckItem>& items_in, const std::vector<SplitItem>& split, int np,
-                     const Layout& L, int nrhs, int tile_steps, int rhs_chunk, int order, MrhsHost* out) {
+void mrhs_build_host(const std::vector<TuckItem>& items_in, const Layout& L, int nrhs, int tile_steps,
+                     int rhs_chunk, int order, MrhsHost* out) {
   // the angular order: each item's cheaper one (order 0), or theta (1) / phi (2) first
   // for every item
   std::vector<TuckItem> items(items_in);
@@ -255,10 +221,8 @@ void mrhs_build_host(const std::vector<TuckItem>& items_in, const std::vector<Sp
       if (!it.ident) it.theta_first = order == 1 ? 1 : 0;
   const int n_items = (int)items.size();
   const int n_chunks = (nrhs + rhs_chunk - 1) / rhs_chunk;
-  // scratch: per item, three blocks per stage (sized for a full chunk); in a split
-  // precision each block is np planes of words, plane strides pa / pd
+  // scratch: per item, three blocks per stage (sized for a full chunk)
   std::vector<int64_t> sa((size_t)3 * n_items), sd((size_t)3 * n_items);
-  std::vector<int64_t> pa((size_t)3 * n_items, 0), pd((size_t)3 * n_items, 0);
   int64_t soff = 0;
   for (int i = 0; i < n_items; ++i) {
     const TuckItem& it = items[i];
@@ -268,10 +232,8 @@ void mrhs_build_host(const std::vector<TuckItem>& items_in, const std::vector<Sp
     const int64_t sz[3] = {it.rb, it.ident ? 0 : q, it.ident ? 0 : t3};
     for (int st = 0; st < 2; ++st)
       for (int j = 0; j < 3; ++j) {
-        const int64_t plane = np ? (sz[j] * rhs_chunk + 63) / 64 * 64 : up32(sz[j] * rhs_chunk);
         (st ? sd : sa)[3 * i + j] = soff;
-        (st ? pd : pa)[3 * i + j] = np ? plane : 0;
-        soff += (np ? np : 1) * plane;
+        soff += up32(sz[j] * rhs_chunk);
       }
   }
   out->scratch_elems = soff;
@@ -284,7 +246,6 @@ void mrhs_build_host(const std::vector<TuckItem>& items_in, const std::vector<Sp
     for (int i = 0; i < n_items; ++i) {
       CGemm g[8];
       item_products(items[i], L, nrhs, h.r0, h.rc, &sa[3 * i], &sd[3 * i], g);
-      if (np) split_fixup(items[i], split[i], &pa[3 * i], &pd[3 * i], g);
       for (int j = 0; j < 8; ++j) h.probs[(size_t)j * n_items + i] = g[j];
     }
     for (int j = 0; j < 4; ++j) {
@@ -321,7 +282,7 @@ fmm_status mrhs_get(PrecSlot& s, size_t elem_bytes, const Layout& L, int nrhs, i
       return FMM_OK;
     }
   MrhsHost host;
-  mrhs_build_host(s.items, s.split, s.np, L, nrhs, tile_steps, rhs_chunk, order, &host);
+  mrhs_build_host(s.items, L, nrhs, tile_steps, rhs_chunk, order, &host);
   const int n_chunks = (int)host.chunks.size();
   size_t table_bytes = 0;
   for (const MrhsHostChunk& h : host.chunks) {
@@ -329,8 +290,7 @@ fmm_status mrhs_get(PrecSlot& s, size_t elem_bytes, const Layout& L, int nrhs, i
     for (int k = 0; k < 3; ++k)
       for (int j = 0; j < 4; ++j) table_bytes += align256(h.lists[k][j].size() * sizeof(CTile));
   }
-  // a split precision's scratch holds 4-byte words, the others complex values
-  const size_t scratch_bytes = (size_t)host.scratch_elems * (s.np ? 4 : elem_bytes);
+  const size_t scratch_bytes = (size_t)host.scratch_elems * elem_bytes;
 
   // one device allocation: tables, then scratch
   MrhsPlan p;

@@ -146,6 +146,30 @@ def test_mrhs_ragged_layout(prec, rank_mode, nrhs):
 
 
 @pytest.mark.parametrize("prec", PRECS, ids=PIDS)
+def test_mrhs_many_small_items(prec):
+    """5000 small items (n_beta 1..80 on the 17 x 33 grid), 8 right-hand sides, on the
+    matrix cores: every tile is a ragged tail."""
+    rng = synth.rng(71)
+    sizes = rng.integers(1, 81, size=2500)
+    lay = T.Layout(17, 33, np.concatenate([[0], np.cumsum(sizes)]))
+    nrhs = 8
+    banner("mrhs many small items prec=%d groups=%d nrhs=%d" % (prec, lay.n_groups, nrhs))
+    tuck = random_tucker(lay, 73)
+    x, gin = inputs(lay, nrhs, 8)
+    f_ref = pr.aggregate_all("tucker", tuck, lay.offsets, x)
+    v_ref = pr.disaggregate_all("tucker", tuck, lay.offsets, gin)
+    H = Handle(lay, tuck, prec)
+    try:
+        T.fmm_tucker_set_tuned(H.h, prec, nrhs, 1, tile_steps=16, rhs_chunk=nrhs)
+        F = dev(np.zeros(f_ref.shape, CDT[prec]))
+        V = dev(np.zeros(v_ref.shape, CDT[prec]))
+        T.fmm_tucker_pass(H.h, prec, nrhs, dev(x, CDT[prec]), F, dev(gin, CDT[prec]), V)
+        check(prec, host(F), host(V), f_ref, v_ref)
+    finally:
+        H.close()
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=PIDS)
 def test_mrhs_paper_grid(prec):
     """38 x 75 grid, realistic ranks, 8 right-hand sides: pass and separate stages."""
     lay, tuck = paper_grid_tucker()

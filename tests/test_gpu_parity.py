@@ -351,6 +351,50 @@ def test_tucker_workgroup_sizes(prec, threads, monkeypatch):
         T.fmm_tucker_destroy(h)
 
 
+def many_small_layout(n_groups=2500, seed=71):
+    """Thousands of small groups, n_beta drawn from 1..80, on the 17 x 33 grid of the
+    0.5-lambda boxes: the regime where a single item streams only a few kilobytes."""
+    rng = synth.rng(seed)
+    sizes = rng.integers(1, 81, size=n_groups)
+    return T.Layout(17, 33, np.concatenate([[0], np.cumsum(sizes)]))
+
+
+@pytest.mark.parametrize("threads", [0, 64, 128])
+@pytest.mark.parametrize("prec", [T.FMM_C128, T.FMM_C64], ids=["c128", "c64"])
+def test_tucker_many_small_items(prec, threads, monkeypatch):
+    """5000 small items (no row-block splitting at this count) with random ranks: the
+    merged pass and the separate stages against the oracle, for the workgroup size the
+    layout picks (0) and forced sizes."""
+    if threads:
+        monkeypatch.setenv("TUCKFMM_STREAM_THREADS", str(threads))
+    lay = many_small_layout()
+    banner("tucker many small items prec=%d threads=%d groups=%d" % (prec, threads, lay.n_groups))
+    tuck = random_tucker(lay, 72)
+    rng = synth.rng(12)
+    x = synth.complex_normal(rng, lay.n_basis)
+    gin = synth.complex_normal(rng, (lay.n_groups, 2, lay.n_dir))
+    f_ref, v_ref = oracle_tucker(lay, tuck, x, gin)
+    h = make_handle(lay, tuck)
+    try:
+        _, nbytes = T.fmm_tucker_storage_bytes(h, prec)
+        ar = arena(nbytes)
+        T.fmm_tucker_upload(h, prec, ar)
+        xd, gd = dev(x, CDT[prec]), dev(gin, CDT[prec])
+        F = dev(np.zeros(f_ref.shape, CDT[prec]))
+        V = dev(np.zeros(v_ref.shape, CDT[prec]))
+        T.fmm_tucker_pass(h, prec, 1, xd, F, gd, V)
+        Fp, Vp = host(F), host(V)
+        tol = TOL[prec]
+        res = (l2_rel(Fp, f_ref), max_rel(Fp, f_ref), l2_rel(Vp, v_ref), max_rel(Vp, v_ref))
+        print("  errors: F l2 %.2e max %.2e | V l2 %.2e max %.2e" % res, flush=True)
+        assert max(res) < tol, res
+        T.fmm_tucker_aggregate(h, prec, 1, xd, F)
+        T.fmm_tucker_disaggregate(h, prec, 1, gd, V)
+        assert np.array_equal(host(F), Fp) and np.array_equal(host(V), Vp)
+    finally:
+        T.fmm_tucker_destroy(h)
+
+
 # ------------------------------------------------------------ truncated SVD (comparison)
 
 def random_svd(lay, seed, rank_mode="random"):
