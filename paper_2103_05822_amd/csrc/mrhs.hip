@@ -329,19 +329,24 @@ struct LdsBf16 {
   uint32_t b[NP][kBN * kWS];
 };
 
-// bf16 pieces of v: v ~ pc[0] + pc[1] (+ pc[2]), each the rounding of what is left.
+// The NP words of a complex value v: word u holds the bf16 pieces u of Re v (low half)
+// and Im v (high half), v ~ sum of the pieces, each piece the round-to-nearest bf16 of
+// what the earlier pieces leave.  Both parts convert in one packed instruction, and a
+// half widens back to FP32 by its position (shift or mask).
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 template <int NP>
-__device__ __forceinline__ void split(float v, __bf16 (&pc)[NP]) {
-  pc[0] = (__bf16)v;
-  float r = v - (float)pc[0];
-  pc[1] = (__bf16)r;
-  if constexpr (NP == 3) {
-    r -= (float)pc[1];
-    pc[2] = (__bf16)r;
+__device__ __forceinline__ void split_words(float2 v, uint32_t (&w)[NP]) {
+  floatx2 r = {v.x, v.y};
+#pragma unroll
+  for (int u = 0; u < NP; ++u) {
+    w[u] = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2));
+    if (u + 1 < NP) {
+      r.x -= __builtin_bit_cast(float, w[u] << 16);
+      r.y -= __builtin_bit_cast(float, w[u] & 0xffff0000u);
+    }
   }
 }
-
-__device__ __forceinline__ uint32_t bf16_bits(__bf16 h) { return (uint32_t)__builtin_bit_cast(uint16_t, h); }
 
 // A and B are loaded by the FP32 variant's walkers and split into bf16 pieces when the
 // step is written to LDS, with the invalid elements zeroed and the conjugation flags
@@ -355,12 +360,10 @@ __device__ __forceinline__ void store_stage_b16(const CGemm& p, const Stage<floa
     uint32_t w[NP][4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const float2 v = a_val(p, st, e);
-      __bf16 re[NP], im[NP];
-      split<NP>(v.x, re);
-      split<NP>(v.y, im);
+      uint32_t pc[NP];
+      split_words<NP>(a_val(p, st, e), pc);
 #pragma unroll
-      for (int u = 0; u < NP; ++u) w[u][e] = bf16_bits(re[u]) | (bf16_bits(im[u]) << 16);
+      for (int u = 0; u < NP; ++u) w[u][e] = pc[u];
     }
 #pragma unroll
     for (int u = 0; u < NP; ++u)
@@ -370,12 +373,10 @@ __device__ __forceinline__ void store_stage_b16(const CGemm& p, const Stage<floa
   uint32_t w[NP][4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    const float2 v = b_val(p, st, e);
-    __bf16 re[NP], im[NP];
-    split<NP>(v.x, re);
-    split<NP>(v.y, im);
+    uint32_t pc[NP];
+    split_words<NP>(b_val(p, st, e), pc);
 #pragma unroll
-    for (int u = 0; u < NP; ++u) w[u][e] = bf16_bits(re[u]) | (bf16_bits(im[u]) << 16);
+    for (int u = 0; u < NP; ++u) w[u][e] = pc[u];
   }
 #pragma unroll
   for (int u = 0; u < NP; ++u)
