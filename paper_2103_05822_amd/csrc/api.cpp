@@ -218,10 +218,17 @@ fmm_status plan_arena(const fmm_tucker_s* h, fmm_prec prec, ArenaPlan* P) {
   P->order.resize(n);
   std::iota(P->order.begin(), P->order.end(), 0);
   std::stable_sort(P->order.begin(), P->order.end(), [&](int32_t a, int32_t b) { return ucost[a] > ucost[b]; });
+  // The pass list takes the aggregation and the disaggregation of the i-th largest
+  // unit in turn.  Workgroups go to the eight XCDs round-robin by index, so with the
+  // pair always in the same order the even XCDs would run only aggregation units and
+  // the odd ones only disaggregation units, which take longer on small boxes (the 0.5-
+  // lambda layout of the 20-lambda sphere: the two halves of the chip finished 623 and
+  // 900 us into the pass).  Every other group of four pairs is therefore swapped.
   P->pass.resize((size_t)2 * n);
   for (int i = 0; i < n; ++i) {
-    P->pass[2 * i] = P->order[i];        // aggregation of the i-th largest unit
-    P->pass[2 * i + 1] = ~P->order[i];   // and its disaggregation
+    const int first = (i / 4) & 1;
+    P->pass[2 * i + first] = P->order[i];        // aggregation of the i-th largest unit
+    P->pass[2 * i + 1 - first] = ~P->order[i];   // and its disaggregation
   }
   // box grid: the rows of the empty boxes, written zero by the aggregation
   if (!h->box.empty()) {
