@@ -312,8 +312,11 @@ fmm_status fmm_tucker_disaggregate(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, 
 /* One aggregation + disaggregation pass: F = aggregation of x and V = disaggregation
  * of G exactly as fmm_tucker_aggregate and fmm_tucker_disaggregate compute them (same
  * arithmetic, bitwise equal results), with the work of both stages interleaved in
- * longest-first work lists (streaming kernels: one launch; matrix-core path: four
- * grouped launches per chunk of right-hand sides).  F must not alias G, x or V. */
+ * longest-first work lists (streaming kernels: one persistent launch that takes the
+ * list's entries from a work counter; matrix-core path: four grouped launches per chunk
+ * of right-hand sides).  F must not alias G, x or V.  Passes of one handle and
+ * precision must not overlap in time (on different streams): they share the work
+ * counter, the partial sums and the multi-RHS scratch. */
 fmm_status fmm_tucker_pass(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F, const void* G,
                            void* V, void* stream);
 
@@ -327,17 +330,19 @@ fmm_status fmm_graph_capture(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid allocation): fmm_tucker_pass with the same
  * arguments, results and errors, computed by the streaming kernels (whatever the
- * route of fmm_tucker_pass for this nrhs) with the partial sums of split items in a
- * static device array of 64 MiB per GPU instead of a library allocation.  It calls no
- * hipMalloc, hipFree or allocating library routine.
+ * route of fmm_tucker_pass for this nrhs) with the pass kernel's work counter (first
+ * 256 bytes) and the partial sums of split items in a static device array of 64 MiB
+ * per GPU instead of library allocations.  It calls no hipMalloc, hipFree or
+ * allocating library routine.
  *   prec  FMM_C128 or FMM_C64 (the bf16 split precisions run only on the matrix-core
  *         path, whose tables the library allocates: FMM_ERR_UNSUPPORTED; so is a layout
  *         whose FP64 items exceed the streaming kernels' LDS).
  * FMM_ERR_SIZE when the split items' partial sums (their r_theta r_phi and n_beta
- * values per block, per right-hand side) exceed the array: fewer right-hand sides per
- * call, or no split items, fit.  Every call on one GPU shares that GPU's array, which
- * keeps the last call's contents (the kernels overwrite every block they read):
- * calls that overlap on one GPU, from two streams or two threads, race. */
+ * values per block, per right-hand side) exceed the array after the counter: fewer
+ * right-hand sides per call, or no split items, fit.  Every call on one GPU shares
+ * that GPU's array, which keeps the last call's contents (the kernels overwrite every
+ * block they read, and the counter is reset before each pass): calls that overlap on
+ * one GPU, from two streams or two threads, race. */
 fmm_status fmm_tucker_pass_noalloc(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, const void* x, void* F,
                                    const void* G, void* V, void* stream);
 

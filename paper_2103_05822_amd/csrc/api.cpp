@@ -356,9 +356,12 @@ fmm_status route_of(const PrecSlot& s, fmm_prec prec, int nrhs, Route* r) {
 // Drops a captured graph (it may point at tables or factors about to change).
 void drop_graph(fmm_tucker_t h);
 
-// Partial-sum buffer of the split items for nrhs right-hand sides (grown on demand;
-// a graph captured with the old buffer is dropped).
+// Work counter of the pass kernel (allocated once) and partial-sum buffer of the split
+// items for nrhs right-hand sides (grown on demand; a graph captured with the old
+// buffer is dropped).
 fmm_status ensure_part(fmm_tucker_t h, PrecSlot& s, fmm_prec prec, int nrhs) {
+  if (!s.next) TFMM_HIP(hipMalloc(&s.next, 256));
+  s.plan.next = s.next;
   if (s.plan.n_splits == 0) return FMM_OK;
   const size_t need = (size_t)s.plan.part_stride * nrhs * elem_bytes(prec);
   if (need > s.part_bytes) {
@@ -375,9 +378,12 @@ fmm_status ensure_part(fmm_tucker_t h, PrecSlot& s, fmm_prec prec, int nrhs) {
 
 void part_release(PrecSlot& s) {
   if (s.part) (void)hipFree(s.part);
+  if (s.next) (void)hipFree(s.next);
   s.part = nullptr;
   s.part_bytes = 0;
+  s.next = nullptr;
   s.plan.part = nullptr;
+  s.plan.next = nullptr;
 }
 
 // Launches one stage (0 aggregation, 1 disaggregation, 2 both) for a validated call.
@@ -690,6 +696,7 @@ extern "C" fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* are
   pl.n_splits = (int)P.splits.size();
   pl.part_stride = P.part_stride;
   pl.part = nullptr;
+  pl.next = sl.next;
   pl.n_items = (int)P.items.size();
   pl.n_basis = h->layout.n_basis();
   pl.factors = sl.arena + P.header_bytes;
@@ -754,14 +761,17 @@ fmm_status tuckfmm::noalloc_pass(fmm_tucker_t h, fmm_prec prec, int32_t nrhs, co
   Route r;
   if ((st = route_of(*s, prec, nrhs, &r)) != FMM_OK) return st;
   const Layout& L = h->layout;
-  TuckPlan pl = s->plan;  // the slot's own partial-sum buffer stays untouched
+  // the slot's own counter and partial-sum buffer stay untouched: the scratch holds the
+  // pass kernel's work counter in its first 256 bytes, then the partial sums
+  TuckPlan pl = s->plan;
+  pl.next = static_cast<int32_t*>(scratch);
   pl.part = nullptr;
   if (pl.n_splits > 0) {
     const size_t need = (size_t)pl.part_stride * (size_t)nrhs * elem_bytes(prec);
-    if (need > scratch_bytes)
+    if (need > scratch_bytes - 256)
       return fail(FMM_ERR_SIZE, "the split items' partial sums need %zu bytes for nrhs = %d, the static scratch "
-                                "holds %zu", need, nrhs, scratch_bytes);
-    pl.part = scratch;
+                                "holds %zu after the work counter", need, nrhs, scratch_bytes - 256);
+    pl.part = static_cast<char*>(scratch) + 256;
   }
   if (s->plan.n_zero_rows > 0)
     TFMM_HIP(launch_zero_rows(elem_bytes(prec), F, pl.zero_rows, pl.n_zero_rows, (int64_t)L.ndir() * nrhs, hs));

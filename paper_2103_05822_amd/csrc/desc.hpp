@@ -80,6 +80,7 @@ struct TuckPlan {
   int n_units = 0, n_splits = 0;
   int64_t part_stride = 0;  // partial-sum elements per right-hand side
   void* part = nullptr;     // library-owned partial sums (device), set per call
+  int32_t* next = nullptr;  // work counter of the pass kernel (device), set per call
   int n_items = 0;
   int64_t n_basis = 0;
   TuckMax mx{};

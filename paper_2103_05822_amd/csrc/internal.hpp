@@ -94,6 +94,7 @@ struct PrecSlot {
   std::vector<TuneChoice> tuned;
   void* part = nullptr;             // library-owned partial sums of split items (device)
   size_t part_bytes = 0;
+  int32_t* next = nullptr;          // library-owned work counter of the pass kernel (device)
 };
 
 // Multi-RHS path (mrhs_plan.cpp).

@@ -613,28 +613,40 @@ __global__ __launch_bounds__(NT) void tucker_dis_kernel(const typename Tr<T>::c*
 // One launch for a whole aggregation + disaggregation pass: work-list entry e is
 // the aggregation of unit e if e >= 0 and the disaggregation of unit ~e otherwise.
 // Both stages' units interleave in one longest-first list, so small units of either
-// stage fill the end of the launch.
+// stage fill the end of the launch.  The launch is persistent: as many workgroups as
+// the CUs hold at once, each taking the next entry (of n_list per right-hand side) from
+// the work counter `next`, which the V-zeroing kernel before it sets to zero.  On
+// layouts of many small units this keeps every CU full; with one workgroup per entry
+// the hardware refilled a CU's free slot only tens of microseconds after a unit ended.
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void tucker_pass_kernel(const typename Tr<T>::c* __restrict__ fac,
                                                          const TuckItem* __restrict__ items,
                                                          const TuckUnit* __restrict__ units,
                                                          const TuckSplit* __restrict__ splits,
-                                                         const int32_t* __restrict__ list, TuckMax mx, int n_theta,
-                                                         int n_phi, int nrhs,
+                                                         const int32_t* __restrict__ list, int n_list, TuckMax mx,
+                                                         int n_theta, int n_phi, int nrhs,
                                                          const typename Tr<T>::c* __restrict__ x,
                                                          typename Tr<T>::c* __restrict__ F,
                                                          const typename Tr<T>::c* __restrict__ G,
                                                          typename Tr<T>::c* __restrict__ V, typename Tr<T>::c* part,
-                                                         int64_t part_stride) {
+                                                         int64_t part_stride, int32_t* __restrict__ next) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int32_t e = list[blockIdx.x];
+  __shared__ int32_t take;
   const Lds<T> L(mx);
-  if (e >= 0)
-    agg_unit<T, NT>(fac, items, units[e], splits, L, smem, n_theta, n_phi, nrhs, blockIdx.y, x, F, part,
-                    part_stride);
-  else
-    dis_unit<T, NT>(fac, items, units[~e], splits, L, smem, n_theta, n_phi, nrhs, blockIdx.y, G, V, part,
-                    part_stride);
+  const int total = n_list * nrhs;
+  for (;;) {
+    if (threadIdx.x == 0) take = atomicAdd(next, 1);
+    __syncthreads();
+    const int i = take;
+    if (i >= total) break;  // uniform: every wavefront leaves
+    const int r = i / n_list;
+    const int32_t e = list[i - r * n_list];
+    if (e >= 0)
+      agg_unit<T, NT>(fac, items, units[e], splits, L, smem, n_theta, n_phi, nrhs, r, x, F, part, part_stride);
+    else
+      dis_unit<T, NT>(fac, items, units[~e], splits, L, smem, n_theta, n_phi, nrhs, r, G, V, part, part_stride);
+    __syncthreads();  // the unit's last LDS reads and `take` are done before the next entry
+  }
 }
 
 // Finishing kernel of the split items, after the units: blocks [0, n_agg) sum the
@@ -686,16 +698,18 @@ __global__ __launch_bounds__(NT) void tucker_finish_kernel(const typename Tr<T>:
   }
 }
 
+// v[0 .. n) = 0; with `counter`, also the pass kernel's work counter.
 template <typename C>
-__global__ __launch_bounds__(256) void zero_kernel(C* __restrict__ v, int64_t n) {
+__global__ __launch_bounds__(256) void zero_kernel(C* __restrict__ v, int64_t n, int32_t* __restrict__ counter) {
+  if (counter && blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) v[i] = czero<C>();
 }
 
 template <typename C>
-hipError_t zero(C* v, int64_t n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(zero_kernel<C>, dim3((unsigned)blocks), dim3(256), 0, s, v, n);
+hipError_t zero(C* v, int64_t n, hipStream_t s, int32_t* counter = nullptr) {
+  if (n <= 0 && !counter) return hipSuccess;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+  hipLaunchKernelGGL(zero_kernel<C>, dim3((unsigned)blocks), dim3(256), 0, s, v, n, counter);
   return hipGetLastError();
 }
 
@@ -815,15 +829,25 @@ hipError_t launch_tucker_pass(const TuckPlan& pl, int threads, int n_theta, int 
   using C = typename Tr<T>::c;
   if (threads != 64 && threads != 128 && threads != 256 && threads != 512) return hipErrorInvalidValue;
   if (pl.n_splits > 0 && pl.part == nullptr) return hipErrorInvalidValue;
-  hipError_t e = zero(static_cast<C*>(V), pl.n_basis * nrhs, s);
+  if (pl.next == nullptr) return hipErrorInvalidValue;
+  hipError_t e = zero(static_cast<C*>(V), pl.n_basis * nrhs, s, pl.next);
   if (e != hipSuccess || pl.n_units == 0) return e;
+  const int n_list = 2 * pl.n_units;
+  const size_t lds = Lds<T>(pl.mx).bytes();
+  int dev = 0, n_cu = 0, per_cu = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  TFMM_NT_SWITCH(threads, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                              &per_cu, reinterpret_cast<const void*>(&tucker_pass_kernel<T, NT>), NT, lds))
+  if (e != hipSuccess) return e;
+  // persistent grid: the workgroups resident at once, at most one per entry
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((int64_t)n_list * nrhs, (int64_t)per_cu * n_cu));
   TFMM_NT_SWITCH(threads,
-                 hipLaunchKernelGGL((tucker_pass_kernel<T, NT>), dim3(2 * pl.n_units, nrhs), dim3(NT),
-                                    Lds<T>(pl.mx).bytes(), s, static_cast<const C*>(pl.factors), pl.items,
-                                    pl.units, pl.splits, pl.pass_list, pl.mx, n_theta, n_phi, nrhs,
-                                    static_cast<const C*>(x),
+                 hipLaunchKernelGGL((tucker_pass_kernel<T, NT>), dim3((unsigned)blocks), dim3(NT), lds, s,
+                                    static_cast<const C*>(pl.factors), pl.items, pl.units, pl.splits, pl.pass_list,
+                                    n_list, pl.mx, n_theta, n_phi, nrhs, static_cast<const C*>(x),
                                     static_cast<C*>(F), static_cast<const C*>(G), static_cast<C*>(V),
-                                    static_cast<C*>(pl.part), pl.part_stride))
+                                    static_cast<C*>(pl.part), pl.part_stride, pl.next))
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_finish<T>(pl, threads, pl.n_splits, pl.n_splits, n_theta, n_phi, nrhs, F, V, s);
