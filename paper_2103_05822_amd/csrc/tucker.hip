@@ -578,32 +578,20 @@ __device__ __forceinline__ void dis_unit(const typename Tr<T>::c* __restrict__ f
   dis_stream<T, NT>(fac, it, L, smem, nrhs, r, u.b0, u.b1, dst, V);
 }
 
-// The stages alone: persistent launches over the longest-first unit list `order`
-// (n_list units per right-hand side), like the pass kernel below.
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void tucker_agg_kernel(const typename Tr<T>::c* __restrict__ fac,
                                                         const TuckItem* __restrict__ items,
                                                         const TuckUnit* __restrict__ units,
                                                         const TuckSplit* __restrict__ splits,
-                                                        const int32_t* __restrict__ order, int n_list, TuckMax mx,
-                                                        int n_theta, int n_phi, int nrhs,
+                                                        const int32_t* __restrict__ order, TuckMax mx, int n_theta,
+                                                        int n_phi, int nrhs,
                                                         const typename Tr<T>::c* __restrict__ x,
                                                         typename Tr<T>::c* __restrict__ F, typename Tr<T>::c* part,
-                                                        int64_t part_stride, int32_t* __restrict__ next) {
+                                                        int64_t part_stride) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int32_t take;
-  const Lds<T> L(mx);
-  const int total = n_list * nrhs;
-  for (;;) {
-    if (threadIdx.x == 0) take = atomicAdd(next, 1);
-    __syncthreads();
-    const int i = take;
-    if (i >= total) break;  // uniform
-    const int r = i / n_list;
-    agg_unit<T, NT>(fac, items, units[order[i - r * n_list]], splits, L, smem, n_theta, n_phi, nrhs, r, x, F, part,
-                    part_stride);
-    __syncthreads();
-  }
+  const TuckUnit u = units[order[blockIdx.x]];
+  agg_unit<T, NT>(fac, items, u, splits, Lds<T>(mx), smem, n_theta, n_phi, nrhs, blockIdx.y, x, F,
+                  part, part_stride);
 }
 
 template <typename T, int NT>
@@ -611,25 +599,15 @@ __global__ __launch_bounds__(NT) void tucker_dis_kernel(const typename Tr<T>::c*
                                                         const TuckItem* __restrict__ items,
                                                         const TuckUnit* __restrict__ units,
                                                         const TuckSplit* __restrict__ splits,
-                                                        const int32_t* __restrict__ order, int n_list, TuckMax mx,
-                                                        int n_theta, int n_phi, int nrhs,
+                                                        const int32_t* __restrict__ order, TuckMax mx, int n_theta,
+                                                        int n_phi, int nrhs,
                                                         const typename Tr<T>::c* __restrict__ G,
                                                         typename Tr<T>::c* __restrict__ V, typename Tr<T>::c* part,
-                                                        int64_t part_stride, int32_t* __restrict__ next) {
+                                                        int64_t part_stride) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int32_t take;
-  const Lds<T> L(mx);
-  const int total = n_list * nrhs;
-  for (;;) {
-    if (threadIdx.x == 0) take = atomicAdd(next, 1);
-    __syncthreads();
-    const int i = take;
-    if (i >= total) break;  // uniform
-    const int r = i / n_list;
-    dis_unit<T, NT>(fac, items, units[order[i - r * n_list]], splits, L, smem, n_theta, n_phi, nrhs, r, G, V, part,
-                    part_stride);
-    __syncthreads();
-  }
+  const TuckUnit u = units[order[blockIdx.x]];
+  dis_unit<T, NT>(fac, items, u, splits, Lds<T>(mx), smem, n_theta, n_phi, nrhs, blockIdx.y, G, V,
+                  part, part_stride);
 }
 
 // One launch for a whole aggregation + disaggregation pass: work-list entry e is
@@ -828,22 +806,15 @@ template <typename T>
 hipError_t launch_tucker_agg(const TuckPlan& pl, int threads, int n_theta, int n_phi, int nrhs, const void* x,
                              void* F, hipStream_t s) {
   using C = typename Tr<T>::c;
-  if (threads != 64 && threads != 128 && threads != 256 && threads != 512) return hipErrorInvalidValue;
   if (pl.n_units == 0) return hipSuccess;
   if (pl.n_splits > 0 && pl.part == nullptr) return hipErrorInvalidValue;
-  if (pl.next == nullptr) return hipErrorInvalidValue;
-  hipError_t e = zero<C>(nullptr, 0, s, pl.next);  // the work counter
-  if (e != hipSuccess) return e;
-  const size_t lds = Lds<T>(pl.mx).agg_bytes();
-  unsigned blocks = 0;
-  TFMM_NT_SWITCH(threads, e = persistent_grid(&tucker_agg_kernel<T, NT>, NT, lds, (int64_t)pl.n_units * nrhs, &blocks))
-  if (e != hipSuccess) return e;
   TFMM_NT_SWITCH(threads,
-                 hipLaunchKernelGGL((tucker_agg_kernel<T, NT>), dim3(blocks), dim3(NT), lds, s,
-                                    static_cast<const C*>(pl.factors), pl.items, pl.units, pl.splits, pl.order,
-                                    pl.n_units, pl.mx, n_theta, n_phi, nrhs, static_cast<const C*>(x),
-                                    static_cast<C*>(F), static_cast<C*>(pl.part), pl.part_stride, pl.next))
-  e = hipGetLastError();
+                 hipLaunchKernelGGL((tucker_agg_kernel<T, NT>), dim3(pl.n_units, nrhs), dim3(NT),
+                                    Lds<T>(pl.mx).agg_bytes(), s, static_cast<const C*>(pl.factors), pl.items,
+                                    pl.units, pl.splits, pl.order, pl.mx, n_theta, n_phi, nrhs,
+                                    static_cast<const C*>(x), static_cast<C*>(F), static_cast<C*>(pl.part),
+                                    pl.part_stride))
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_finish<T>(pl, threads, pl.n_splits, 0, n_theta, n_phi, nrhs, F, nullptr, s);
 }
@@ -854,18 +825,14 @@ hipError_t launch_tucker_disagg(const TuckPlan& pl, int threads, int n_theta, in
   using C = typename Tr<T>::c;
   if (threads != 64 && threads != 128 && threads != 256 && threads != 512) return hipErrorInvalidValue;
   if (pl.n_splits > 0 && pl.part == nullptr) return hipErrorInvalidValue;
-  if (pl.next == nullptr) return hipErrorInvalidValue;
-  hipError_t e = zero(static_cast<C*>(V), pl.n_basis * nrhs, s, pl.next);
+  hipError_t e = zero(static_cast<C*>(V), pl.n_basis * nrhs, s);
   if (e != hipSuccess || pl.n_units == 0) return e;
-  const size_t lds = Lds<T>(pl.mx).dis_bytes();
-  unsigned blocks = 0;
-  TFMM_NT_SWITCH(threads, e = persistent_grid(&tucker_dis_kernel<T, NT>, NT, lds, (int64_t)pl.n_units * nrhs, &blocks))
-  if (e != hipSuccess) return e;
   TFMM_NT_SWITCH(threads,
-                 hipLaunchKernelGGL((tucker_dis_kernel<T, NT>), dim3(blocks), dim3(NT), lds, s,
-                                    static_cast<const C*>(pl.factors), pl.items, pl.units, pl.splits, pl.order,
-                                    pl.n_units, pl.mx, n_theta, n_phi, nrhs, static_cast<const C*>(G),
-                                    static_cast<C*>(V), static_cast<C*>(pl.part), pl.part_stride, pl.next))
+                 hipLaunchKernelGGL((tucker_dis_kernel<T, NT>), dim3(pl.n_units, nrhs), dim3(NT),
+                                    Lds<T>(pl.mx).dis_bytes(), s, static_cast<const C*>(pl.factors), pl.items,
+                                    pl.units, pl.splits, pl.order, pl.mx, n_theta, n_phi, nrhs,
+                                    static_cast<const C*>(G), static_cast<C*>(V), static_cast<C*>(pl.part),
+                                    pl.part_stride))
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_finish<T>(pl, threads, 0, pl.n_splits, n_theta, n_phi, nrhs, nullptr, V, s);
