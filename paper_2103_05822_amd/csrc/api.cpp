@@ -113,6 +113,9 @@ constexpr double kSplitMin = 65536.0;
 constexpr double kSplitUnits = 512.0;
 constexpr int kSplitMinRows = 4;
 
+// Largest workgroup LDS with which the streaming kernels stage the angular operands.
+constexpr size_t kStageLdsMax = 160 * 1024;
+
 double split_elems(const std::vector<TuckItem>& items) {
   if (const char* env = std::getenv("TUCKFMM_SPLIT_ELEMS")) {
     const double v = std::atof(env);
@@ -177,6 +180,17 @@ fmm_status plan_arena(const fmm_tucker_s* h, fmm_prec prec, ArenaPlan* P) {
                    : es * ((size_t)it.rt * it.rp * it.rb + (size_t)L.n_theta * it.rt + (size_t)L.n_phi * it.rp +
                            (size_t)it.nb * it.rb);
     }
+  }
+  mx.nt = L.n_theta;
+  mx.np = L.n_phi;
+  {
+    // the angular products read their factors (and the disaggregation G) from LDS
+    // when the staged workgroup LDS fits
+    TuckMax ms = mx;
+    ms.stage = 1;
+    const size_t staged = prec == FMM_C128 ? tucker_lds_bytes<double>(ms) : tucker_lds_bytes<float>(ms);
+    mx.stage = staged <= kStageLdsMax ? 1 : 0;
+    if (const char* env = std::getenv("TUCKFMM_STAGE_ANGULAR")) mx.stage = mx.stage && std::atoi(env) != 0;
   }
   P->mx = mx;
   // work units: whole items, or row blocks of the items above the split size

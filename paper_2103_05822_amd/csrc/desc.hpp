@@ -57,7 +57,9 @@ static_assert(sizeof(TuckSplit) == 32, "TuckSplit layout");
 // Maxima over all items of a precision slot; they size the kernels' LDS.
 struct TuckMax {
   int32_t nb, rt, rp, rb, q;
-  int32_t t3;   // max of n_theta*r_phi or r_theta*n_phi intermediate
+  int32_t t3;      // max of n_theta*r_phi or r_theta*n_phi intermediate
+  int32_t nt, np;  // the direction grid n_theta x n_phi
+  int32_t stage;   // 1: the angular products read their factors (and G) from LDS
 };
 
 // Device pointers and sizes of one uploaded precision.

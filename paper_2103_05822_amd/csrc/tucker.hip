@@ -71,11 +71,12 @@ __device__ __forceinline__ P ldnt(const P* p) {
 
 // LDS regions (complex elements).
 // Aggregation:    r1 = x (n_beta), later t (r_theta r_phi);  r2 = y (r_beta), later
-//                 the angular intermediate.
-// Disaggregation: s1 = angular intermediate, S (r_theta r_phi), s (r_beta).
+//                 the angular intermediate; with staging, sa = U^theta and U^phi^T.
+// Disaggregation: s1 = angular intermediate, S (r_theta r_phi), s (r_beta); with
+//                 staging, sd = conj(G) of the item and one angular factor at a time.
 template <typename T>
 struct Lds {
-  int r1, r2, s1, s2, s3;
+  int r1, r2, s1, s2, s3, sa, sd;
   __host__ __device__ explicit Lds(const TuckMax& mx) {
     constexpr int E = Tr<T>::E;
     r1 = round_up(max(round_up(mx.nb, E), round_up(mx.q, E)), 2);
@@ -83,9 +84,11 @@ struct Lds {
     s1 = round_up(mx.t3, 2);
     s2 = round_up(round_up(mx.q, E), 2);
     s3 = round_up(mx.rb, 2);
+    sa = mx.stage ? round_up(mx.nt * mx.rt, 2) + round_up(mx.np * mx.rp, 2) : 0;
+    sd = mx.stage ? round_up(mx.nt * mx.np, 2) + round_up(max(mx.nt * mx.rt, mx.np * mx.rp), 2) : 0;
   }
-  __host__ __device__ size_t agg_bytes() const { return size_t(r1 + r2) * sizeof(typename Tr<T>::c); }
-  __host__ __device__ size_t dis_bytes() const { return size_t(s1 + s2 + s3) * sizeof(typename Tr<T>::c); }
+  __host__ __device__ size_t agg_bytes() const { return size_t(r1 + r2 + sa) * sizeof(typename Tr<T>::c); }
+  __host__ __device__ size_t dis_bytes() const { return size_t(s1 + s2 + s3 + sd) * sizeof(typename Tr<T>::c); }
   __host__ __device__ size_t bytes() const { return agg_bytes() > dis_bytes() ? agg_bytes() : dis_bytes(); }
 };
 
@@ -396,25 +399,13 @@ __device__ __forceinline__ void agg_stream(const typename Tr<T>::c* __restrict__
   }
 }
 
-// Angular phase: F = U^theta t U^phi^T from t in LDS (`ts`); the intermediate uses
-// LDS region r2.
-template <typename T, int NT>
-__device__ __forceinline__ void agg_angular(const typename Tr<T>::c* __restrict__ fac, const TuckItem& it,
-                                            const Lds<T>& L, unsigned char* smem, const typename Tr<T>::c* ts,
-                                            int n_theta, int n_phi, int nrhs, int r,
-                                            typename Tr<T>::c* __restrict__ F) {
-  using C = typename Tr<T>::c;
-  C* t3 = reinterpret_cast<C*>(smem) + L.r1;
-  const int tid = threadIdx.x;
+// The two angular products of the aggregation, F = U^theta t U^phi^T, with the
+// factors at `ut` [n_theta][r_theta] and `upt` [r_phi][n_phi] (global memory or LDS).
+template <typename C, int NT>
+__device__ __forceinline__ void agg_angular_products(const TuckItem& it, int n_theta, int n_phi, int nrhs,
+                                                     const C* ts, C* t3, const C* ut, const C* upt, C* Fo,
+                                                     int tid) {
   const int rt = it.rt, rp = it.rp;
-  const C* ut = fac + it.off_ut;    // [n_theta][rt]
-  const C* upt = fac + it.off_upt;  // [rp][n_phi]
-  const int ndir = n_theta * n_phi;
-  C* Fo = F + ((int64_t)it.frow * ndir) * nrhs + r;
-  if (it.ident) {  // truncated-SVD item: t already holds the directions
-    for (int i = tid; i < ndir; i += NT) Fo[(int64_t)i * nrhs] = ts[i];
-    return;
-  }
   if (it.theta_first) {
     // t3[i][c] = sum_a U^theta[i][a] t[a][c]           (n_theta x r_phi)
     tile_product<C, NT>(
@@ -437,6 +428,39 @@ __device__ __forceinline__ void agg_angular(const typename Tr<T>::c* __restrict_
         n_theta, n_phi, rt, [&](int i, int a) { return ut[i * rt + a]; },
         [&](int a, int j) { return t3[a * n_phi + j]; },
         [&](int i, int j, C v) { Fo[(int64_t)(i * n_phi + j) * nrhs] = v; }, tid);
+  }
+}
+
+// Angular phase: F = U^theta t U^phi^T from t in LDS (`ts`); the intermediate uses
+// LDS region r2.
+template <typename T, int NT>
+__device__ __forceinline__ void agg_angular(const typename Tr<T>::c* __restrict__ fac, const TuckItem& it,
+                                            const Lds<T>& L, unsigned char* smem, const typename Tr<T>::c* ts,
+                                            int n_theta, int n_phi, int nrhs, int r,
+                                            typename Tr<T>::c* __restrict__ F) {
+  using C = typename Tr<T>::c;
+  C* t3 = reinterpret_cast<C*>(smem) + L.r1;
+  const int tid = threadIdx.x;
+  const int rt = it.rt, rp = it.rp;
+  const C* ut = fac + it.off_ut;    // [n_theta][rt]
+  const C* upt = fac + it.off_upt;  // [rp][n_phi]
+  const int ndir = n_theta * n_phi;
+  C* Fo = F + ((int64_t)it.frow * ndir) * nrhs + r;
+  if (it.ident) {  // truncated-SVD item: t already holds the directions
+    for (int i = tid; i < ndir; i += NT) Fo[(int64_t)i * nrhs] = ts[i];
+    return;
+  }
+  if (L.sa) {
+    // the factors into LDS (one load latency for both) after the r1 and r2 regions:
+    // the products then take one LDS access per K step instead of a memory latency
+    C* s_ut = reinterpret_cast<C*>(smem) + L.r1 + L.r2;
+    C* s_upt = s_ut + round_up(n_theta * rt, 2);
+    for (int q = tid; q < n_theta * rt; q += NT) s_ut[q] = ut[q];
+    for (int q = tid; q < rp * n_phi; q += NT) s_upt[q] = upt[q];
+    __syncthreads();
+    agg_angular_products<C, NT>(it, n_theta, n_phi, nrhs, ts, t3, s_ut, s_upt, Fo, tid);
+  } else {
+    agg_angular_products<C, NT>(it, n_theta, n_phi, nrhs, ts, t3, ut, upt, Fo, tid);
   }
 }
 
@@ -463,6 +487,37 @@ __device__ __forceinline__ void dis_angular(const typename Tr<T>::c* __restrict_
   // the angular order mirrors the aggregation choice
   if (it.ident) {  // truncated-SVD item: S2 is conj(G) itself
     for (int q = tid; q < Q; q += NT) S2[q] = conjc(Gi[(int64_t)q * nrhs]);
+  } else if (L.sd) {
+    // conj(G) and the first product's factor into LDS after the s regions (one load
+    // latency), then the second product's factor in their place
+    C* gs = reinterpret_cast<C*>(smem) + L.s1 + L.s2 + L.s3;
+    C* fs = gs + round_up(ndir, 2);
+    for (int q = tid; q < ndir; q += NT) gs[q] = conjc(Gi[(int64_t)q * nrhs]);
+    if (!it.theta_first) {
+      for (int q = tid; q < n_theta * rt; q += NT) fs[q] = ut[q];
+      __syncthreads();
+      tile_product<C, NT>(
+          rt, n_phi, n_theta, [&](int a, int i) { return fs[i * rt + a]; },
+          [&](int i, int j) { return gs[i * n_phi + j]; }, [&](int a, int j, C v) { s1[a * n_phi + j] = v; }, tid);
+      __syncthreads();
+      for (int q = tid; q < n_phi * rp; q += NT) gs[q] = up[q];
+      __syncthreads();
+      tile_product<C, NT>(
+          rt, rp, n_phi, [&](int a, int j) { return s1[a * n_phi + j]; }, [&](int j, int c) { return gs[j * rp + c]; },
+          [&](int a, int c, C v) { S2[a * rp + c] = v; }, tid);
+    } else {
+      for (int q = tid; q < n_phi * rp; q += NT) fs[q] = up[q];
+      __syncthreads();
+      tile_product<C, NT>(
+          n_theta, rp, n_phi, [&](int i, int j) { return gs[i * n_phi + j]; },
+          [&](int j, int c) { return fs[j * rp + c]; }, [&](int i, int c, C v) { s1[i * rp + c] = v; }, tid);
+      __syncthreads();
+      for (int q = tid; q < n_theta * rt; q += NT) gs[q] = ut[q];
+      __syncthreads();
+      tile_product<C, NT>(
+          rt, rp, n_theta, [&](int a, int i) { return gs[i * rt + a]; }, [&](int i, int c) { return s1[i * rp + c]; },
+          [&](int a, int c, C v) { S2[a * rp + c] = v; }, tid);
+    }
   } else if (!it.theta_first) {
     // s1[a][j] = sum_i U^theta[i][a] conj(G[i][j])     (r_theta x n_phi)
     tile_product<C, NT>(
