@@ -113,8 +113,10 @@ constexpr double kSplitMin = 65536.0;
 constexpr double kSplitUnits = 512.0;
 constexpr int kSplitMinRows = 4;
 
-// Largest workgroup LDS with which the streaming kernels stage the angular operands.
-constexpr size_t kStageLdsMax = 160 * 1024;
+// LDS of one CU (gfx950), and the fewest wavefronts per CU with which the streaming
+// kernels stage the angular operands in LDS.
+constexpr size_t kCuLds = 160 * 1024;
+constexpr int kStageMinWaves = 8;
 
 double split_elems(const std::vector<TuckItem>& items) {
   if (const char* env = std::getenv("TUCKFMM_SPLIT_ELEMS")) {
@@ -183,15 +185,7 @@ fmm_status plan_arena(const fmm_tucker_s* h, fmm_prec prec, ArenaPlan* P) {
   }
   mx.nt = L.n_theta;
   mx.np = L.n_phi;
-  {
-    // the angular products read their factors (and the disaggregation G) from LDS
-    // when the staged workgroup LDS fits
-    TuckMax ms = mx;
-    ms.stage = 1;
-    const size_t staged = prec == FMM_C128 ? tucker_lds_bytes<double>(ms) : tucker_lds_bytes<float>(ms);
-    mx.stage = staged <= kStageLdsMax ? 1 : 0;
-    if (const char* env = std::getenv("TUCKFMM_STAGE_ANGULAR")) mx.stage = mx.stage && std::atoi(env) != 0;
-  }
+  mx.stage = 0;  // decided at upload, with the workgroup size
   P->mx = mx;
   // work units: whole items, or row blocks of the items above the split size
   const double split = split_elems(P->items);
@@ -684,9 +678,23 @@ extern "C" fmm_status fmm_tucker_upload(fmm_tucker_t h, fmm_prec prec, void* are
     double c = 0.0;
     for (const TuckUnit& u : P.units) c += item_cost(P.items[u.item]) * (u.b1 - u.b0) / P.items[u.item].rb;
     c /= std::max<size_t>(1, P.units.size());
-    // (measured on MI355X: mean 12k elements runs best at 64 threads, 50k at 128,
-    // 258k at 256, 1.7M at 512)
-    sl.threads = c >= 1.5e6 ? 512 : (c >= 1e5 ? 256 : (c >= 3e4 ? 128 : 64));
+    // (measured on MI355X, FP32 pass.  Angular operands read from memory: mean 12k
+    // elements runs best at 64 threads, 50k at 128, 258k at 256, 1.7M at 512.  Staged
+    // in LDS, the shorter angular phases favour wider workgroups: 12k and 50k at 128,
+    // 258k at 512.)
+    const int t_plain = c >= 1.5e6 ? 512 : (c >= 1e5 ? 256 : (c >= 3e4 ? 128 : 64));
+    const int t_staged = c >= 1e5 ? 512 : (c >= 5e3 ? 128 : 64);
+    // Staging the angular operands (and G) in LDS shortens the angular phases but
+    // takes LDS from the resident workgroups: it pays while a CU still holds
+    // kStageMinWaves wavefronts (FP64 at 1-lambda boxes, 4 wavefronts staged, ran
+    // 1.24 ms unstaged and 1.59 ms staged; every layout with 8 or more gained).
+    TuckMax ms = P.mx;
+    ms.stage = 1;
+    const size_t staged = prec == FMM_C128 ? tucker_lds_bytes<double>(ms) : tucker_lds_bytes<float>(ms);
+    const int waves = staged > kCuLds ? 0 : (int)(kCuLds / staged) * (t_staged / 64);
+    P.mx.stage = staged <= (size_t)lds_lim && waves >= kStageMinWaves ? 1 : 0;
+    if (const char* env = std::getenv("TUCKFMM_STAGE_ANGULAR")) P.mx.stage = P.mx.stage && std::atoi(env) != 0;
+    sl.threads = P.mx.stage ? t_staged : t_plain;
     if (const char* env = std::getenv("TUCKFMM_STREAM_THREADS")) {
       const int v = std::atoi(env);
       if (v == 64 || v == 128 || v == 256 || v == 512) sl.threads = v;
