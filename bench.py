@@ -51,7 +51,8 @@ def parse():
                    choices=["sphere30", "sphere30g29", "sphere6", "small", "sphere20b0.5", "sphere20b1", "sphere20b2",
                             "sphere20b4", "sphere45", "trihedral", "trihedral_small"])
     p.add_argument("--sample-groups", type=int, default=6, help="groups checked against the oracle")
-    p.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU timing")
+    p.add_argument("--cpu-seconds", type=float, default=12.0,
+                   help="budget of the oracle CPU timing (0: no CPU baseline)")
     p.add_argument("--no-oracle", action="store_true", help="skip accuracy sampling and the CPU baseline")
     p.add_argument("--no-dense", action="store_true", help="Tucker stages only (profiling runs)")
     p.add_argument("--nrhs", type=int, default=None,
@@ -862,7 +863,11 @@ def oracle_checks(args, w, verts, tris, lay, x, gin, F32h, V32h, F64h, V64h, sam
     assert np.array_equal(P.offsets, lay.offsets)
     nb = P.group_sizes()
     off = P.offsets
-    blocks = {g: ff.farfield_group(P, g) for g in sample}
+    blocks = {}
+    for i, g in enumerate(sample):
+        blocks[g] = ff.farfield_group(P, g)
+        if (i + 1) % 8 == 0 or i + 1 == len(sample):
+            log("oracle: far-fields of %d of %d sampled groups" % (i + 1, len(sample)))
     c64 = lambda a: np.asarray(a).astype(np.complex64).astype(np.complex128)   # noqa: E731
 
     def err(got_by_g, ref_by_g):
@@ -928,13 +933,19 @@ def oracle_checks(args, w, verts, tris, lay, x, gin, F32h, V32h, F64h, V64h, sam
            "rel_err_sample_groups": [int(g) for g in sample]}
     log("errors vs oracle (end to end): %s" % e2e)
     log("errors vs oracle (arithmetic only): %s" % arith)
+    if args.cpu_seconds <= 0:
+        return out
 
     # Oracle throughput.  The sampled groups alone (tens of MB) would sit in the host's
     # last-level cache, so the timing sample is a contiguous run of groups whose FP64
     # factors total >= 2 GB, with seeded random factors of the ranks the oracle's own
     # HOSVD gives on the sampled groups (values do not change the arithmetic).
-    rk = np.array([[H.hosvd(H.tensorize(blocks[g], a), w.gamma)[0].shape for a in range(2)] for g in sample])
-    rk = rk.reshape(-1, 3)
+    rk = []
+    for g in sample:
+        for a in range(2):
+            rk.append(H.hosvd(H.tensorize(blocks[g], a), w.gamma)[0].shape)
+        log("cpu baseline: oracle HOSVD ranks of group %d: %s" % (g, rk[-2:]))
+    rk = np.array(rk)
     rt_m, rp_m = int(round(rk[:, 0].mean())), int(round(rk[:, 1].mean()))
     rb_frac = float(np.mean(rk[:, 2] / np.repeat(nb[sample], 2)))
     frng = synth.rng(5)
