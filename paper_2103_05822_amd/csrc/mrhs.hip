@@ -72,11 +72,13 @@ __device__ __forceinline__ C2* base_ptr(const CGemmBases& b, int i) {
 //   A  K-contiguous: row t / 4, K quad t % 4;   M-contiguous: row t % 64, K quad t / 64
 //   B  column t % 64, K quad t / 64
 // so that a step's piece of an operand is written to LDS as whole 16-byte chunks.
-// Each thread keeps a pointer to its quad that advances by one step per K step; an
-// element outside the product (row beyond M, column beyond N, K beyond the last
-// step's tail) is read from a clamp address inside the operand instead and zeroed
-// when the step is written to LDS.  Nothing consumes the loaded values before that
-// point, so the loads stay in flight while the previous step runs on the matrix cores.
+// Each thread keeps a pointer to its quad that advances by one step per K step; a
+// row beyond M or a column beyond N reads the operand's first elements instead.  In
+// the step that holds the K tail, every element outside the product (row beyond M,
+// column beyond N, K beyond the tail) is read from such a clamp address and zeroed
+// when the step is written to LDS; the steps before it mask nothing (see load_stage).
+// Nothing consumes the loaded values before that point, so the loads stay in flight
+// while the previous step runs on the matrix cores.
 template <typename C2>
 struct Stage {
   C2 a[4];
@@ -132,45 +134,61 @@ __device__ __forceinline__ void walk_block(const CGemm& p, int n0, int tid, Walk
 // read as two 16-byte pairs.  A pair whose first element is valid is read whole; at
 // an odd K its second element is the row's zero padding (factor rows are padded to
 // an even length) and is masked.  (A complex128 element is a 16-byte load by itself.)
-template <bool AVEC, typename C2>
+// FULL (uniform): the step lies inside K (k0 + 16 <= K).  Then no element is masked:
+// a row beyond M or a column beyond N reads the operand's first elements (valid, as
+// K >= 16) and only feeds accumulator rows or columns that the epilogue never stores,
+// so the step needs no per-element selects.  Only the step holding the K tail masks.
+template <bool AVEC, bool FULL, typename C2>
 __device__ __forceinline__ void load_stage(const CGemm& p, int k0, Walk<C2>& w, Stage<C2>& st) {
-  const int na = w.arow ? min(4, max(0, p.K - k0 - 4 * w.aq)) : 0;
-  const int nb = w.bcol ? min(4, max(0, p.K - k0 - 4 * w.bq)) : 0;
-  const C2* pa = na > 0 ? w.a : w.clampa;
+  int na = 4, nb = 4;
+  if constexpr (!FULL) {
+    na = w.arow ? min(4, max(0, p.K - k0 - 4 * w.aq)) : 0;
+    nb = w.bcol ? min(4, max(0, p.K - k0 - 4 * w.bq)) : 0;
+  }
+  const C2* pa = FULL || na > 0 ? w.a : w.clampa;
   if constexpr (AVEC) {
     static_assert(sizeof(C2) == 8, "paired loads are for complex64");
     const float4 u = *reinterpret_cast<const float4*>(pa);
-    const float4 v = *reinterpret_cast<const float4*>(pa + (na > 2 ? 2 : 0));
+    const float4 v = *reinterpret_cast<const float4*>(pa + (FULL || na > 2 ? 2 : 0));
     st.a[0] = make_float2(u.x, u.y);
     st.a[1] = make_float2(u.z, u.w);
     st.a[2] = make_float2(v.x, v.y);
     st.a[3] = make_float2(v.z, v.w);
   } else {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) st.a[e] = pa[e < na ? e * w.aes : 0];
+    for (int e = 0; e < 4; ++e) st.a[e] = pa[FULL || e < na ? e * w.aes : 0];
   }
-  const C2* pb = nb > 0 ? w.b : w.clampb;
+  const C2* pb = FULL || nb > 0 ? w.b : w.clampb;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) st.b[e] = pb[e < nb ? e * w.bes : 0];
+  for (int e = 0; e < 4; ++e) st.b[e] = pb[FULL || e < nb ? e * w.bes : 0];
   st.na = na;
   st.nb = nb;
   w.a += w.astep;
   w.b += w.bstep;
 }
 
-// Element e of the stage's A (B) values with invalid elements zeroed and the
-// conjugation flag applied -- the point where the loads are waited for.
-template <typename C2>
-__device__ __forceinline__ C2 a_val(const CGemm& p, const Stage<C2>& st, int e) {
-  C2 v = e < st.na ? st.a[e] : czero<C2>();
-  if (p.flags & kConjA) v.y = -v.y;
+// Conjugation flips the sign bit of the imaginary part: conj is 0 or 0x80000000,
+// uniform per product (one XOR, no select).
+__device__ __forceinline__ float flip_sign(float v, uint32_t conj) { return __uint_as_float(__float_as_uint(v) ^ conj); }
+__device__ __forceinline__ double flip_sign(double v, uint32_t conj) {
+  return __longlong_as_double(__double_as_longlong(v) ^ (long long)((uint64_t)conj << 32));
+}
+
+__device__ __forceinline__ uint32_t conj_mask(const CGemm& p, int flag) { return (p.flags & flag) ? 0x80000000u : 0u; }
+
+// Element e of the stage's A (B) values with invalid elements zeroed (not in a FULL
+// step) and the conjugation applied -- the point where the loads are waited for.
+template <bool FULL, typename C2>
+__device__ __forceinline__ C2 a_val(const Stage<C2>& st, int e, uint32_t conj) {
+  C2 v = FULL || e < st.na ? st.a[e] : czero<C2>();
+  v.y = flip_sign(v.y, conj);
   return v;
 }
 
-template <typename C2>
-__device__ __forceinline__ C2 b_val(const CGemm& p, const Stage<C2>& st, int e) {
-  C2 v = e < st.nb ? st.b[e] : czero<C2>();
-  if (p.flags & kConjB) v.y = -v.y;
+template <bool FULL, typename C2>
+__device__ __forceinline__ C2 b_val(const Stage<C2>& st, int e, uint32_t conj) {
+  C2 v = FULL || e < st.nb ? st.b[e] : czero<C2>();
+  v.y = flip_sign(v.y, conj);
   return v;
 }
 
@@ -196,17 +214,20 @@ struct LdsF32 {
   float2 b[kKC * kXS];
 };
 
-__device__ __forceinline__ void store_f32(const CGemm& p, const Stage<float2>& st, LdsF32& L, int tid) {
+template <bool FULL>
+__device__ __forceinline__ void store_f32(const CGemm& p, const Stage<float2>& st, LdsF32& L, int tid, uint32_t ca,
+                                          uint32_t cb) {
   int m, kq;
   a_slot(p, tid, m, kq);
   float2* da = &L.a[m * kAS + 4 * kq];
-  const float2 a0 = a_val(p, st, 0), a1 = a_val(p, st, 1), a2 = a_val(p, st, 2), a3 = a_val(p, st, 3);
+  const float2 a0 = a_val<FULL>(st, 0, ca), a1 = a_val<FULL>(st, 1, ca), a2 = a_val<FULL>(st, 2, ca),
+               a3 = a_val<FULL>(st, 3, ca);
   *reinterpret_cast<float4*>(da) = make_float4(a0.x, a0.y, a1.x, a1.y);
   *reinterpret_cast<float4*>(da + 2) = make_float4(a2.x, a2.y, a3.x, a3.y);
   const int nn = tid % 64, kb = 4 * (tid / 64);
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    const float2 v = b_val(p, st, e);
+    const float2 v = b_val<FULL>(st, e, cb);
     *reinterpret_cast<float4*>(&L.b[(kb + e) * kXS + 2 * nn]) = make_float4(v.x, -v.y, v.y, v.x);
   }
 }
@@ -257,16 +278,18 @@ struct LdsF64 {
   double2 b[kKC * kXS];
 };
 
-__device__ __forceinline__ void store_f64(const CGemm& p, const Stage<double2>& st, LdsF64& L, int tid) {
+template <bool FULL>
+__device__ __forceinline__ void store_f64(const CGemm& p, const Stage<double2>& st, LdsF64& L, int tid, uint32_t ca,
+                                          uint32_t cb) {
   int m, kq;
   a_slot(p, tid, m, kq);
   double2* da = &L.a[m * kAS + 4 * kq];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) da[e] = a_val(p, st, e);
+  for (int e = 0; e < 4; ++e) da[e] = a_val<FULL>(st, e, ca);
   const int nn = tid % 64, kb = 4 * (tid / 64);
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    const double2 v = b_val(p, st, e);
+    const double2 v = b_val<FULL>(st, e, cb);
     double2* db = &L.b[(kb + e) * kXS + 2 * nn];
     db[0] = make_double2(v.x, -v.y);
     db[1] = make_double2(v.y, v.x);
@@ -351,9 +374,9 @@ __device__ __forceinline__ void split_words(float2 v, uint32_t (&w)[NP]) {
 // A and B are loaded by the FP32 variant's walkers and split into bf16 pieces when the
 // step is written to LDS, with the invalid elements zeroed and the conjugation flags
 // applied.
-template <int NP>
-__device__ __forceinline__ void store_stage_b16(const CGemm& p, const Stage<float2>& st, LdsBf16<NP>& L,
-                                                 int tid) {
+template <int NP, bool FULL>
+__device__ __forceinline__ void store_stage_b16(const CGemm& p, const Stage<float2>& st, LdsBf16<NP>& L, int tid,
+                                                 uint32_t ca, uint32_t cb) {
   {
     int m, kq;
     a_slot(p, tid, m, kq);
@@ -361,7 +384,7 @@ __device__ __forceinline__ void store_stage_b16(const CGemm& p, const Stage<floa
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       uint32_t pc[NP];
-      split_words<NP>(a_val(p, st, e), pc);
+      split_words<NP>(a_val<FULL>(st, e, ca), pc);
 #pragma unroll
       for (int u = 0; u < NP; ++u) w[u][e] = pc[u];
     }
@@ -374,7 +397,7 @@ __device__ __forceinline__ void store_stage_b16(const CGemm& p, const Stage<floa
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     uint32_t pc[NP];
-    split_words<NP>(b_val(p, st, e), pc);
+    split_words<NP>(b_val<FULL>(st, e, cb), pc);
 #pragma unroll
     for (int u = 0; u < NP; ++u) w[u][e] = pc[u];
   }
@@ -537,14 +560,34 @@ struct VarOf<3> {
   static constexpr int waves = 2;
 };
 
-template <int VARIANT>
+template <int VARIANT, bool FULL>
 __device__ __forceinline__ void store_stage(const CGemm& p, const Stage<typename VarOf<VARIANT>::c2>& st,
-                                            typename VarOf<VARIANT>::lds& L, int tid) {
-  static_assert(VARIANT == 0 || VARIANT == 3, "the bf16 variants stage pre-split operands (run_tile_b16)");
+                                            typename VarOf<VARIANT>::lds& L, int tid, uint32_t ca, uint32_t cb) {
   if constexpr (VARIANT == 0)
-    store_f32(p, st, L, tid);
+    store_f32<FULL>(p, st, L, tid, ca, cb);
+  else if constexpr (VARIANT == 3)
+    store_f64<FULL>(p, st, L, tid, ca, cb);
   else
-    store_f64(p, st, L, tid);
+    store_stage_b16<VARIANT + 1, FULL>(p, st, L, tid, ca, cb);
+}
+
+// Loads one step (k0 = ns * 16) in the form its position in K allows; the same test
+// picks the matching store.
+template <bool AVEC, typename C2>
+__device__ __forceinline__ void load_step(const CGemm& p, bool full, int ns, Walk<C2>& w, Stage<C2>& st) {
+  if (full)
+    load_stage<AVEC, true>(p, ns * kKC, w, st);
+  else
+    load_stage<AVEC, false>(p, ns * kKC, w, st);
+}
+
+template <int VARIANT>
+__device__ __forceinline__ void store_step(const CGemm& p, bool full, const Stage<typename VarOf<VARIANT>::c2>& st,
+                                           typename VarOf<VARIANT>::lds& L, int tid, uint32_t ca, uint32_t cb) {
+  if (full)
+    store_stage<VARIANT, true>(p, st, L, tid, ca, cb);
+  else
+    store_stage<VARIANT, false>(p, st, L, tid, ca, cb);
 }
 
 template <int VARIANT, int NTE>
@@ -585,9 +628,10 @@ __device__ __forceinline__ void run_tile(const CGemm& p, const CTile& tl, const 
   Walk<C2> wk;
   walk_init(p, A, B, tl.m0, tid, wk);
   walk_block(p, tl.n0, tid, wk);
+  const uint32_t ca = conj_mask(p, kConjA), cb = conj_mask(p, kConjB);
   Stage<C2> st;
-  load_stage<AVEC>(p, 0, wk, st);
-  store_stage<VARIANT>(p, st, L, tid);
+  load_step<AVEC>(p, kKC <= p.K, 0, wk, st);
+  store_step<VARIANT>(p, kKC <= p.K, st, L, tid, ca, cb);
   __syncthreads();
   for (int n0 = tl.n0;;) {
     // K sweep of one column block; the epilogue stays outside this loop so that the
@@ -598,15 +642,15 @@ __device__ __forceinline__ void run_tile(const CGemm& p, const CTile& tl, const 
         ns = 0;
         nn0 += kBN;
       }
-      const bool more = nn0 < tl.n1;
+      const bool more = nn0 < tl.n1, full = (ns + 1) * kKC <= p.K;
       if (more) {
         if (ns == 0) walk_block(p, nn0, tid, wk);
-        load_stage<AVEC>(p, ns * kKC, wk, st);
+        load_step<AVEC>(p, full, ns, wk, st);
       }
       if constexpr (ACTIVE) mma_stage<VARIANT, NTE>(L, w, lane, acc);
       if (more) {
         __syncthreads();  // every wavefront is done reading the step
-        store_stage<VARIANT>(p, st, L, tid);
+        store_step<VARIANT>(p, full, st, L, tid, ca, cb);
         __syncthreads();
       }
     }
@@ -656,9 +700,10 @@ __device__ __forceinline__ void run_tile_b16(const CGemm& p, const CTile& tl, co
   Walk<float2> wk;
   walk_init(p, A, B, tl.m0, tid, wk);
   walk_block(p, tl.n0, tid, wk);
+  const uint32_t ca = conj_mask(p, kConjA), cb = conj_mask(p, kConjB);
   Stage<float2> st;
-  load_stage<AVEC>(p, 0, wk, st);
-  store_stage_b16<NP>(p, st, L, tid);
+  load_step<AVEC>(p, kKC <= p.K, 0, wk, st);
+  store_step<VARIANT>(p, kKC <= p.K, st, L, tid, ca, cb);
   __syncthreads();
   for (int n0 = tl.n0;;) {
     for (int s = 0; s < nsteps; ++s) {
@@ -667,15 +712,15 @@ __device__ __forceinline__ void run_tile_b16(const CGemm& p, const CTile& tl, co
         ns = 0;
         nn0 += kBN;
       }
-      const bool more = nn0 < tl.n1;
+      const bool more = nn0 < tl.n1, full = (ns + 1) * kKC <= p.K;
       if (more) {
         if (ns == 0) walk_block(p, nn0, tid, wk);
-        load_stage<AVEC>(p, ns * kKC, wk, st);
+        load_step<AVEC>(p, full, ns, wk, st);
       }
       if constexpr (ACTIVE) mma_bf16<NP, NTB>(L, w, lane, acc);
       if (more) {
         __syncthreads();  // every wavefront is done reading the step
-        store_stage_b16<NP>(p, st, L, tid);
+        store_step<VARIANT>(p, full, st, L, tid, ca, cb);
         __syncthreads();
       }
     }
