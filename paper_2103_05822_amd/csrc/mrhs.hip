@@ -533,17 +533,16 @@ __device__ __forceinline__ void epilogue(const CGemm& p, C2* Cp, int m0, int n0,
 
 // Per-variant types (LDS stage, complex element, accumulator) and the wavefronts per
 // SIMD the register allocation is held to.  More resident wavefronts hide more of the
-// operand-load latency.  FP32 and BF16x2 fit 4 (up from 3) and BF16x3 fits 3 (up from
-// 2), with the accumulators in VGPRs: the 64-RHS pass of the 30-lambda sphere takes
-// 5.5%, 5.5% and 9.5% less time.  (With the narrow-product instantiations below,
-// BF16x2 spills 7 registers at 4, one reload per K step, which gives back 2%.)  FP64
-// would spill at 3 and keeps 2; its new register allocation still saves 4.6%.
+// operand-load latency: FP32, BF16x2 and BF16x3 run 4, FP64 3 (its 52 KB of LDS allows
+// no more).  BF16x3 and FP64 then spill 10 and 15 registers, all outside the K loop
+// (where a column block starts or ends); on the 64-RHS pass of the 30-lambda sphere
+// they take 6% and 5% less time than at 3 and 2.  BF16x2 at 5 would spill 57.
 template <int VARIANT>
 struct VarOf {
   using lds = LdsBf16<VARIANT + 1>;
   using c2 = float2;
   using acc = floatx4;
-  static constexpr int waves = VARIANT == 1 ? 4 : 3;
+  static constexpr int waves = 4;
 };
 template <>
 struct VarOf<0> {
@@ -557,7 +556,7 @@ struct VarOf<3> {
   using lds = LdsF64;
   using c2 = double2;
   using acc = doublex4;
-  static constexpr int waves = 2;
+  static constexpr int waves = 3;
 };
 
 template <int VARIANT, bool FULL>
