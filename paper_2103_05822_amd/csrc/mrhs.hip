@@ -536,7 +536,8 @@ __device__ __forceinline__ void epilogue(const CGemm& p, C2* Cp, int m0, int n0,
 // operand-load latency: FP32, BF16x2 and BF16x3 run 4, FP64 3 (its 52 KB of LDS allows
 // no more).  BF16x3 and FP64 then spill 10 and 15 registers, all outside the K loop
 // (where a column block starts or ends); on the 64-RHS pass of the 30-lambda sphere
-// they take 6% and 5% less time than at 3 and 2.  BF16x2 at 5 would spill 57.
+// they take 6% and 5% less time than at 3 and 2.  FP32 at 5 spills 54 registers, four
+// of them reloaded in every K step, and ran 9% slower; BF16x2 at 5 would spill 57.
 template <int VARIANT>
 struct VarOf {
   using lds = LdsBf16<VARIANT + 1>;
