@@ -1116,13 +1116,31 @@ extern "C" fmm_status fmm_dense_create(const fmm_layout* layout, fmm_dense_t* ou
   const int G = d->layout.n_groups;
   std::vector<DenseGroup> grp(G);
   for (int g = 0; g < G; ++g) grp[g] = DenseGroup{d->layout.offsets[g], d->layout.nb(g), 0};
+  // Row blocks of the multi-RHS disaggregation.  Workgroups go to the eight XCDs
+  // round-robin by index; the list gives XCD x the x-th eighth of the blocks in group
+  // order (position 8 j + x holds block x * per + j), so that the few groups an XCD
+  // works on at a time keep their G in its L2.
+  std::vector<DenseBlock> nat;
+  for (int g = 0; g < G; ++g)
+    for (int i = 0; i < d->layout.nb(g); i += kDenseBlockRows)
+      nat.push_back(DenseBlock{d->layout.offsets[g] + i, std::min(kDenseBlockRows, d->layout.nb(g) - i), g});
+  std::vector<DenseBlock> blk;
+  blk.reserve(nat.size());
+  const size_t per = (nat.size() + 7) / 8;
+  for (size_t j = 0; j < per; ++j)
+    for (size_t x = 0; x < 8; ++x)
+      if (x * per + j < nat.size()) blk.push_back(nat[x * per + j]);
+  d->n_blocks = (int)blk.size();
   hipError_t e = hipGetDevice(&d->device);
   if (e == hipSuccess && G > 0) e = hipMalloc(&d->d_groups, sizeof(DenseGroup) * G);
   if (e == hipSuccess) e = hipMalloc(&d->d_offsets, sizeof(int64_t) * (G + 1));
+  if (e == hipSuccess && !blk.empty()) e = hipMalloc(&d->d_blocks, sizeof(DenseBlock) * blk.size());
   if (e == hipSuccess && G > 0)
     e = hipMemcpy(d->d_groups, grp.data(), sizeof(DenseGroup) * G, hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(d->d_offsets, d->layout.offsets.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !blk.empty())
+    e = hipMemcpy(d->d_blocks, blk.data(), sizeof(DenseBlock) * blk.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     fmm_dense_destroy(d);
     return fail(FMM_ERR_DEVICE, "dense plan upload: %s", hipGetErrorString(e));
@@ -1173,11 +1191,11 @@ extern "C" fmm_status fmm_dense_disaggregate(fmm_dense_t d, fmm_prec prec, const
   const int ncols = 2 * d->layout.ndir();
   hipStream_t hs = static_cast<hipStream_t>(stream);
   if (prec == FMM_C128)
-    TFMM_HIP(launch_dense_disagg<double>(farfield, d->d_offsets, d->layout.n_groups, d->layout.n_basis(), ncols,
-                                         nrhs, G, V, hs));
+    TFMM_HIP(launch_dense_disagg<double>(farfield, d->d_offsets, d->layout.n_groups, d->layout.n_basis(),
+                                         d->d_blocks, d->n_blocks, ncols, nrhs, G, V, hs));
   else
-    TFMM_HIP(launch_dense_disagg<float>(farfield, d->d_offsets, d->layout.n_groups, d->layout.n_basis(), ncols,
-                                        nrhs, G, V, hs));
+    TFMM_HIP(launch_dense_disagg<float>(farfield, d->d_offsets, d->layout.n_groups, d->layout.n_basis(),
+                                        d->d_blocks, d->n_blocks, ncols, nrhs, G, V, hs));
   return FMM_OK;
 }
 
@@ -1185,5 +1203,6 @@ extern "C" void fmm_dense_destroy(fmm_dense_t d) {
   if (!d) return;
   if (d->d_groups) (void)hipFree(d->d_groups);
   if (d->d_offsets) (void)hipFree(d->d_offsets);
+  if (d->d_blocks) (void)hipFree(d->d_blocks);
   delete d;
 }

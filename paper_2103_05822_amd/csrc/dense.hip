@@ -5,7 +5,9 @@
 //                                                         rows walked in order
 //   disaggregation V[n] = sum_col conj(A[n][col]) G[g][col]   one wavefront per row,
 //                                                         lane-strided, butterfly sum
-// with up to 8 right-hand sides per read of A.
+// with up to 8 right-hand sides per read of A.  With 2 or more right-hand sides the
+// disaggregation works on blocks of rows of one group instead (see
+// dense_disagg_block_kernel).
 #include <hip/hip_runtime.h>
 #include "cplx.hpp"
 #include "kernels.hpp"
@@ -144,6 +146,101 @@ __global__ __launch_bounds__(kThreads) void dense_disagg_kernel(const typename T
   }
 }
 
+// Disaggregation with RB = 2, 4 or 8 right-hand sides per read of A, over the row
+// blocks of the plan (up to 16 rows of one group).  Read per row, the group's G would
+// cost RB times the row's bytes, and a lane's RB values of one column sit 16 RB bytes
+// apart from the next lane's, so each load instruction would touch 64 cache lines.
+// Instead the workgroup walks the columns in chunks of 64: its 256 threads load the
+// chunk's G[g][c][r0 .. r0 + RB) with coalesced loads into LDS (double buffered, one
+// barrier per chunk), and wavefront w, owning rows 4w .. 4w + 3 of the block, reads a
+// lane's column from there for its four rows while the rows of A stream from HBM
+// (prefetched one chunk ahead).  The plan orders the blocks so that each XCD works on
+// a few groups at a time, whose G then stays in its L2.
+template <typename T, int RB>
+__global__ __launch_bounds__(kThreads) void dense_disagg_block_kernel(const typename Tr<T>::c* __restrict__ A,
+                                                                      const DenseBlock* __restrict__ blocks,
+                                                                      int ncols, int nrhs,
+                                                                      const typename Tr<T>::c* __restrict__ Gin,
+                                                                      typename Tr<T>::c* __restrict__ V) {
+  using C = typename Tr<T>::c;
+  constexpr int RW = 4;                               // rows per wavefront
+  constexpr int CW = 64;                              // columns per chunk
+  constexpr int GS = RB + 1;                          // LDS row stride (complex): spreads the banks
+  constexpr int GL = (CW * RB + kThreads - 1) / kThreads;  // G elements per thread and chunk
+  __shared__ C gsh[2][CW * GS];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const DenseBlock b = blocks[blockIdx.x];
+  const int i0 = RW * w;
+  const int nrow = max(0, min(RW, b.rows - i0));  // uniform per wavefront; 0: loads and barriers only
+  const int r0 = blockIdx.y * RB;
+  const int nr = min(RB, nrhs - r0);
+  const C* rows = A + (b.row0 + min(i0, b.rows - 1)) * ncols;
+  const C* gv = Gin + (int64_t)b.group * ncols * nrhs + r0;
+  const int nchunks = (ncols + CW - 1) / CW;
+
+  C greg[GL];
+  auto load_g = [&](int chunk) {
+#pragma unroll
+    for (int k = 0; k < GL; ++k) {
+      const int e = tid + kThreads * k, cc = e / RB, r = e % RB, c = chunk * CW + cc;
+      greg[k] = e < CW * RB && c < ncols && r < nr ? gv[(int64_t)c * nrhs + r] : czero<C>();
+    }
+  };
+  auto store_g = [&](int buf) {
+#pragma unroll
+    for (int k = 0; k < GL; ++k) {
+      const int e = tid + kThreads * k;
+      if (e < CW * RB) gsh[buf][(e / RB) * GS + e % RB] = greg[k];
+    }
+  };
+  auto load_a = [&](int chunk, C (&a)[RW]) {
+    const int c = chunk * CW + lane;
+#pragma unroll
+    for (int i = 0; i < RW; ++i) a[i] = i < nrow && c < ncols ? rows[(int64_t)i * ncols + c] : czero<C>();
+  };
+
+  C acc[RW][RB];
+#pragma unroll
+  for (int i = 0; i < RW; ++i)
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[i][r] = czero<C>();
+  C a[RW], an[RW];
+  load_g(0);
+  load_a(0, a);
+  store_g(0);
+  __syncthreads();
+  for (int chunk = 0; chunk < nchunks; ++chunk) {
+    const bool more = chunk + 1 < nchunks;
+    if (more) {
+      load_a(chunk + 1, an);
+      load_g(chunk + 1);
+    }
+    const C* gc = &gsh[chunk & 1][lane * GS];
+    C gt[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) gt[r] = gc[r];
+#pragma unroll
+    for (int i = 0; i < RW; ++i)
+#pragma unroll
+      for (int r = 0; r < RB; ++r) cfma_conj(acc[i][r], a[i], gt[r]);
+    if (more) {
+      store_g((chunk + 1) & 1);  // that buffer was last read before the previous barrier
+#pragma unroll
+      for (int i = 0; i < RW; ++i) a[i] = an[i];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < RW; ++i) {
+    if (i >= nrow) break;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const C sum = wave_sum(acc[i][r]);
+      if (lane == 0 && r < nr) V[(b.row0 + i0 + i) * nrhs + r0 + r] = sum;
+    }
+  }
+}
+
 // RB for a call: the smallest of 1, 2, 4, 8 covering nrhs (8 beyond).
 int rhs_block(int nrhs) { return nrhs >= 8 ? 8 : (nrhs > 2 ? 4 : nrhs); }
 
@@ -188,15 +285,23 @@ hipError_t launch_dense_agg(const void* A, const DenseGroup* groups, int n_group
 }
 
 template <typename T>
-hipError_t launch_dense_disagg(const void* A, const int64_t* offsets, int n_groups, int64_t n_rows, int ncols,
-                               int nrhs, const void* G, void* V, hipStream_t s) {
+hipError_t launch_dense_disagg(const void* A, const int64_t* offsets, int n_groups, int64_t n_rows,
+                               const DenseBlock* row_blocks, int n_blocks, int ncols, int nrhs, const void* G,
+                               void* V, hipStream_t s) {
   using C = typename Tr<T>::c;
   if (n_rows == 0) return hipSuccess;
-  const int64_t blocks = (n_rows + kThreads / 64 - 1) / (kThreads / 64);
   const int rb = rhs_block(nrhs);
-  dim3 grid((unsigned)blocks, (nrhs + rb - 1) / rb);
-  TFMM_RB_SWITCH(rb, hipLaunchKernelGGL((dense_disagg_kernel<T, RB>), grid, dim3(kThreads), 0, s,
-                                        static_cast<const C*>(A), offsets, n_groups, n_rows, ncols, nrhs,
+  if (rb == 1) {
+    const int64_t blocks = (n_rows + kThreads / 64 - 1) / (kThreads / 64);
+    hipLaunchKernelGGL((dense_disagg_kernel<T, 1>), dim3((unsigned)blocks), dim3(kThreads), 0, s,
+                       static_cast<const C*>(A), offsets, n_groups, n_rows, ncols, nrhs, static_cast<const C*>(G),
+                       static_cast<C*>(V));
+    return hipGetLastError();
+  }
+  if (n_blocks <= 0 || row_blocks == nullptr) return hipErrorInvalidValue;
+  dim3 grid((unsigned)n_blocks, (nrhs + rb - 1) / rb);
+  TFMM_RB_SWITCH(rb, hipLaunchKernelGGL((dense_disagg_block_kernel<T, RB>), grid, dim3(kThreads), 0, s,
+                                        static_cast<const C*>(A), row_blocks, ncols, nrhs,
                                         static_cast<const C*>(G), static_cast<C*>(V)))
   return hipGetLastError();
 }
@@ -205,9 +310,9 @@ template hipError_t launch_dense_agg<float>(const void*, const DenseGroup*, int,
                                             hipStream_t);
 template hipError_t launch_dense_agg<double>(const void*, const DenseGroup*, int, int, int, const void*, void*,
                                              hipStream_t);
-template hipError_t launch_dense_disagg<float>(const void*, const int64_t*, int, int64_t, int, int, const void*,
-                                               void*, hipStream_t);
-template hipError_t launch_dense_disagg<double>(const void*, const int64_t*, int, int64_t, int, int, const void*,
-                                                void*, hipStream_t);
+template hipError_t launch_dense_disagg<float>(const void*, const int64_t*, int, int64_t, const DenseBlock*, int,
+                                               int, int, const void*, void*, hipStream_t);
+template hipError_t launch_dense_disagg<double>(const void*, const int64_t*, int, int64_t, const DenseBlock*, int,
+                                                int, int, const void*, void*, hipStream_t);
 
 }  // namespace tuckfmm

@@ -126,4 +126,13 @@ struct DenseGroup {
   int32_t pad;
 };
 
+// Dense plan: up to kDenseBlockRows consecutive rows of one group (the work unit of
+// the multi-RHS disaggregation).
+constexpr int kDenseBlockRows = 16;
+struct DenseBlock {
+  int64_t row0;
+  int32_t rows;
+  int32_t group;
+};
+
 }  // namespace tuckfmm

@@ -152,6 +152,8 @@ struct fmm_dense_s {
   int device = -1;
   tuckfmm::DenseGroup* d_groups = nullptr;  // library-owned device table
   int64_t* d_offsets = nullptr;
+  tuckfmm::DenseBlock* d_blocks = nullptr;  // row blocks, in XCD order (see fmm_dense_create)
+  int n_blocks = 0;
 };
 
 struct fmm_geometry_s {

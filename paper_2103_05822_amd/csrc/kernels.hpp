@@ -38,8 +38,9 @@ template <typename T>
 hipError_t launch_dense_agg(const void* A, const DenseGroup* groups, int n_groups, int ncols, int nrhs,
                             const void* x, void* F, hipStream_t s);
 template <typename T>
-hipError_t launch_dense_disagg(const void* A, const int64_t* offsets, int n_groups, int64_t n_rows, int ncols,
-                               int nrhs, const void* G, void* V, hipStream_t s);
+hipError_t launch_dense_disagg(const void* A, const int64_t* offsets, int n_groups, int64_t n_rows,
+                               const DenseBlock* blocks, int n_blocks, int ncols, int nrhs, const void* G, void* V,
+                               hipStream_t s);
 
 // Far-field fill, eq. (4): rowdata [rows][kRowDoubles], dirs [ndir][9].
 constexpr int kRowDoubles = 40;  // 6 points x (rel xyz, rho xyz) + scale + box centre
