@@ -89,19 +89,18 @@ __global__ __launch_bounds__(kThreads) void dense_agg_kernel(const typename Tr<T
     }
 }
 
-template <typename T, int RB>
+// Disaggregation with one right-hand side: a wavefront per row, four columns in
+// flight per lane, butterfly sum.
+template <typename T>
 __global__ __launch_bounds__(kThreads) void dense_disagg_kernel(const typename Tr<T>::c* __restrict__ A,
                                                                 const int64_t* __restrict__ offsets,
                                                                 int n_groups, int64_t n_rows, int ncols,
-                                                                int nrhs,
                                                                 const typename Tr<T>::c* __restrict__ Gin,
                                                                 typename Tr<T>::c* __restrict__ V) {
   using C = typename Tr<T>::c;
-  constexpr int U = RB == 1 ? 4 : (RB <= 4 ? 2 : 1);  // columns in flight per lane
+  constexpr int U = 4;  // columns in flight per lane
   const int lane = threadIdx.x & 63;
   const int64_t n = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
-  const int r0 = blockIdx.y * RB;
-  const int nr = min(RB, nrhs - r0);
   if (n >= n_rows) return;  // no barrier below
   // group of row n: largest g with offsets[g] <= n
   int lo = 0, hi = n_groups;
@@ -110,40 +109,27 @@ __global__ __launch_bounds__(kThreads) void dense_disagg_kernel(const typename T
     if (offsets[mid] <= n) lo = mid; else hi = mid;
   }
   const C* row = A + n * ncols;
-  const C* gv = Gin + (int64_t)lo * ncols * nrhs + r0;
-  C acc[U][RB];
+  const C* gv = Gin + (int64_t)lo * ncols;
+  C acc[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u)
-#pragma unroll
-    for (int r = 0; r < RB; ++r) acc[u][r] = czero<C>();
+  for (int u = 0; u < U; ++u) acc[u] = czero<C>();
   int c = lane;
   for (; c + 64 * (U - 1) < ncols; c += 64 * U) {
     C a[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) a[u] = row[c + 64 * u];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int r = 0; r < RB; ++r)
-        if (r < nr) cfma_conj(acc[u][r], a[u], gv[(int64_t)(c + 64 * u) * nrhs + r]);
+    for (int u = 0; u < U; ++u) cfma_conj(acc[u], a[u], gv[c + 64 * u]);
   }
-  for (; c < ncols; c += 64) {
-    const C a = row[c];
+  for (; c < ncols; c += 64) cfma_conj(acc[0], row[c], gv[c]);
+  C s = acc[0];
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
-      if (r < nr) cfma_conj(acc[0][r], a, gv[(int64_t)c * nrhs + r]);
+  for (int u = 1; u < U; ++u) {
+    s.x += acc[u].x;
+    s.y += acc[u].y;
   }
-#pragma unroll
-  for (int r = 0; r < RB; ++r) {
-    C s = acc[0][r];
-#pragma unroll
-    for (int u = 1; u < U; ++u) {
-      s.x += acc[u][r].x;
-      s.y += acc[u][r].y;
-    }
-    s = wave_sum(s);
-    if (lane == 0 && r < nr) V[n * nrhs + r0 + r] = s;
-  }
+  s = wave_sum(s);
+  if (lane == 0) V[n] = s;
 }
 
 // Disaggregation with RB = 2, 4 or 8 right-hand sides per read of A, over the row
@@ -293,8 +279,8 @@ hipError_t launch_dense_disagg(const void* A, const int64_t* offsets, int n_grou
   const int rb = rhs_block(nrhs);
   if (rb == 1) {
     const int64_t blocks = (n_rows + kThreads / 64 - 1) / (kThreads / 64);
-    hipLaunchKernelGGL((dense_disagg_kernel<T, 1>), dim3((unsigned)blocks), dim3(kThreads), 0, s,
-                       static_cast<const C*>(A), offsets, n_groups, n_rows, ncols, nrhs, static_cast<const C*>(G),
+    hipLaunchKernelGGL((dense_disagg_kernel<T>), dim3((unsigned)blocks), dim3(kThreads), 0, s,
+                       static_cast<const C*>(A), offsets, n_groups, n_rows, ncols, static_cast<const C*>(G),
                        static_cast<C*>(V));
     return hipGetLastError();
   }
