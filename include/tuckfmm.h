@@ -389,8 +389,9 @@ void fmm_tucker_destroy(fmm_tucker_t h);
 
 /* ------------------------------------------------------------------- dense */
 
-/* Plan of the plain method for a layout: uploads the group table to the current
- * device. */
+/* Plan of the plain method for a layout: uploads the group table and the row-block
+ * table of the multi-RHS disaggregation to the current device.  Both stages read each
+ * far-field element once per 8 right-hand sides. */
 fmm_status fmm_dense_create(const fmm_layout* layout, fmm_dense_t* out);
 
 /* Dense aggregation, eq. (3) / Fig. 2(a): F^alpha_g = A^alpha_g x_g.
