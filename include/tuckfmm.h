@@ -367,7 +367,7 @@ typedef struct {
 
 /* Autotuner: times fmm_tucker_pass with these buffers under each candidate
  * configuration for (prec, nrhs) (1 warm-up + 3 timed passes each, HIP events on the
- * stream): the four streaming workgroup sizes, and on the matrix cores 8, 16 and 32 K
+ * stream): the four streaming workgroup sizes, and on the matrix cores 8, 16, 32 and 64 K
  * steps per tile, up to three chunk sizes and the three angular orders.  Keeps the
  * fastest for later calls with this nrhs and reports it in *out (may be NULL).  With
  * the environment variable TUCKFMM_TUNE_CACHE naming a file, a result stored there

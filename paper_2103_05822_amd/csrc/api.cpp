@@ -993,7 +993,7 @@ extern "C" fmm_status fmm_tucker_tune(fmm_tucker_t h, fmm_prec prec, int32_t nrh
     if (nrhs > 2 * kMrhsDefaultChunk) chunks.push_back(2 * kMrhsDefaultChunk);
     if (nrhs >= kMrhsDefaultChunk) chunks.push_back(kMrhsDefaultChunk / 2);
     for (int od : {0, 1, 2})
-      for (int ts : {8, 16, 32})
+      for (int ts : {8, 16, 32, 64})
         for (int rc : chunks) cand.push_back(TuneChoice{nrhs, 1, ts, rc, 0, od});
   }
   if (cand.empty()) return fail(FMM_ERR_UNSUPPORTED, "no kernels for precision %d with nrhs %d", (int)prec, nrhs);
