@@ -55,6 +55,7 @@ def parse():
                    help="budget of the oracle CPU timing (0: no CPU baseline)")
     p.add_argument("--no-oracle", action="store_true", help="skip accuracy sampling and the CPU baseline")
     p.add_argument("--no-dense", action="store_true", help="Tucker stages only (profiling runs)")
+    p.add_argument("--no-dense-rhs", action="store_true", help="skip the dense pass with 8 right-hand sides")
     p.add_argument("--nrhs", type=int, default=None,
                    help="right-hand sides of the multi-RHS section (default: the workload's, else 64; 0: skip)")
     p.add_argument("--mrhs-precs", default="c128,c64,bf16x2,bf16x3",
@@ -379,6 +380,11 @@ def main():
         result["box_grid"] = box_grid_pass(T, torch, geom, h, lay, w, arenas[T.FMM_C64], x32, g32, F32, V32,
                                            tucker_ms, per_stage_bytes["tucker_pass_f32"])
 
+    # the plain method with 8 right-hand sides: one read of A serves all 8
+    if not args.no_dense and not args.no_dense_rhs:
+        result["dense_8rhs"] = dense_rhs_block(T, torch, synth, dplan, dense, x64, g64, F64, V64,
+                                               result["dense_pass_ms"], b_d64)
+
     # ------------------------- the other stated configurations of the same sphere
     extra = {}
     if not args.no_dense and not args.no_extra:
@@ -389,9 +395,6 @@ def main():
         # tolerance 1e-4 (Table III's first Tucker row), FP32 pass
         result["gamma_1e-4"], extra["gamma_1e-4_f32"] = gamma_pass(
             args, T, torch, lay, dense, w, 1e-4, x32, g32, sample, result.get("dense_pass_ms"))
-        # the plain method with 8 right-hand sides: one read of A serves all 8
-        result["dense_8rhs"] = dense_rhs_block(T, torch, synth, dplan, dense, x64, g64, F64, V64,
-                                               result["dense_pass_ms"], b_d64)
     if args.workload == "sphere30" and not args.no_extra and not args.no_dense:
         dense = None
         torch.cuda.empty_cache()
