@@ -218,11 +218,14 @@ def test_tucker_deterministic_and_graph_replays():
 # ------------------------------------------------------------------------------- dense
 
 @pytest.mark.parametrize("prec", [T.FMM_C128, T.FMM_C64], ids=["c128", "c64"])
-@pytest.mark.parametrize("nrhs", [1, 2, 3, 8, 66])
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 5, 8, 9, 66])
 def test_dense_ragged_layout(prec, nrhs):
     """Dense products against the oracle: right-hand sides in blocks of 1, 2, 4 and 8
-    per read of A, ragged blocks (3 = one block of 4 with 3 valid, 66 = 8 blocks of 8
-    and one with 2 valid)."""
+    per read of A, ragged blocks (3 = one block of 4 with 3 valid, 5 = one block of 8
+    with 5 valid, 9 = a block of 8 and one with 1 valid, 66 = 8 blocks of 8 and one
+    with 2 valid).  The disaggregation with 2 or more runs on row blocks of up to 16
+    rows of one group: the groups of 1-3 rows leave wavefronts without rows, 65 and
+    257 leave a one-row block."""
     lay = ragged_layout(7, 13)
     banner("dense ragged prec=%d nrhs=%d" % (prec, nrhs))
     rng = synth.rng(9)
